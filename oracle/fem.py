@@ -1,0 +1,128 @@
+"""P1 finite-element assembly on simplex meshes (oracle side).
+
+Section 2: the space V_h of continuous piecewise-linear functions vanishing on
+the boundary (eq. "linear_fe_space"), the bilinear form a(u,v) = (grad u, grad v)
+(the operator matrix A is the identity in every example of Section 4), and the
+discrete problem eq. "FEM_form".
+
+Quadrature reading: the L2 pairings (f(x,u), v) and (g, v) are taken with the
+vertex (nodal) rule, (w, phi_j) ~ m_j w(x_j) with the lumped mass
+m_j = sum_{T contains x_j} |T|/(d+1).  The paper writes exact integrals and
+names no rule; the vertex rule keeps the P1 rates and positive weights, and is
+used identically on every space, including the augmented space of
+Algorithm 3.1.
+
+Everything is assembled element by element from the vertex coordinates; no
+stencil formula is used, so the stencil closed forms are independent checks.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+from .mesh import Mesh
+
+
+def simplex_geometry(X: np.ndarray):
+    """Barycentric-coordinate gradients and volumes of simplices.
+
+    X: (E, d+1, d) vertex coordinates.  Returns (grads (E, d+1, d), vol (E,),
+    C (E, d+1, d+1)) where lambda_i(x) = C[:,0,i] + x . C[:,1:,i].
+    """
+    E, dp1, d = X.shape
+    M = np.concatenate([np.ones((E, dp1, 1)), X], axis=2)  # rows [1, x_v]
+    C = np.linalg.inv(M)                                   # M @ C = I
+    vol = np.abs(np.linalg.det(M)) / math.factorial(d)
+    grads = np.transpose(C[:, 1:, :], (0, 2, 1))           # (E, d+1, d)
+    return grads, vol, C
+
+
+def assemble_full(mesh: Mesh):
+    """Full stiffness matrix (all nodes, CSR) and lumped mass vector.
+
+    K_T[i,j] = |T| grad(lambda_i) . grad(lambda_j)  (local P1 stiffness).
+    """
+    T = mesh.simplices
+    X = mesh.coords[T]
+    grads, vol, _ = simplex_geometry(X)
+    d = mesh.dim
+    Kloc = vol[:, None, None] * np.einsum("eia,eja->eij", grads, grads)
+    rows = np.repeat(T, d + 1, axis=1).reshape(-1)
+    cols = np.tile(T, (1, d + 1)).reshape(-1)
+    N = mesh.coords.shape[0]
+    K = sp.csr_matrix((Kloc.reshape(-1), (rows, cols)), shape=(N, N))
+    K.sum_duplicates()
+    mass = np.zeros(N)
+    np.add.at(mass, T.reshape(-1), np.repeat(vol / (d + 1), d + 1))
+    return K, mass
+
+
+def assemble_interior(mesh: Mesh):
+    """Stiffness A (interior x interior, CSR) and lumped mass m on interior nodes.
+
+    Dirichlet nodes are eliminated (u = 0 on the boundary, Section 2).
+    """
+    K, mass = assemble_full(mesh)
+    I = mesh.interior
+    A = K[I][:, I].tocsr()
+    A.sort_indices()
+    return A, mass[I]
+
+
+def locate_in_coarse(coarse: Mesh, points: np.ndarray, tol: float = 1e-12):
+    """Point location: for each point, a coarse simplex containing it and the
+    point's barycentric coordinates in that simplex.
+
+    The candidate simplices are those of the coarse cell floor(x n_c) (clamped),
+    found through the cell's grid index; the containment test itself uses the
+    generic barycentric coordinates of each candidate.
+    """
+    d, nc = coarse.dim, coarse.n
+    cell = np.clip(np.floor(points * nc + 1e-9).astype(np.int64), 0, nc - 1)
+    # map cell -> its simplices: simplices are stored as d! blocks of nc^d cells,
+    # block p lists cells in 'ij' meshgrid order of (axis0, axis1, ...).
+    ncell = nc ** d
+    lin = np.zeros(points.shape[0], dtype=np.int64)
+    for a in range(d):
+        lin = lin * nc + cell[:, a]
+    nperm = math.factorial(d)
+    found_simplex = np.full(points.shape[0], -1, dtype=np.int64)
+    found_bary = np.zeros((points.shape[0], d + 1))
+    for p in range(nperm):
+        sid = p * ncell + lin
+        X = coarse.coords[coarse.simplices[sid]]
+        _, _, C = simplex_geometry(X)
+        bary = C[:, 0, :] + np.einsum("ea,eai->ei", points, C[:, 1:, :])
+        ok = np.all(bary >= -tol, axis=1) & (found_simplex < 0)
+        found_simplex[ok] = sid[ok]
+        found_bary[ok] = bary[ok]
+    if np.any(found_simplex < 0):
+        raise RuntimeError("point location failed")
+    return found_simplex, found_bary
+
+
+def interpolation_matrix(coarse: Mesh, fine_points: np.ndarray) -> sp.csr_matrix:
+    """Matrix evaluating coarse interior-node P1 functions at the given points.
+
+    Entry (j, c) = phi_c(x_j): the natural inclusion V_coarse -> V_fine used by
+    the nested spaces (eq. "FEM_Space_Series").  Columns are coarse interior
+    nodes in ascending id order.
+    """
+    sid, bary = locate_in_coarse(coarse, fine_points)
+    verts = coarse.simplices[sid]                       # (Nf, d+1) coarse node ids
+    col_of = -np.ones(coarse.coords.shape[0], dtype=np.int64)
+    col_of[coarse.interior] = np.arange(coarse.interior.size)
+    cols = col_of[verts]
+    rows = np.repeat(np.arange(fine_points.shape[0]), coarse.dim + 1).reshape(cols.shape)
+    keep = (cols >= 0) & (np.abs(bary) > 0)
+    P = sp.csr_matrix((bary[keep], (rows[keep], cols[keep])),
+                      shape=(fine_points.shape[0], coarse.interior.size))
+    P.sum_duplicates()
+    return P
+
+
+def prolongation(coarse: Mesh, fine: Mesh) -> sp.csr_matrix:
+    """P_k: V_{h_{k-1}} -> V_{h_k} on interior nodes (natural inclusion)."""
+    return interpolation_matrix(coarse, fine.coords[fine.interior])
