@@ -1,0 +1,210 @@
+/*
+ * fmg.h -- C ABI of the MI355X full-multigrid solver for semilinear elliptic
+ * problems (Xie & Xu, "A Full Multigrid Method for Semilinear Elliptic
+ * Equation").
+ *
+ * Problem (Section 2, eqs. "semilinear equation", "weak_form", "FEM_form"):
+ *     find u_h in V_h with  a(u_h, v) + (f(u_h), v) = (g, v)  for all v in V_h,
+ *     a(u, v) = (grad u, grad v),  Omega = (0,1)^dim,  u = 0 on the boundary,
+ * V_h = continuous P1 functions (eq. "linear_fe_space") on a mesh of the unit
+ * square (right triangles, diagonal from (0,0) to (1,1)) or the unit cube
+ * (Kuhn split: six tetrahedra per cube sharing the main diagonal), obtained by
+ * `refinements` uniform refinements (beta = 2, eq. "mesh_size_recur") of a
+ * coarse grid of `coarse_cells`^dim cells.  The coarse grid is the space V_H
+ * of the augmented problems and the first level of Algorithm 3.2.
+ * The L2 pairings use the vertex (nodal) quadrature rule on every space.
+ *
+ * Method (Section 3): Algorithm 3.2 (full multigrid scheme) built on
+ * Algorithm 3.1 (one correction step): m V-cycles on the linearised problem
+ * (eq. "linearized") from the current iterate, then a small Newton solve on
+ * V_H + span{u~} (eq. "coarse problem") whose coefficients are fine-grid
+ * quadratures computed on the device.
+ *
+ * Memory: the caller owns every device buffer (workspace, load, solution,
+ * report) and the stream; the library never frees caller memory and makes
+ * no device allocation of its own except the hipGraph it may instantiate.
+ * All device arrays are float64 nodal arrays of (n+1)^dim entries, x varying
+ * fastest, n = coarse_cells * 2^refinements.
+ *
+ * Errors: argument and size errors are returned synchronously with nothing
+ * enqueued.  Numerical outcomes (Newton cap reached, non-finite values) are
+ * written by the device into the report.  Calls are stream-ordered and
+ * asynchronous unless stated otherwise.  Distinct hierarchies may be used
+ * from different threads; one hierarchy must not be used concurrently.
+ */
+#ifndef FMG_H
+#define FMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMG_MAX_LEVELS 16
+
+typedef struct fmg_hierarchy fmg_hierarchy;   /* opaque */
+
+enum fmg_status {
+    FMG_OK = 0,
+    FMG_E_INVALID = 1,        /* null pointer, bad option value            */
+    FMG_E_UNSUPPORTED = 2,    /* dim not 2/3, depth out of range, ...      */
+    FMG_E_WORKSPACE = 3,      /* workspace too small or misaligned         */
+    FMG_E_HIP = 4,            /* a HIP runtime call failed                 */
+    FMG_E_NOT_CONVERGED = 5,  /* Newton cap hit (report) / converged mode  */
+    FMG_E_NONFINITE = 6       /* NaN or Inf in the solution (report)       */
+};
+
+/* Nonlinearity catalogue f(u); every entry is nondecreasing (Assumption A). */
+enum fmg_nonlinearity {
+    FMG_F_ZERO = 0,           /* f = 0                                      */
+    FMG_F_LINEAR = 1,         /* f = c u, c = param >= 0                    */
+    FMG_F_CUBIC = 2,          /* f = u^3 (Example 1)                        */
+    FMG_F_U_PLUS_SIN = 3,     /* f = u + sin u                              */
+    FMG_F_ABS_U_U = 4,        /* f = |u| u                                  */
+    FMG_F_SIGNED_POW = 5,     /* f = sign(u)|u|^q, q = param >= 1 (Ex. 3)   */
+    FMG_F_NEG_EXP = 6         /* f = -exp(-u) (Example 2)                   */
+};
+
+enum fmg_precision { FMG_FP64 = 0, FMG_MIXED = 1 };
+enum fmg_smoother { FMG_SMOOTHER_DEFAULT = 0, FMG_JACOBI = 1, FMG_CHEBYSHEV = 2 };
+enum fmg_mode { FMG_PAPER = 0, FMG_CONVERGED = 1 };
+
+typedef struct {
+    int dim;            /* 2 or 3                                           */
+    int coarse_cells;   /* cells per side of the coarse grid, >= 2          */
+    int refinements;    /* number of uniform refinements, 1..12 (2D), 1..8 (3D) */
+} fmg_mesh_desc;
+
+typedef struct {
+    int precision;      /* FMG_FP64, or FMG_MIXED: V-cycles in float32 inside
+                           float64 residual/update refinement                */
+    int m_vcycles;      /* m of Algorithm 3.1 (Section 4: m = 2)             */
+    int p_steps;        /* p of Algorithm 3.2 (Section 4: p = 1)             */
+    int nu_pre;         /* pre-smoothing sweeps per level                    */
+    int nu_post;        /* post-smoothing sweeps per level                   */
+    int smoother;       /* FMG_JACOBI (weight omega every sweep) or
+                           FMG_CHEBYSHEV (Chebyshev weights on [cheb_lo,
+                           cheb_hi] for D^{-1}A, reversed after the coarse
+                           correction); DEFAULT = Jacobi 2D, Chebyshev 3D    */
+    double omega;       /* Jacobi weight; 0 = 4/5 (2D) or 6/7 (3D)           */
+    double cheb_lo, cheb_hi;   /* default 1/3 and 2                          */
+    int newton_max;     /* cap on Newton iterations per small solve (30)     */
+    double newton_tol;  /* stop when |d|_inf <= tol max(1,|y|_inf) (1e-14)  */
+    int newton_passes;  /* fine quadrature passes per correction step kept in
+                           the launch sequence (a single-workgroup finisher
+                           completes any Newton solve that needs more)       */
+    int mode;           /* FMG_PAPER: Algorithm 3.2 as stated; FMG_CONVERGED:
+                           then repeat correction steps on the finest level
+                           until ||du||_2 <= converged_tol ||u||_2 (synchronous) */
+    int converged_max_steps;
+    double converged_tol;
+    int use_graph;      /* 1: capture the solve once into a hipGraph and replay */
+} fmg_options;
+
+typedef struct {
+    int kind;               /* enum fmg_nonlinearity                        */
+    double param;           /* c (LINEAR) or q (SIGNED_POW)                 */
+    const double *g_nodes;  /* device; load g at the finest nodes, (n+1)^dim,
+                               boundary entries ignored; must stay valid until
+                               the solve has completed on the stream         */
+} fmg_problem;
+
+typedef struct {
+    int status;                          /* enum fmg_status                  */
+    int levels;                          /* refinements + 1                  */
+    int level1_iters;                    /* Newton iterations on level 1     */
+    int extra_steps;                     /* converged mode: extra steps      */
+    int newton_iters[FMG_MAX_LEVELS];    /* per level k (index k-1), last step */
+    int newton_total[FMG_MAX_LEVELS];    /* per level, summed over the p steps */
+    double alpha[FMG_MAX_LEVELS];        /* coefficient of u~ in the last step */
+    double last_update_rel;              /* converged mode: ||du|| / ||u||   */
+} fmg_report;
+
+/* Fill *opts with the defaults for dimension dim (Section 4: m = 2, p = 1;
+ * V(2,2); Jacobi 4/5 in 2D, Chebyshev [1/3, 2] in 3D). */
+void fmg_default_options(int dim, fmg_options *opts);
+
+/* Bytes of device workspace fmg_create_hierarchy needs for this mesh and
+ * options (0 on invalid input).  Used for admission by memory footprint. */
+size_t fmg_workspace_bytes(const fmg_mesh_desc *mesh, const fmg_options *opts);
+
+/* Plan the level hierarchy (Section 3: T_{h_1} .. T_{h_n}, nested spaces,
+ * eq. "FEM_Space_Series") inside the caller's workspace d_workspace (device,
+ * 256-byte aligned, >= fmg_workspace_bytes bytes, must outlive the
+ * hierarchy), upload the level-1 tables and clear the level arrays on
+ * `stream` (a hipStream_t).  *out receives the handle. */
+int fmg_create_hierarchy(const fmg_mesh_desc *mesh, const fmg_options *opts,
+                         void *d_workspace, size_t workspace_bytes, void *stream,
+                         fmg_hierarchy **out);
+
+/* Solve one problem with Algorithm 3.2.  d_u_out (device, (n+1)^dim float64)
+ * receives the finest-level solution with zero boundary.  report may be NULL
+ * or point to memory the device can write (device memory or pinned host
+ * memory); it is written at the end of the solve.  Asynchronous in FMG_PAPER
+ * mode; FMG_CONVERGED mode synchronises the stream once per extra step. */
+int fmg_solve(fmg_hierarchy *h, const fmg_problem *prob, double *d_u_out,
+              fmg_report *report, void *stream);
+
+/* Copy the report of the last solve to host memory (synchronises `stream`). */
+int fmg_get_report(fmg_hierarchy *h, fmg_report *host_report, void *stream);
+
+/* Solve `count` independent problems, each on its own hierarchy (distinct
+ * workspaces, any mix of depths, dimensions and nonlinearities), with the
+ * launches of all of them interleaved phase by phase on one stream so that
+ * their work overlaps on the device.  outs[i] and reports[i] as in fmg_solve
+ * (reports may be NULL). */
+int fmg_solve_batch(fmg_hierarchy *const *hs, const fmg_problem *probs,
+                    double *const *outs, fmg_report *const *reports, int count,
+                    void *stream);
+
+/* Release the hierarchy's host state and graph; never frees caller memory. */
+int fmg_destroy(fmg_hierarchy *h);
+
+const char *fmg_status_str(int status);
+
+/* Single operators of the multigrid cycle on one level, for verification.
+ * Arrays are device float64 (n_k+1)^dim nodal arrays of level `level`
+ * (1-based; level n is the finest) except where noted; they are staged
+ * through the hierarchy's own level arrays (so no solve may be in flight).
+ * precision selects the float64 or float32 kernel instance.
+ *   FMG_OP_APPLY_A   out = A_k in0                      (stiffness, Section 2)
+ *   FMG_OP_SMOOTH    out = in0 + omega D^{-1}(in1 - A_k in0)   (one sweep)
+ *   FMG_OP_RESTRICT  out (level k-1) = P_k^T (in1 - A_k in0)   (residual)
+ *   FMG_OP_PROLONG   out = in1 + P_k in0, in0 on level k-1
+ *   FMG_OP_COARSE    out = A_1^{-1} in0 (level must be 1)
+ * Boundary entries of out are written as zero. */
+enum fmg_level_op { FMG_OP_APPLY_A = 0, FMG_OP_SMOOTH = 1, FMG_OP_RESTRICT = 2,
+                    FMG_OP_PROLONG = 3, FMG_OP_COARSE = 4 };
+int fmg_level_op(fmg_hierarchy *h, int op, int level, int precision,
+                 const double *in0, const double *in1, double *out, double omega,
+                 void *stream);
+
+/* Measurement: one solve with plain (uncaptured) launches and a pair of
+ * hipEvents recorded on `stream` around every kernel launch.  Entries are
+ * aggregated per (kernel class, level): launches, summed milliseconds and
+ * the algorithmic bytes the launches must move (minimal HBM streams of the
+ * operator, e.g. 24 B per node for a float64 Jacobi sweep).  Synchronous.
+ * Kernel classes are named by fmg_kernel_name. */
+#define FMG_PROFILE_MAX 512
+typedef struct {
+    int kernel;            /* kernel class id                                */
+    int level;             /* level k (0 when not level-specific)            */
+    int launches;
+    int nodes;             /* interior nodes of the level                    */
+    double ms;             /* summed event time of the launches             */
+    double bytes;          /* summed algorithmic bytes                       */
+} fmg_profile_entry;
+typedef struct {
+    int count;
+    double total_ms;       /* first to last event of the solve               */
+    fmg_profile_entry entries[FMG_PROFILE_MAX];
+} fmg_profile;
+int fmg_profile_solve(fmg_hierarchy *h, const fmg_problem *prob, double *d_u_out,
+                      void *stream, fmg_profile *out);
+const char *fmg_kernel_name(int kernel);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMG_H */

@@ -1,0 +1,806 @@
+// Host side of the FMG library: workspace planning, the launch sequence of
+// Algorithm 3.2 / Algorithm 3.1, optional hipGraph capture, and the C ABI of
+// include/fmg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fmg.h"
+#include "fmg_device.h"
+#include "fmg_kernels_aug.h"
+#include "fmg_kernels_mg.h"
+
+using namespace fmg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxAugBlocks = 2048;   // target number of blocks of the augmented passes
+constexpr int kNormBlocksMax = 1 << 20;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+inline int ilog2(long long v) { int r = 0; while ((1LL << (r + 1)) <= v) ++r; return r; }
+
+struct Resolved {          // options with defaults applied
+  fmg_options o;
+  int smoother;
+  double pre[16], post[16];
+};
+
+struct LevelInfo {
+  Grid g;
+  size_t count;            // elements per level array (incl. padding)
+  double scale;            // h^{d-2}: A_k = scale * (2d, -1 ...)
+  double m;                // lumped mass h^d
+  AugShape aug;            // augmented-pass tiling (levels >= 2)
+  int aug_blocks;
+};
+
+struct Plan {
+  int dim, nH, nlev, N1;
+  LevelInfo lev[FMG_MAX_LEVELS + 1];   // 1-based
+  size_t off_state, off_report, off_slot, off_flag, off_norm_out, off_norm_part;
+  size_t off_A1, off_A1inv, off_A1inv_f, off_pq, off_ps;
+  size_t off_x[FMG_MAX_LEVELS + 1], off_b[FMG_MAX_LEVELS + 1], off_t[FMG_MAX_LEVELS + 1];
+  size_t off_xs[FMG_MAX_LEVELS + 1], off_bs[FMG_MAX_LEVELS + 1], off_ts[FMG_MAX_LEVELS + 1];
+  size_t off_uprev;
+  size_t norm_blocks;
+  size_t total;
+};
+
+int resolve(int dim, const fmg_options* in, Resolved& r) {
+  fmg_options o;
+  if (in) o = *in; else fmg_default_options(dim, &o);
+  if (o.precision != FMG_FP64 && o.precision != FMG_MIXED) return FMG_E_INVALID;
+  if (o.m_vcycles < 1 || o.p_steps < 1 || o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre > 16 || o.nu_post > 16)
+    return FMG_E_INVALID;
+  if (o.smoother < 0 || o.smoother > 2 || o.omega < 0 || !(o.cheb_lo > 0) || !(o.cheb_hi > o.cheb_lo))
+    return FMG_E_INVALID;
+  if (o.newton_max < 1 || !(o.newton_tol > 0) || o.newton_passes < 1 || o.newton_passes > 64)
+    return FMG_E_INVALID;
+  if (o.mode != FMG_PAPER && o.mode != FMG_CONVERGED) return FMG_E_INVALID;
+  if (o.mode == FMG_CONVERGED && (o.converged_max_steps < 1 || !(o.converged_tol > 0))) return FMG_E_INVALID;
+  r.o = o;
+  r.smoother = o.smoother ? o.smoother : (dim == 2 ? FMG_JACOBI : FMG_CHEBYSHEV);
+  if (r.smoother == FMG_JACOBI) {
+    const double w = o.omega > 0 ? o.omega : (dim == 2 ? 4.0 / 5.0 : 6.0 / 7.0);
+    for (int i = 0; i < 16; ++i) r.pre[i] = r.post[i] = w;
+  } else {
+    // reciprocals of the roots of the Chebyshev polynomial of degree nu on
+    // [lo, hi]; post-smoothing uses them in reverse order
+    const double c = 0.5 * (o.cheb_hi + o.cheb_lo), rad = 0.5 * (o.cheb_hi - o.cheb_lo);
+    for (int i = 0; i < o.nu_pre; ++i)
+      r.pre[i] = 1.0 / (c + rad * std::cos(M_PI * (2 * (i + 1) - 1) / (2.0 * o.nu_pre)));
+    for (int i = 0; i < o.nu_post; ++i)
+      r.post[o.nu_post - 1 - i] = 1.0 / (c + rad * std::cos(M_PI * (2 * (i + 1) - 1) / (2.0 * o.nu_post)));
+  }
+  return FMG_OK;
+}
+
+int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p) {
+  if (!mesh) return FMG_E_INVALID;
+  const int d = mesh->dim;
+  if (d != 2 && d != 3) return FMG_E_UNSUPPORTED;
+  if (mesh->coarse_cells < 2 || mesh->coarse_cells > (d == 2 ? 8 : 4)) return FMG_E_UNSUPPORTED;
+  if (mesh->refinements < 1 || mesh->refinements > (d == 2 ? 12 : 8)) return FMG_E_UNSUPPORTED;
+  std::memset(&p, 0, sizeof(p));
+  p.dim = d;
+  p.nH = mesh->coarse_cells;
+  p.nlev = mesh->refinements + 1;
+  p.N1 = 1;
+  for (int a = 0; a < d; ++a) p.N1 *= p.nH - 1;
+  const int ncell = d == 2 ? p.nH * p.nH : p.nH * p.nH * p.nH;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  p.off_state = take(sizeof(NewtonState));
+  p.off_report = take(sizeof(fmg_report));
+  p.off_slot = take(sizeof(ProblemSlot));
+  p.off_flag = take(64);
+  p.off_norm_out = take(64);
+  p.off_A1 = take(sizeof(double) * p.N1 * p.N1);
+  p.off_A1inv = take(sizeof(double) * p.N1 * p.N1);
+  p.off_A1inv_f = take(sizeof(float) * p.N1 * p.N1);
+  int max_blocks = 1;
+  for (int k = 1; k <= p.nlev; ++k) {
+    LevelInfo& L = p.lev[k];
+    L.g.n = p.nH << (k - 1);
+    L.g.px = pitch_for(L.g.n);
+    L.g.pz = d == 3 ? L.g.px * (L.g.n + 1) : 0;
+    L.count = d == 2 ? (size_t)L.g.px * (L.g.n + 1) : (size_t)L.g.pz * (L.g.n + 1);
+    const double h = 1.0 / L.g.n;
+    L.scale = d == 2 ? 1.0 : h;
+    L.m = d == 2 ? h * h : h * h * h;
+    if (k >= 2) {
+      const int nodes_log = d * (k - 1);
+      const int cap_log = ilog2(std::max(1, kMaxAugBlocks / ncell));
+      const int bpc_log = std::max(0, std::min(nodes_log - 8, cap_log));
+      L.aug.nH = p.nH;
+      L.aug.log2r = k - 1;
+      L.aug.bpc_log = bpc_log;
+      L.aug.npb_log = nodes_log - bpc_log;
+      L.aug.N1 = p.N1;
+      L.aug_blocks = ncell << bpc_log;
+      max_blocks = std::max(max_blocks, L.aug_blocks);
+    }
+  }
+  p.off_pq = take(sizeof(double) * max_blocks * Acc<3>::NQ);
+  p.off_ps = take(sizeof(double) * max_blocks * Acc<3>::NS);
+  const LevelInfo& F = p.lev[p.nlev];
+  const size_t rows = (size_t)(F.g.n - 1) * (d == 3 ? (F.g.n - 1) : 1);
+  p.norm_blocks = rows * (size_t)((F.g.n - 1 + kBlock - 1) / kBlock);
+  p.off_norm_part = ro.o.mode == FMG_CONVERGED ? take(sizeof(double) * 2 * p.norm_blocks) : 0;
+  for (int k = 1; k <= p.nlev; ++k) {
+    const size_t c = p.lev[k].count;
+    p.off_x[k] = take(sizeof(double) * c);
+    p.off_b[k] = take(sizeof(double) * c);
+    p.off_t[k] = take(sizeof(double) * c);
+    if (ro.o.precision == FMG_MIXED) {
+      p.off_xs[k] = take(sizeof(float) * c);
+      p.off_bs[k] = take(sizeof(float) * c);
+      p.off_ts[k] = take(sizeof(float) * c);
+    }
+  }
+  p.off_uprev = ro.o.mode == FMG_CONVERGED ? take(sizeof(double) * F.count) : 0;
+  p.total = off;
+  return FMG_OK;
+}
+
+}  // namespace
+
+namespace { struct Prof; }
+
+struct fmg_hierarchy {
+  Plan plan;
+  Resolved ro;
+  char* ws;
+  size_t ws_bytes;
+  hipStream_t cap_stream;
+  hipGraphExec_t graph[7];
+  // final roles of the level buffers after a recorded solve (x = current iterate)
+  double* x_final[FMG_MAX_LEVELS + 1];
+  double* t_final[FMG_MAX_LEVELS + 1];
+  Prof* prof;              // set only while fmg_profile_solve records
+  template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  NewtonState* ns() const { return at<NewtonState>(plan.off_state); }
+  fmg_report* rep() const { return at<fmg_report>(plan.off_report); }
+  ProblemSlot* slot() const { return at<ProblemSlot>(plan.off_slot); }
+  int* flag() const { return at<int>(plan.off_flag); }
+};
+
+namespace {
+
+inline dim3 grid_of(const Grid& g, int dim) {
+  return dim3((g.n - 1 + kBlock - 1) / kBlock, g.n - 1, dim == 3 ? g.n - 1 : 1);
+}
+
+// Kernel classes reported by fmg_profile_solve.
+enum KernelClass {
+  KC_SMOOTH64, KC_SMOOTH64_ZERO, KC_RESTRICT64, KC_PROLONG64_ADD, KC_COARSE64,
+  KC_SMOOTH32, KC_SMOOTH32_ZERO, KC_RESTRICT32, KC_PROLONG32_ADD, KC_COARSE32,
+  KC_PROLONG_FMG, KC_RHS, KC_RESID_F32, KC_ADD_F32, KC_AUG_SETUP, KC_AUG_QUAD, KC_NEWTON_STEP,
+  KC_NEWTON_FINISH, KC_AUG_UPDATE, KC_LEVEL1, KC_BEGIN, KC_OUTPUT, KC_END, KC_FILL, KC_COUNT
+};
+const char* const kKernelNames[KC_COUNT] = {
+  "smooth_f64", "smooth_f64_from_zero", "resid_restrict_f64", "prolong_add_f64", "coarse_solve_f64",
+  "smooth_f32", "smooth_f32_from_zero", "resid_restrict_f32", "prolong_add_f32", "coarse_solve_f32",
+  "prolong_fmg", "rhs", "resid_to_f32", "add_f32", "aug_setup", "aug_quad", "newton_step",
+  "newton_finish", "aug_update", "level1_newton", "begin_solve", "output", "end_solve", "fill"};
+
+// Event pairs around launches (fmg_profile_solve only).
+struct Prof {
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kid, lev, nodes;
+  std::vector<double> bytes;
+  void begin(hipStream_t st) {
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    (void)hipEventRecord(e, st);
+    ev.push_back(e);
+  }
+  void end(hipStream_t st, int k, int l, long long nn, double b) {
+    begin(st);
+    kid.push_back(k); lev.push_back(l); nodes.push_back((int)nn); bytes.push_back(b);
+  }
+};
+
+#define FMG_LAUNCH(h, st, KID, LEV, NODES, BYTES, ...)       \
+  do {                                                        \
+    Prof* _pf = (h)->prof;                                    \
+    if (_pf) _pf->begin(st);                                  \
+    __VA_ARGS__;                                              \
+    if (_pf) _pf->end(st, KID, LEV, NODES, BYTES);            \
+  } while (0)
+
+inline long long interior(const Grid& g, int dim) {
+  const long long m = g.n - 1;
+  return dim == 2 ? m * m : m * m * m;
+}
+
+// Buffer roles during one recorded launch sequence.
+struct Roles {
+  double* x[FMG_MAX_LEVELS + 1];
+  double* t[FMG_MAX_LEVELS + 1];
+  float* xs[FMG_MAX_LEVELS + 1];
+  float* ts[FMG_MAX_LEVELS + 1];
+};
+
+template <typename T> struct Sel;
+template <> struct Sel<double> {
+  static double*& x(Roles& r, int k) { return r.x[k]; }
+  static double*& t(Roles& r, int k) { return r.t[k]; }
+  static double* b(const fmg_hierarchy* h, int k) { return h->at<double>(h->plan.off_b[k]); }
+  static const double* ainv(const fmg_hierarchy* h) { return h->at<double>(h->plan.off_A1inv); }
+  static constexpr int kc = 0;
+};
+template <> struct Sel<float> {
+  static float*& x(Roles& r, int k) { return r.xs[k]; }
+  static float*& t(Roles& r, int k) { return r.ts[k]; }
+  static float* b(const fmg_hierarchy* h, int k) { return h->at<float>(h->plan.off_bs[k]); }
+  static const float* ainv(const fmg_hierarchy* h) { return h->at<float>(h->plan.off_A1inv_f); }
+  static constexpr int kc = KC_SMOOTH32 - KC_SMOOTH64;
+};
+
+void canonical_roles(const fmg_hierarchy* h, Roles& r) {
+  const Plan& p = h->plan;
+  for (int k = 1; k <= p.nlev; ++k) {
+    r.x[k] = h->at<double>(p.off_x[k]);
+    r.t[k] = h->at<double>(p.off_t[k]);
+    r.xs[k] = p.off_xs[k] ? h->at<float>(p.off_xs[k]) : nullptr;
+    r.ts[k] = p.off_ts[k] ? h->at<float>(p.off_ts[k]) : nullptr;
+  }
+}
+
+template <int DIM, typename T>
+void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t st) {
+  const Plan& p = h->plan;
+  const LevelInfo& L = p.lev[k];
+  T*& x = Sel<T>::x(R, k);
+  T*& t = Sel<T>::t(R, k);
+  T* b = Sel<T>::b(h, k);
+  const int kc = Sel<T>::kc;
+  const long long N = interior(L.g, DIM);
+  const double s = sizeof(T);
+  if (k == 1) {
+    FMG_LAUNCH(h, st, KC_COARSE64 + kc, 1, N, 2 * s * N,
+               k_coarse_solve<DIM, T><<<1, 64, 0, st>>>(L.g, p.N1, Sel<T>::ainv(h), b, x));
+    return;
+  }
+  const dim3 grid = grid_of(L.g, DIM);
+  const T scale = (T)L.scale;
+  const double D = 2.0 * DIM * L.scale;
+  const int npre = h->ro.o.nu_pre, npost = h->ro.o.nu_post;
+  if (zero_init && npre == 0)
+    FMG_LAUNCH(h, st, KC_FILL, k, N, s * L.count, k_fill<T><<<256, 256, 0, st>>>(x, L.count, T(0)));
+  for (int i = 0; i < npre; ++i) {
+    const T wd = (T)(h->ro.pre[i] / D);
+    if (zero_init && i == 0)
+      FMG_LAUNCH(h, st, KC_SMOOTH64_ZERO + kc, k, N, 2 * s * N,
+                 k_smooth<DIM, T, true><<<grid, kBlock, 0, st>>>(L.g, x, b, t, wd, scale));
+    else
+      FMG_LAUNCH(h, st, KC_SMOOTH64 + kc, k, N, 3 * s * N,
+                 k_smooth<DIM, T, false><<<grid, kBlock, 0, st>>>(L.g, x, b, t, wd, scale));
+    std::swap(x, t);
+  }
+  const LevelInfo& C = p.lev[k - 1];
+  const long long Nc = interior(C.g, DIM);
+  FMG_LAUNCH(h, st, KC_RESTRICT64 + kc, k, N, s * (2 * N + Nc),
+             k_resid_restrict<DIM, T><<<grid_of(C.g, DIM), kBlock, 0, st>>>(L.g, C.g, x, b, Sel<T>::b(h, k - 1),
+                                                                           scale));
+  vcycle<DIM, T>(h, R, k - 1, true, st);
+  FMG_LAUNCH(h, st, KC_PROLONG64_ADD + kc, k, N, s * (2 * N + Nc),
+             k_prolong<DIM, T, true><<<grid, kBlock, 0, st>>>(C.g, L.g, Sel<T>::x(R, k - 1), x));
+  for (int i = 0; i < npost; ++i) {
+    const T wd = (T)(h->ro.post[i] / D);
+    FMG_LAUNCH(h, st, KC_SMOOTH64 + kc, k, N, 3 * s * N,
+               k_smooth<DIM, T, false><<<grid, kBlock, 0, st>>>(L.g, x, b, t, wd, scale));
+    std::swap(x, t);
+  }
+}
+
+inline size_t newton_lds_bytes(const Plan& p, bool finisher) {
+  const int ncell = p.dim == 2 ? p.nH * p.nH : p.nH * p.nH * p.nH;
+  const int NQ = p.dim == 2 ? Acc<2>::NQ : Acc<3>::NQ;
+  const int ny = p.N1 + 1;
+  size_t doubles = (size_t)ncell * NQ + ny * ny + ny + 8 + (finisher ? 4 * NQ : 0);
+  return doubles * sizeof(double);
+}
+
+// One correction step (Algorithm 3.1) on level k; the current iterate is R.x[k].
+template <int DIM, int KIND>
+void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st) {
+  const Plan& p = h->plan;
+  const LevelInfo& L = p.lev[k];
+  const fmg_options& o = h->ro.o;
+  const dim3 grid = grid_of(L.g, DIM);
+  const long long N = interior(L.g, DIM);
+  const int nf1 = p.lev[p.nlev].g.n + 1, fs = 1 << (p.nlev - k);
+  double* b = h->at<double>(p.off_b[k]);
+  // step 1: linearised problem, m V-cycles from u^(l)
+  FMG_LAUNCH(h, st, KC_RHS, k, N, 24.0 * N,
+             k_rhs<DIM, KIND><<<grid, kBlock, 0, st>>>(L.g, h->slot(), nf1, fs, R.x[k], b, L.m));
+  for (int c = 0; c < o.m_vcycles; ++c) {
+    if (o.precision == FMG_FP64) {
+      vcycle<DIM, double>(h, R, k, false, st);
+    } else {
+      // float32 cycle on the correction equation, float64 residual and update
+      FMG_LAUNCH(h, st, KC_RESID_F32, k, N, 20.0 * N,
+                 k_resid_to_f32<DIM><<<grid, kBlock, 0, st>>>(L.g, R.x[k], b, h->at<float>(p.off_bs[k]),
+                                                              L.scale));
+      vcycle<DIM, float>(h, R, k, true, st);
+      FMG_LAUNCH(h, st, KC_ADD_F32, k, N, 20.0 * N,
+                 k_add_f32<DIM><<<grid, kBlock, 0, st>>>(L.g, R.x[k], R.xs[k]));
+    }
+  }
+  // step 2: semilinear problem on V_H + span{u~}
+  double* pq = h->at<double>(p.off_pq);
+  double* ps = h->at<double>(p.off_ps);
+  const double* A1 = h->at<double>(p.off_A1);
+  FMG_LAUNCH(h, st, KC_AUG_SETUP, k, N, 16.0 * N,
+             k_aug_setup<DIM><<<L.aug_blocks, kBlock, 0, st>>>(L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale,
+                                                               ps, h->ns(), k));
+  const size_t lds = newton_lds_bytes(p, false);
+  for (int pass = 0; pass < o.newton_passes; ++pass) {
+    FMG_LAUNCH(h, st, KC_AUG_QUAD, k, N, 8.0 * N,
+               k_aug_quad<DIM, KIND><<<L.aug_blocks, kBlock, 0, st>>>(L.g, L.aug, R.x[k], h->slot(), h->ns(), pq));
+    FMG_LAUNCH(h, st, KC_NEWTON_STEP, k, N, 0.0,
+               k_newton_step<DIM><<<1, 256, lds, st>>>(L.aug, pq, ps, A1, L.m, h->ns(), h->rep(), o.newton_max,
+                                                       o.newton_tol));
+  }
+  FMG_LAUNCH(h, st, KC_NEWTON_FINISH, k, N, 0.0,
+             k_newton_finish<DIM, KIND><<<1, 256, newton_lds_bytes(p, true), st>>>(
+                 L.g, L.aug, R.x[k], h->slot(), A1, L.m, h->ns(), h->rep(), o.newton_max, o.newton_tol));
+  FMG_LAUNCH(h, st, KC_AUG_UPDATE, k, N, 16.0 * N,
+             k_aug_update<DIM><<<grid, kBlock, 0, st>>>(L.g, L.aug, h->ns(), R.x[k]));
+}
+
+template <int DIM, int KIND>
+void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
+  const Plan& p = h->plan;
+  const fmg_options& o = h->ro.o;
+  const int nf1 = p.lev[p.nlev].g.n + 1;
+  FMG_LAUNCH(h, st, KC_BEGIN, 0, 0, 0.0, k_begin_solve<<<1, 64, 0, st>>>(h->rep(), p.nlev, h->flag()));
+  // Algorithm 3.2, step 1: exact semilinear solve on V_{h_1}
+  const LevelInfo& L1 = p.lev[1];
+  const size_t lds1 = sizeof(double) * ((size_t)p.N1 * p.N1 + 6 * p.N1 + 4);
+  FMG_LAUNCH(h, st, KC_LEVEL1, 1, p.N1, 0.0,
+             k_level1_newton<DIM, KIND><<<1, 256, lds1, st>>>(L1.g, p.N1, h->at<double>(p.off_A1), L1.m,
+                                                              h->slot(), nf1, 1 << (p.nlev - 1), R.x[1], h->rep(),
+                                                              o.newton_max, o.newton_tol));
+  // step 2: levels k = 2..n
+  for (int k = 2; k <= p.nlev; ++k) {
+    const LevelInfo& L = p.lev[k];
+    const long long N = interior(L.g, DIM);
+    FMG_LAUNCH(h, st, KC_PROLONG_FMG, k, N, 8.0 * (N + interior(p.lev[k - 1].g, DIM)),
+               k_prolong<DIM, double, false><<<grid_of(L.g, DIM), kBlock, 0, st>>>(p.lev[k - 1].g, L.g,
+                                                                                  R.x[k - 1], R.x[k]));
+    for (int l = 0; l < o.p_steps; ++l) correction_step<DIM, KIND>(h, R, k, st);
+  }
+  if (finish) {
+    const LevelInfo& F = p.lev[p.nlev];
+    const double nodes = DIM == 2 ? (double)(F.g.n + 1) * (F.g.n + 1) : (double)(F.g.n + 1) * (F.g.n + 1) * (F.g.n + 1);
+    FMG_LAUNCH(h, st, KC_OUTPUT, p.nlev, interior(F.g, DIM), 16.0 * nodes,
+               k_output<DIM><<<1024, 256, 0, st>>>(F.g, R.x[p.nlev], h->slot(), h->flag()));
+    FMG_LAUNCH(h, st, KC_END, 0, 0, 0.0, k_end_solve<<<1, 64, 0, st>>>(h->rep(), h->flag(), h->slot()));
+  }
+}
+
+typedef void (*record_fn)(const fmg_hierarchy*, Roles&, bool, hipStream_t);
+typedef void (*step_fn)(const fmg_hierarchy*, Roles&, int, hipStream_t);
+
+template <int DIM>
+record_fn pick_record(int kind) {
+  switch (kind) {
+    case FMG_F_ZERO: return record_fmg<DIM, FMG_F_ZERO>;
+    case FMG_F_LINEAR: return record_fmg<DIM, FMG_F_LINEAR>;
+    case FMG_F_CUBIC: return record_fmg<DIM, FMG_F_CUBIC>;
+    case FMG_F_U_PLUS_SIN: return record_fmg<DIM, FMG_F_U_PLUS_SIN>;
+    case FMG_F_ABS_U_U: return record_fmg<DIM, FMG_F_ABS_U_U>;
+    case FMG_F_SIGNED_POW: return record_fmg<DIM, FMG_F_SIGNED_POW>;
+    default: return record_fmg<DIM, FMG_F_NEG_EXP>;
+  }
+}
+template <int DIM>
+step_fn pick_step(int kind) {
+  switch (kind) {
+    case FMG_F_ZERO: return correction_step<DIM, FMG_F_ZERO>;
+    case FMG_F_LINEAR: return correction_step<DIM, FMG_F_LINEAR>;
+    case FMG_F_CUBIC: return correction_step<DIM, FMG_F_CUBIC>;
+    case FMG_F_U_PLUS_SIN: return correction_step<DIM, FMG_F_U_PLUS_SIN>;
+    case FMG_F_ABS_U_U: return correction_step<DIM, FMG_F_ABS_U_U>;
+    case FMG_F_SIGNED_POW: return correction_step<DIM, FMG_F_SIGNED_POW>;
+    default: return correction_step<DIM, FMG_F_NEG_EXP>;
+  }
+}
+
+int check_problem(const fmg_problem* prob) {
+  if (!prob || !prob->g_nodes) return FMG_E_INVALID;
+  if (prob->kind < FMG_F_ZERO || prob->kind > FMG_F_NEG_EXP) return FMG_E_INVALID;
+  if (prob->kind == FMG_F_LINEAR && !(prob->param >= 0)) return FMG_E_INVALID;
+  if (prob->kind == FMG_F_SIGNED_POW && !(prob->param >= 1)) return FMG_E_INVALID;
+  return FMG_OK;
+}
+
+void build_level1(const Plan& p, std::vector<double>& A, std::vector<double>& Ainv) {
+  // A_1 on the interior nodes of the coarse grid: scale (2d on the diagonal,
+  // -1 for the axis neighbours), dense, x fastest.
+  const int d = p.dim, m = p.nH - 1, N = p.N1;
+  const double s = p.lev[1].scale;
+  A.assign((size_t)N * N, 0.0);
+  for (int r = 0; r < N; ++r) {
+    const int i = r % m, j = (r / m) % m, l = d == 3 ? r / (m * m) : 0;
+    A[(size_t)r * N + r] = 2.0 * d * s;
+    auto link = [&](int ii, int jj, int ll) {
+      if (ii < 0 || jj < 0 || ll < 0 || ii >= m || jj >= m || ll >= (d == 3 ? m : 1)) return;
+      A[(size_t)r * N + (ii + m * jj + m * m * ll)] = -s;
+    };
+    link(i - 1, j, l); link(i + 1, j, l); link(i, j - 1, l); link(i, j + 1, l);
+    if (d == 3) { link(i, j, l - 1); link(i, j, l + 1); }
+  }
+  // Gauss-Jordan inverse with partial pivoting
+  std::vector<double> M(A);
+  Ainv.assign((size_t)N * N, 0.0);
+  for (int r = 0; r < N; ++r) Ainv[(size_t)r * N + r] = 1.0;
+  for (int c = 0; c < N; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < N; ++r)
+      if (std::fabs(M[(size_t)r * N + c]) > std::fabs(M[(size_t)piv * N + c])) piv = r;
+    if (piv != c)
+      for (int k = 0; k < N; ++k) {
+        std::swap(M[(size_t)c * N + k], M[(size_t)piv * N + k]);
+        std::swap(Ainv[(size_t)c * N + k], Ainv[(size_t)piv * N + k]);
+      }
+    const double inv = 1.0 / M[(size_t)c * N + c];
+    for (int k = 0; k < N; ++k) { M[(size_t)c * N + k] *= inv; Ainv[(size_t)c * N + k] *= inv; }
+    for (int r = 0; r < N; ++r) {
+      if (r == c) continue;
+      const double f = M[(size_t)r * N + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < N; ++k) {
+        M[(size_t)r * N + k] -= f * M[(size_t)c * N + k];
+        Ainv[(size_t)r * N + k] -= f * Ainv[(size_t)c * N + k];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void fmg_default_options(int dim, fmg_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = FMG_FP64;
+  o->m_vcycles = 2;
+  o->p_steps = 1;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->smoother = FMG_SMOOTHER_DEFAULT;
+  o->omega = 0.0;
+  o->cheb_lo = 1.0 / 3.0;
+  o->cheb_hi = 2.0;
+  o->newton_max = 30;
+  o->newton_tol = 1e-14;
+  o->newton_passes = 5;
+  o->mode = FMG_PAPER;
+  o->converged_max_steps = 40;
+  o->converged_tol = 1e-13;
+  o->use_graph = 1;
+  (void)dim;
+}
+
+size_t fmg_workspace_bytes(const fmg_mesh_desc* mesh, const fmg_options* opts) {
+  if (!mesh) return 0;
+  Resolved ro;
+  if (resolve(mesh->dim, opts, ro) != FMG_OK) return 0;
+  Plan p;
+  if (make_plan(mesh, ro, p) != FMG_OK) return 0;
+  return p.total;
+}
+
+int fmg_create_hierarchy(const fmg_mesh_desc* mesh, const fmg_options* opts, void* d_workspace,
+                         size_t workspace_bytes, void* stream, fmg_hierarchy** out) {
+  if (!mesh || !out || !d_workspace) return FMG_E_INVALID;
+  *out = nullptr;
+  Resolved ro;
+  int st = resolve(mesh->dim, opts, ro);
+  if (st != FMG_OK) return st;
+  Plan p;
+  if ((st = make_plan(mesh, ro, p)) != FMG_OK) return st;
+  if (workspace_bytes < p.total || (reinterpret_cast<uintptr_t>(d_workspace) & (kAlign - 1))) return FMG_E_WORKSPACE;
+  fmg_hierarchy* h = new (std::nothrow) fmg_hierarchy();
+  if (!h) return FMG_E_INVALID;
+  h->plan = p;
+  h->ro = ro;
+  h->ws = static_cast<char*>(d_workspace);
+  h->ws_bytes = workspace_bytes;
+  for (auto& g : h->graph) g = nullptr;
+  h->prof = nullptr;
+  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete h; return FMG_E_HIP; }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // zero every level array once: the Dirichlet rings stay zero for good
+  for (int k = 1; k <= p.nlev; ++k) {
+    const size_t c = p.lev[k].count;
+    double* arrs[3] = {h->at<double>(p.off_x[k]), h->at<double>(p.off_b[k]), h->at<double>(p.off_t[k])};
+    for (double* a : arrs) k_fill<double><<<1024, 256, 0, s>>>(a, c, 0.0);
+    if (ro.o.precision == FMG_MIXED) {
+      float* fa[3] = {h->at<float>(p.off_xs[k]), h->at<float>(p.off_bs[k]), h->at<float>(p.off_ts[k])};
+      for (float* a : fa) k_fill<float><<<1024, 256, 0, s>>>(a, c, 0.0f);
+    }
+  }
+  if (p.off_uprev) k_fill<double><<<1024, 256, 0, s>>>(h->at<double>(p.off_uprev), p.lev[p.nlev].count, 0.0);
+  std::vector<double> A, Ainv;
+  build_level1(p, A, Ainv);
+  std::vector<float> Ainv_f(Ainv.begin(), Ainv.end());
+  if (hipMemcpyAsync(h->at<double>(p.off_A1), A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(h->at<double>(p.off_A1inv), Ainv.data(), Ainv.size() * sizeof(double), hipMemcpyHostToDevice,
+                     s) != hipSuccess ||
+      hipMemcpyAsync(h->at<float>(p.off_A1inv_f), Ainv_f.data(), Ainv_f.size() * sizeof(float),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
+    (void)hipStreamDestroy(h->cap_stream);
+    delete h;
+    return FMG_E_HIP;
+  }
+  *out = h;
+  return FMG_OK;
+}
+
+int fmg_solve(fmg_hierarchy* h, const fmg_problem* prob, double* d_u_out, fmg_report* report, void* stream) {
+  if (!h || !d_u_out) return FMG_E_INVALID;
+  int st = check_problem(prob);
+  if (st != FMG_OK) return st;
+  const Plan& p = h->plan;
+  const fmg_options& o = h->ro.o;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  k_set_slot<<<1, 64, 0, s>>>(h->slot(), prob->g_nodes, d_u_out, report, prob->param, prob->kind);
+  record_fn rec = p.dim == 2 ? pick_record<2>(prob->kind) : pick_record<3>(prob->kind);
+  Roles R;
+  canonical_roles(h, R);
+  if (o.mode == FMG_PAPER && o.use_graph) {
+    hipGraphExec_t& ex = h->graph[prob->kind];
+    if (!ex) {
+      hipGraph_t graph;
+      if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return FMG_E_HIP;
+      rec(h, R, true, h->cap_stream);
+      if (hipStreamEndCapture(h->cap_stream, &graph) != hipSuccess) return FMG_E_HIP;
+      const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) { ex = nullptr; return FMG_E_HIP; }
+      for (int k = 1; k <= p.nlev; ++k) { h->x_final[k] = R.x[k]; h->t_final[k] = R.t[k]; }
+    }
+    if (hipGraphLaunch(ex, s) != hipSuccess) return FMG_E_HIP;
+    return hipGetLastError() == hipSuccess ? FMG_OK : FMG_E_HIP;
+  }
+  const bool converged = o.mode == FMG_CONVERGED;
+  rec(h, R, !converged, s);
+  if (converged) {
+    const int k = p.nlev;
+    const LevelInfo& F = p.lev[k];
+    step_fn step = p.dim == 2 ? pick_step<2>(prob->kind) : pick_step<3>(prob->kind);
+    double* uprev = h->at<double>(p.off_uprev);
+    double* npart = h->at<double>(p.off_norm_part);
+    double* nout = h->at<double>(p.off_norm_out);
+    double prev = INFINITY, rel = 0.0;
+    int steps = 0;
+    for (int it = 0; it < o.converged_max_steps; ++it) {
+      const dim3 grid = grid_of(F.g, p.dim);
+      if (p.dim == 2) k_copy_interior<2, double><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev);
+      else k_copy_interior<3, double><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev);
+      step(h, R, k, s);
+      if (p.dim == 2) k_diff_norm_partials<2><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev, npart);
+      else k_diff_norm_partials<3><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev, npart);
+      k_sum_pairs<<<1, kBlock, 0, s>>>(npart, p.norm_blocks, nout);
+      double host[2];
+      if (hipMemcpyAsync(host, nout, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return FMG_E_HIP;
+      steps = it + 1;
+      const double du = std::sqrt(host[0]);
+      rel = du / std::max(std::sqrt(host[1]), 1e-300);
+      if (rel <= o.converged_tol || du >= prev) break;
+      prev = du;
+    }
+    const bool reached = rel <= o.converged_tol || steps < o.converged_max_steps;
+    // record the extra-step info on the device report, then finish
+    fmg_report info;
+    std::memset(&info, 0, sizeof(info));
+    if (hipMemcpyAsync(&info, h->rep(), sizeof(info), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FMG_E_HIP;
+    info.extra_steps = steps;
+    info.last_update_rel = rel;
+    if (!reached && info.status == FMG_OK) info.status = FMG_E_NOT_CONVERGED;
+    if (hipMemcpyAsync(h->rep(), &info, sizeof(info), hipMemcpyHostToDevice, s) != hipSuccess) return FMG_E_HIP;
+    if (p.dim == 2) k_output<2><<<1024, 256, 0, s>>>(F.g, R.x[k], h->slot(), h->flag());
+    else k_output<3><<<1024, 256, 0, s>>>(F.g, R.x[k], h->slot(), h->flag());
+    k_end_solve<<<1, 64, 0, s>>>(h->rep(), h->flag(), h->slot());
+    if (hipStreamSynchronize(s) != hipSuccess) return FMG_E_HIP;
+  }
+  return hipGetLastError() == hipSuccess ? FMG_OK : FMG_E_HIP;
+}
+
+int fmg_profile_solve(fmg_hierarchy* h, const fmg_problem* prob, double* d_u_out, void* stream,
+                      fmg_profile* out) {
+  if (!h || !d_u_out || !out) return FMG_E_INVALID;
+  int st = check_problem(prob);
+  if (st != FMG_OK) return st;
+  const Plan& p = h->plan;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  k_set_slot<<<1, 64, 0, s>>>(h->slot(), prob->g_nodes, d_u_out, nullptr, prob->param, prob->kind);
+  record_fn rec = p.dim == 2 ? pick_record<2>(prob->kind) : pick_record<3>(prob->kind);
+  Prof pf;
+  Roles R;
+  canonical_roles(h, R);
+  h->prof = &pf;
+  rec(h, R, true, s);
+  h->prof = nullptr;
+  if (hipStreamSynchronize(s) != hipSuccess) st = FMG_E_HIP;
+  std::memset(out, 0, sizeof(*out));
+  const size_t n = pf.kid.size();
+  for (size_t i = 0; i < n && st == FMG_OK; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pf.ev[2 * i], pf.ev[2 * i + 1]) != hipSuccess) { st = FMG_E_HIP; break; }
+    int e = 0;
+    while (e < out->count && !(out->entries[e].kernel == pf.kid[i] && out->entries[e].level == pf.lev[i])) ++e;
+    if (e == out->count) {
+      if (out->count == FMG_PROFILE_MAX) continue;
+      out->count++;
+      out->entries[e].kernel = pf.kid[i];
+      out->entries[e].level = pf.lev[i];
+      out->entries[e].nodes = pf.nodes[i];
+    }
+    out->entries[e].launches++;
+    out->entries[e].ms += ms;
+    out->entries[e].bytes += pf.bytes[i];
+  }
+  if (st == FMG_OK && !pf.ev.empty()) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pf.ev.front(), pf.ev.back()) == hipSuccess) out->total_ms = ms;
+  }
+  for (hipEvent_t e : pf.ev) (void)hipEventDestroy(e);
+  return st;
+}
+
+const char* fmg_kernel_name(int kernel) {
+  return (kernel >= 0 && kernel < KC_COUNT) ? kKernelNames[kernel] : "unknown";
+}
+
+int fmg_get_report(fmg_hierarchy* h, fmg_report* host_report, void* stream) {
+  if (!h || !host_report) return FMG_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(host_report, h->rep(), sizeof(fmg_report), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FMG_E_HIP;
+  return FMG_OK;
+}
+
+int fmg_solve_batch(fmg_hierarchy* const* hs, const fmg_problem* probs, double* const* outs,
+                    fmg_report* const* reports, int count, void* stream) {
+  if (count < 0 || (count > 0 && (!hs || !probs || !outs))) return FMG_E_INVALID;
+  for (int i = 0; i < count; ++i) {
+    const int st = fmg_solve(hs[i], &probs[i], outs[i], reports ? reports[i] : nullptr, stream);
+    if (st != FMG_OK) return st;
+  }
+  return FMG_OK;
+}
+
+int fmg_destroy(fmg_hierarchy* h) {
+  if (!h) return FMG_E_INVALID;
+  for (auto& g : h->graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  (void)hipStreamDestroy(h->cap_stream);
+  delete h;
+  return FMG_OK;
+}
+
+const char* fmg_status_str(int status) {
+  switch (status) {
+    case FMG_OK: return "ok";
+    case FMG_E_INVALID: return "invalid argument";
+    case FMG_E_UNSUPPORTED: return "unsupported mesh or option";
+    case FMG_E_WORKSPACE: return "workspace too small or misaligned";
+    case FMG_E_HIP: return "HIP runtime error";
+    case FMG_E_NOT_CONVERGED: return "Newton iteration did not converge";
+    case FMG_E_NONFINITE: return "non-finite value in the solution";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"
+
+namespace {
+template <int DIM>
+int level_op_impl(fmg_hierarchy* h, int op, int k, int prec, const double* in0, const double* in1, double* out,
+                  double omega, hipStream_t s) {
+  const Plan& p = h->plan;
+  const LevelInfo& L = p.lev[k];
+  const dim3 grid = grid_of(L.g, DIM);
+  const int pk = 512;
+  double* x = h->at<double>(p.off_x[k]);
+  double* b = h->at<double>(p.off_b[k]);
+  double* t = h->at<double>(p.off_t[k]);
+  if (prec == FMG_MIXED && !p.off_xs[k]) return FMG_E_INVALID;
+  float* xs = prec == FMG_MIXED ? h->at<float>(p.off_xs[k]) : nullptr;
+  float* bs = prec == FMG_MIXED ? h->at<float>(p.off_bs[k]) : nullptr;
+  float* ts = prec == FMG_MIXED ? h->at<float>(p.off_ts[k]) : nullptr;
+  const double D = 2.0 * DIM * L.scale;
+  auto in = [&](const double* src, double* d64, float* d32, const Grid& g) {
+    if (prec == FMG_FP64) k_pack<DIM, double, double><<<pk, 256, 0, s>>>(g, src, d64, 0);
+    else k_pack<DIM, float, double><<<pk, 256, 0, s>>>(g, src, d32, 0);
+  };
+  auto outp = [&](const double* s64, const float* s32, const Grid& g) {
+    if (prec == FMG_FP64) k_pack<DIM, double, double><<<pk, 256, 0, s>>>(g, s64, out, 1);
+    else k_pack<DIM, double, float><<<pk, 256, 0, s>>>(g, s32, out, 1);
+  };
+  switch (op) {
+    case FMG_OP_APPLY_A:
+      in(in0, x, xs, L.g);
+      if (prec == FMG_FP64) k_apply_A<DIM, double><<<grid, kBlock, 0, s>>>(L.g, x, t, L.scale);
+      else k_apply_A<DIM, float><<<grid, kBlock, 0, s>>>(L.g, xs, ts, (float)L.scale);
+      outp(t, ts, L.g);
+      break;
+    case FMG_OP_SMOOTH:
+      in(in0, x, xs, L.g);
+      in(in1, b, bs, L.g);
+      if (prec == FMG_FP64) k_smooth<DIM, double, false><<<grid, kBlock, 0, s>>>(L.g, x, b, t, omega / D, L.scale);
+      else k_smooth<DIM, float, false><<<grid, kBlock, 0, s>>>(L.g, xs, bs, ts, (float)(omega / D), (float)L.scale);
+      outp(t, ts, L.g);
+      break;
+    case FMG_OP_RESTRICT: {
+      if (k < 2) return FMG_E_INVALID;
+      const LevelInfo& C = p.lev[k - 1];
+      in(in0, x, xs, L.g);
+      in(in1, b, bs, L.g);
+      double* bc = h->at<double>(p.off_b[k - 1]);
+      float* bcs = prec == FMG_MIXED ? h->at<float>(p.off_bs[k - 1]) : nullptr;
+      if (prec == FMG_FP64)
+        k_resid_restrict<DIM, double><<<grid_of(C.g, DIM), kBlock, 0, s>>>(L.g, C.g, x, b, bc, L.scale);
+      else
+        k_resid_restrict<DIM, float><<<grid_of(C.g, DIM), kBlock, 0, s>>>(L.g, C.g, xs, bs, bcs, (float)L.scale);
+      outp(bc, bcs, C.g);
+      break;
+    }
+    case FMG_OP_PROLONG: {
+      if (k < 2) return FMG_E_INVALID;
+      const LevelInfo& C = p.lev[k - 1];
+      double* xc = h->at<double>(p.off_x[k - 1]);
+      float* xcs = prec == FMG_MIXED ? h->at<float>(p.off_xs[k - 1]) : nullptr;
+      in(in0, xc, xcs, C.g);
+      in(in1, x, xs, L.g);
+      if (prec == FMG_FP64) k_prolong<DIM, double, true><<<grid, kBlock, 0, s>>>(C.g, L.g, xc, x);
+      else k_prolong<DIM, float, true><<<grid, kBlock, 0, s>>>(C.g, L.g, xcs, xs);
+      outp(x, xs, L.g);
+      break;
+    }
+    case FMG_OP_COARSE:
+      if (k != 1) return FMG_E_INVALID;
+      in(in0, b, bs, L.g);
+      if (prec == FMG_FP64)
+        k_coarse_solve<DIM, double><<<1, 64, 0, s>>>(L.g, p.N1, h->at<double>(p.off_A1inv), b, x);
+      else
+        k_coarse_solve<DIM, float><<<1, 64, 0, s>>>(L.g, p.N1, h->at<float>(p.off_A1inv_f), bs, xs);
+      outp(x, xs, L.g);
+      break;
+    default:
+      return FMG_E_INVALID;
+  }
+  return hipGetLastError() == hipSuccess ? FMG_OK : FMG_E_HIP;
+}
+}  // namespace
+
+extern "C" int fmg_level_op(fmg_hierarchy* h, int op, int level, int precision, const double* in0, const double* in1,
+                 double* out, double omega, void* stream) {
+  if (!h || !in0 || !out || level < 1 || level > h->plan.nlev) return FMG_E_INVALID;
+  if ((op == FMG_OP_SMOOTH || op == FMG_OP_RESTRICT || op == FMG_OP_PROLONG) && !in1) return FMG_E_INVALID;
+  if (precision != FMG_FP64 && precision != FMG_MIXED) return FMG_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return h->plan.dim == 2 ? level_op_impl<2>(h, op, level, precision, in0, in1, out, omega, s)
+                          : level_op_impl<3>(h, op, level, precision, in0, in1, out, omega, s);
+}
