@@ -109,13 +109,15 @@ def profile_mode(B, H, P, g, torch):
 
 
 def roofline_from_profile(rows, finest):
-    """Dominant kernel class (most event time) and its finest-level launches."""
-    by_kernel = {}
+    """Dominant bandwidth kernel (most event time among the kernels that stream
+    nodal arrays) and its launches on the finest level."""
+    by_kernel, streaming = {}, {}
     for r in rows:
-        by_kernel.setdefault(r["kernel"], 0.0)
-        by_kernel[r["kernel"]] += r["ms"]
+        by_kernel[r["kernel"]] = by_kernel.get(r["kernel"], 0.0) + r["ms"]
+        if r["bytes"] > 0:
+            streaming[r["kernel"]] = streaming.get(r["kernel"], 0.0) + r["ms"]
     total = sum(by_kernel.values())
-    dominant = max(by_kernel, key=by_kernel.get)
+    dominant = max(streaming, key=streaming.get)
     fine = [r for r in rows if r["kernel"] == dominant and r["level"] == finest]
     if not fine or fine[0]["bytes"] <= 0:
         return None, by_kernel, total
@@ -190,6 +192,7 @@ def main():
             total_ms, rows = profile_mode(B, hier[name], P, g, torch)
             r, by_kernel, tot = roofline_from_profile(rows, P.n_levels)
             modes[name]["profile_event_ms_total"] = total_ms
+            modes[name]["profile_rows"] = sorted(rows, key=lambda r: -r["ms"])[:40]
             modes[name]["profile_ms_by_kernel"] = {k: round(v, 4) for k, v in
                                                    sorted(by_kernel.items(), key=lambda kv: -kv[1])}
             if name == "fp64":

@@ -100,6 +100,10 @@ typedef struct {
     int converged_max_steps;
     double converged_tol;
     int use_graph;      /* 1: capture the solve once into a hipGraph and replay */
+    int tail_max_nodes; /* V-cycle levels with at most this many interior nodes
+                           run together in one single-workgroup launch (0: off) */
+    int fuse_small_levels; /* 1: run Algorithm 3.2 on those small levels (all
+                              steps, incl. the Newton solves) in one launch */
 } fmg_options;
 
 typedef struct {

@@ -14,7 +14,7 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfmg.so")
+LIB_PATH = os.environ.get("FMG_LIBRARY", os.path.join(HERE, "libfmg.so"))
 
 FMG_MAX_LEVELS = 16
 FMG_OK, FMG_E_INVALID, FMG_E_UNSUPPORTED, FMG_E_WORKSPACE, FMG_E_HIP, FMG_E_NOT_CONVERGED, \
@@ -40,7 +40,8 @@ class Options(ctypes.Structure):
                 ("newton_max", ctypes.c_int), ("newton_tol", ctypes.c_double),
                 ("newton_passes", ctypes.c_int), ("mode", ctypes.c_int),
                 ("converged_max_steps", ctypes.c_int), ("converged_tol", ctypes.c_double),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("tail_max_nodes", ctypes.c_int),
+                ("fuse_small_levels", ctypes.c_int)]
 
 
 class ProblemC(ctypes.Structure):

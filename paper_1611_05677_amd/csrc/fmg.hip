@@ -14,6 +14,8 @@
 #include "fmg_device.h"
 #include "fmg_kernels_aug.h"
 #include "fmg_kernels_mg.h"
+#include "fmg_kernels_tail.h"
+#include "fmg_kernels_fmgtail.h"
 
 using namespace fmg;
 
@@ -43,12 +45,16 @@ struct LevelInfo {
 
 struct Plan {
   int dim, nH, nlev, N1;
+  int tail_top;            // deepest level handled by the single-workgroup tail (0: none)
   LevelInfo lev[FMG_MAX_LEVELS + 1];   // 1-based
   size_t off_state, off_report, off_slot, off_flag, off_norm_out, off_norm_part;
   size_t off_A1, off_A1inv, off_A1inv_f, off_pq, off_ps;
   size_t off_x[FMG_MAX_LEVELS + 1], off_b[FMG_MAX_LEVELS + 1], off_t[FMG_MAX_LEVELS + 1];
   size_t off_xs[FMG_MAX_LEVELS + 1], off_bs[FMG_MAX_LEVELS + 1], off_ts[FMG_MAX_LEVELS + 1];
   size_t off_uprev;
+  size_t off_fmgtail;
+  size_t off_ticket;
+  size_t off_cellsum;
   size_t norm_blocks;
   size_t total;
 };
@@ -65,6 +71,7 @@ int resolve(int dim, const fmg_options* in, Resolved& r) {
     return FMG_E_INVALID;
   if (o.mode != FMG_PAPER && o.mode != FMG_CONVERGED) return FMG_E_INVALID;
   if (o.mode == FMG_CONVERGED && (o.converged_max_steps < 1 || !(o.converged_tol > 0))) return FMG_E_INVALID;
+  if (o.tail_max_nodes < 0 || (o.fuse_small_levels != 0 && o.fuse_small_levels != 1)) return FMG_E_INVALID;
   r.o = o;
   r.smoother = o.smoother ? o.smoother : (dim == 2 ? FMG_JACOBI : FMG_CHEBYSHEV);
   if (r.smoother == FMG_JACOBI) {
@@ -128,6 +135,12 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p) {
       max_blocks = std::max(max_blocks, L.aug_blocks);
     }
   }
+  p.tail_top = 0;
+  if (ro.o.tail_max_nodes > 0 && ro.o.nu_pre <= kTailSweeps && ro.o.nu_post <= kTailSweeps)
+    for (int k = 2; k <= std::min(p.nlev, kTailLevels); ++k) {
+      const long long m = p.lev[k].g.n - 1;
+      if ((d == 2 ? m * m : m * m * m) <= ro.o.tail_max_nodes) p.tail_top = k;
+    }
   p.off_pq = take(sizeof(double) * max_blocks * Acc<3>::NQ);
   p.off_ps = take(sizeof(double) * max_blocks * Acc<3>::NS);
   const LevelInfo& F = p.lev[p.nlev];
@@ -146,6 +159,9 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p) {
     }
   }
   p.off_uprev = ro.o.mode == FMG_CONVERGED ? take(sizeof(double) * F.count) : 0;
+  p.off_fmgtail = take(sizeof(FmgTailParams));
+  p.off_ticket = take(sizeof(unsigned) * (1 + ncell));
+  p.off_cellsum = take(sizeof(double) * ncell * (Acc<3>::NQ + Acc<3>::NS));
   p.total = off;
   return FMG_OK;
 }
@@ -182,14 +198,16 @@ inline dim3 grid_of(const Grid& g, int dim) {
 enum KernelClass {
   KC_SMOOTH64, KC_SMOOTH64_ZERO, KC_RESTRICT64, KC_PROLONG64_ADD, KC_COARSE64,
   KC_SMOOTH32, KC_SMOOTH32_ZERO, KC_RESTRICT32, KC_PROLONG32_ADD, KC_COARSE32,
-  KC_PROLONG_FMG, KC_RHS, KC_RESID_F32, KC_ADD_F32, KC_AUG_SETUP, KC_AUG_QUAD, KC_NEWTON_STEP,
-  KC_NEWTON_FINISH, KC_AUG_UPDATE, KC_LEVEL1, KC_BEGIN, KC_OUTPUT, KC_END, KC_FILL, KC_COUNT
+  KC_TRANSITION, KC_RHS, KC_RESID_F32, KC_ADD_F32, KC_AUG_PASS0, KC_AUG_PASS, KC_OUTPUT_UPDATE,
+  KC_NEWTON_FINISH, KC_AUG_UPDATE, KC_LEVEL1, KC_BEGIN, KC_OUTPUT, KC_END, KC_FILL,
+  KC_VCYCLE_TAIL64, KC_VCYCLE_TAIL32, KC_FMG_TAIL, KC_COUNT
 };
 const char* const kKernelNames[KC_COUNT] = {
   "smooth_f64", "smooth_f64_from_zero", "resid_restrict_f64", "prolong_add_f64", "coarse_solve_f64",
   "smooth_f32", "smooth_f32_from_zero", "resid_restrict_f32", "prolong_add_f32", "coarse_solve_f32",
-  "prolong_fmg", "rhs", "resid_to_f32", "add_f32", "aug_setup", "aug_quad", "newton_step",
-  "newton_finish", "aug_update", "level1_newton", "begin_solve", "output", "end_solve", "fill"};
+  "transition", "rhs", "resid_to_f32", "add_f32", "aug_pass0_setup", "aug_pass", "output_update",
+  "newton_finish", "aug_update", "level1_newton", "begin_solve", "output", "end_solve", "fill",
+  "vcycle_tail_f64", "vcycle_tail_f32", "fmg_tail"};
 
 // Event pairs around launches (fmg_profile_solve only).
 struct Prof {
@@ -256,6 +274,28 @@ void canonical_roles(const fmg_hierarchy* h, Roles& r) {
 }
 
 template <int DIM, typename T>
+void fill_tail_args(const fmg_hierarchy* h, Roles& R, int top, TailArgs<T>& a) {
+  const Plan& p = h->plan;
+  std::memset(&a, 0, sizeof(a));
+  for (int j = 1; j <= top; ++j) {
+    a.x[j] = Sel<T>::x(R, j);
+    a.t[j] = Sel<T>::t(R, j);
+    a.b[j] = Sel<T>::b(h, j);
+    a.g[j] = p.lev[j].g;
+    a.scale[j] = (T)p.lev[j].scale;
+    const double Dj = 2.0 * DIM * p.lev[j].scale;
+    for (int i = 0; i < h->ro.o.nu_pre; ++i) a.wdpre[j][i] = (T)(h->ro.pre[i] / Dj);
+    for (int i = 0; i < h->ro.o.nu_post; ++i) a.wdpost[j][i] = (T)(h->ro.post[i] / Dj);
+  }
+  a.ainv = Sel<T>::ainv(h);
+  a.N1 = p.N1;
+  a.top = top;
+  a.npre = h->ro.o.nu_pre;
+  a.npost = h->ro.o.nu_post;
+  a.zero_top = 0;
+}
+
+template <int DIM, typename T>
 void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t st) {
   const Plan& p = h->plan;
   const LevelInfo& L = p.lev[k];
@@ -268,6 +308,20 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
   if (k == 1) {
     FMG_LAUNCH(h, st, KC_COARSE64 + kc, 1, N, 2 * s * N,
                k_coarse_solve<DIM, T><<<1, 64, 0, st>>>(L.g, p.N1, Sel<T>::ainv(h), b, x));
+    return;
+  }
+  if (k <= p.tail_top) {
+    TailArgs<T> a;
+    fill_tail_args<DIM, T>(h, R, k, a);
+    a.zero_top = zero_init ? 1 : 0;
+    double bytes = 0.0;
+    for (int j = 1; j <= k; ++j)
+      bytes += s * interior(p.lev[j].g, DIM) * (3.0 * (h->ro.o.nu_pre + h->ro.o.nu_post) + 4.0);
+    FMG_LAUNCH(h, st, KC_VCYCLE_TAIL64 + (Sel<T>::kc ? 1 : 0), k, N, bytes,
+               k_vcycle_tail<DIM, T><<<1, kTailThreads, 0, st>>>(a));
+    // mirror the kernel's role swaps
+    if ((h->ro.o.nu_pre + h->ro.o.nu_post) & 1)
+      for (int j = 2; j <= k; ++j) std::swap(Sel<T>::x(R, j), Sel<T>::t(R, j));
     return;
   }
   const dim3 grid = grid_of(L.g, DIM);
@@ -302,17 +356,35 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
   }
 }
 
+constexpr int kNewtonThreads = 1024;
+
 inline size_t newton_lds_bytes(const Plan& p, bool finisher) {
   const int ncell = p.dim == 2 ? p.nH * p.nH : p.nH * p.nH * p.nH;
   const int NQ = p.dim == 2 ? Acc<2>::NQ : Acc<3>::NQ;
-  const int ny = p.N1 + 1;
-  size_t doubles = (size_t)ncell * NQ + ny * ny + ny + 8 + (finisher ? 4 * NQ : 0);
-  return doubles * sizeof(double);
+  (void)finisher;
+  return sizeof(double) * (size_t)newton_kernel_lds_doubles(ncell, NQ, p.N1, kNewtonThreads);
+}
+
+inline size_t aug_pass_lds_bytes(const Plan& p) {
+  const int ncell = p.dim == 2 ? p.nH * p.nH : p.nH * p.nH * p.nH;
+  const int NQ = p.dim == 2 ? Acc<2>::NQ : Acc<3>::NQ;
+  return sizeof(double) * (size_t)newton_kernel_lds_doubles(ncell, NQ, p.N1, kBlock);
+}
+
+inline size_t fmg_tail_lds_bytes(const Plan& p) {
+  const int ncell = p.dim == 2 ? p.nH * p.nH : p.nH * p.nH * p.nH;
+  const int NQ = p.dim == 2 ? Acc<2>::NQ : Acc<3>::NQ;
+  const size_t aug = (size_t)ncell * NQ + newton_scratch_doubles(p.N1);
+  const size_t lev1 = level1_lds_doubles(p.N1);
+  return std::max(aug, lev1) * sizeof(double);
 }
 
 // One correction step (Algorithm 3.1) on level k; the current iterate is R.x[k].
+// rhs_ready: b_k was already formed (by the level transition).  defer_update:
+// leave u = Q w + alpha u~ to the consumer (next transition or the output).
 template <int DIM, int KIND>
-void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st) {
+void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bool rhs_ready,
+                     bool defer_update) {
   const Plan& p = h->plan;
   const LevelInfo& L = p.lev[k];
   const fmg_options& o = h->ro.o;
@@ -321,8 +393,9 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st) {
   const int nf1 = p.lev[p.nlev].g.n + 1, fs = 1 << (p.nlev - k);
   double* b = h->at<double>(p.off_b[k]);
   // step 1: linearised problem, m V-cycles from u^(l)
-  FMG_LAUNCH(h, st, KC_RHS, k, N, 24.0 * N,
-             k_rhs<DIM, KIND><<<grid, kBlock, 0, st>>>(L.g, h->slot(), nf1, fs, R.x[k], b, L.m));
+  if (!rhs_ready)
+    FMG_LAUNCH(h, st, KC_RHS, k, N, 24.0 * N,
+               k_rhs<DIM, KIND><<<grid, kBlock, 0, st>>>(L.g, h->slot(), nf1, fs, R.x[k], b, L.m));
   for (int c = 0; c < o.m_vcycles; ++c) {
     if (o.precision == FMG_FP64) {
       vcycle<DIM, double>(h, R, k, false, st);
@@ -339,23 +412,25 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st) {
   // step 2: semilinear problem on V_H + span{u~}
   double* pq = h->at<double>(p.off_pq);
   double* ps = h->at<double>(p.off_ps);
+  unsigned* ticket = h->at<unsigned>(p.off_ticket);
+  double* cellsum = h->at<double>(p.off_cellsum);
   const double* A1 = h->at<double>(p.off_A1);
-  FMG_LAUNCH(h, st, KC_AUG_SETUP, k, N, 16.0 * N,
-             k_aug_setup<DIM><<<L.aug_blocks, kBlock, 0, st>>>(L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale,
-                                                               ps, h->ns(), k));
-  const size_t lds = newton_lds_bytes(p, false);
-  for (int pass = 0; pass < o.newton_passes; ++pass) {
-    FMG_LAUNCH(h, st, KC_AUG_QUAD, k, N, 8.0 * N,
-               k_aug_quad<DIM, KIND><<<L.aug_blocks, kBlock, 0, st>>>(L.g, L.aug, R.x[k], h->slot(), h->ns(), pq));
-    FMG_LAUNCH(h, st, KC_NEWTON_STEP, k, N, 0.0,
-               k_newton_step<DIM><<<1, 256, lds, st>>>(L.aug, pq, ps, A1, L.m, h->ns(), h->rep(), o.newton_max,
-                                                       o.newton_tol));
-  }
+  const size_t lds = aug_pass_lds_bytes(p);
+  FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
+             (k_aug_pass<DIM, KIND, true><<<L.aug_blocks, kBlock, lds, st>>>(
+                 L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, cellsum,
+                 ticket, k, o.newton_max, o.newton_tol)));
+  for (int pass = 1; pass < o.newton_passes; ++pass)
+    FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
+               (k_aug_pass<DIM, KIND, false><<<L.aug_blocks, kBlock, lds, st>>>(
+                   L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, cellsum,
+                   ticket, k, o.newton_max, o.newton_tol)));
   FMG_LAUNCH(h, st, KC_NEWTON_FINISH, k, N, 0.0,
-             k_newton_finish<DIM, KIND><<<1, 256, newton_lds_bytes(p, true), st>>>(
+             k_newton_finish<DIM, KIND><<<1, kNewtonThreads, newton_lds_bytes(p, true), st>>>(
                  L.g, L.aug, R.x[k], h->slot(), A1, L.m, h->ns(), h->rep(), o.newton_max, o.newton_tol));
-  FMG_LAUNCH(h, st, KC_AUG_UPDATE, k, N, 16.0 * N,
-             k_aug_update<DIM><<<grid, kBlock, 0, st>>>(L.g, L.aug, h->ns(), R.x[k]));
+  if (!defer_update)
+    FMG_LAUNCH(h, st, KC_AUG_UPDATE, k, N, 16.0 * N,
+               k_aug_update<DIM><<<grid, kBlock, 0, st>>>(L.g, L.aug, h->ns(), R.x[k]));
 }
 
 template <int DIM, int KIND>
@@ -364,33 +439,68 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
   const fmg_options& o = h->ro.o;
   const int nf1 = p.lev[p.nlev].g.n + 1;
   FMG_LAUNCH(h, st, KC_BEGIN, 0, 0, 0.0, k_begin_solve<<<1, 64, 0, st>>>(h->rep(), p.nlev, h->flag()));
-  // Algorithm 3.2, step 1: exact semilinear solve on V_{h_1}
-  const LevelInfo& L1 = p.lev[1];
-  const size_t lds1 = sizeof(double) * ((size_t)p.N1 * p.N1 + 6 * p.N1 + 4);
-  FMG_LAUNCH(h, st, KC_LEVEL1, 1, p.N1, 0.0,
-             k_level1_newton<DIM, KIND><<<1, 256, lds1, st>>>(L1.g, p.N1, h->at<double>(p.off_A1), L1.m,
-                                                              h->slot(), nf1, 1 << (p.nlev - 1), R.x[1], h->rep(),
-                                                              o.newton_max, o.newton_tol));
-  // step 2: levels k = 2..n
-  for (int k = 2; k <= p.nlev; ++k) {
+  int first = 2;
+  if (p.tail_top >= 2 && o.fuse_small_levels) {
+    // Algorithm 3.2 on levels 1..T in one single-workgroup launch
+    const int T = std::min(p.tail_top, p.nlev);
+    const size_t lds = fmg_tail_lds_bytes(p);
+    const FmgTailParams* P = h->at<FmgTailParams>(p.off_fmgtail);
+    if (o.precision == FMG_FP64)
+      FMG_LAUNCH(h, st, KC_FMG_TAIL, T, interior(p.lev[T].g, DIM), 0.0,
+                 (k_fmg_tail<DIM, KIND, false><<<1, kTailThreads, lds, st>>>(P)));
+    else
+      FMG_LAUNCH(h, st, KC_FMG_TAIL, T, interior(p.lev[T].g, DIM), 0.0,
+                 (k_fmg_tail<DIM, KIND, true><<<1, kTailThreads, lds, st>>>(P)));
+    // mirror the role swaps of the V-cycles inside
+    const bool odd = (o.nu_pre + o.nu_post) & 1;
+    for (int k = 2; k <= T; ++k)
+      for (int c = 0; c < o.p_steps * o.m_vcycles; ++c)
+        if (odd)
+          for (int j = 2; j <= k; ++j) {
+            if (o.precision == FMG_FP64) std::swap(R.x[j], R.t[j]);
+            else std::swap(R.xs[j], R.ts[j]);
+          }
+    first = T + 1;
+  } else {
+    // Algorithm 3.2, step 1: exact semilinear solve on V_{h_1}
+    const LevelInfo& L1 = p.lev[1];
+    const size_t lds1 = sizeof(double) * (size_t)level1_lds_doubles(p.N1);
+    FMG_LAUNCH(h, st, KC_LEVEL1, 1, p.N1, 0.0,
+               k_level1_newton<DIM, KIND><<<1, 256, lds1, st>>>(L1.g, p.N1, h->at<double>(p.off_A1), L1.m,
+                                                                h->slot(), nf1, 1 << (p.nlev - 1), R.x[1],
+                                                                h->rep(), o.newton_max, o.newton_tol));
+  }
+  // step 2: levels k = first..n
+  bool pending_aug = false;   // last update of level k-1 left to the transition
+  for (int k = first; k <= p.nlev; ++k) {
     const LevelInfo& L = p.lev[k];
+    const LevelInfo& C = p.lev[k - 1];
     const long long N = interior(L.g, DIM);
-    FMG_LAUNCH(h, st, KC_PROLONG_FMG, k, N, 8.0 * (N + interior(p.lev[k - 1].g, DIM)),
-               k_prolong<DIM, double, false><<<grid_of(L.g, DIM), kBlock, 0, st>>>(p.lev[k - 1].g, L.g,
-                                                                                  R.x[k - 1], R.x[k]));
-    for (int l = 0; l < o.p_steps; ++l) correction_step<DIM, KIND>(h, R, k, st);
+    FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (3 * N + interior(C.g, DIM)),
+               k_transition<DIM, KIND><<<grid_of(L.g, DIM), kBlock, 0, st>>>(
+                   C.g, C.aug, h->ns(), R.x[k - 1], pending_aug ? 1 : 0, L.g, R.x[k], h->at<double>(p.off_b[k]),
+                   h->slot(), nf1, 1 << (p.nlev - k), L.m));
+    for (int l = 0; l < o.p_steps; ++l) {
+      const bool defer = l == o.p_steps - 1 && (k < p.nlev || finish);
+      correction_step<DIM, KIND>(h, R, k, st, l == 0, defer);
+      pending_aug = defer;
+    }
   }
   if (finish) {
     const LevelInfo& F = p.lev[p.nlev];
     const double nodes = DIM == 2 ? (double)(F.g.n + 1) * (F.g.n + 1) : (double)(F.g.n + 1) * (F.g.n + 1) * (F.g.n + 1);
-    FMG_LAUNCH(h, st, KC_OUTPUT, p.nlev, interior(F.g, DIM), 16.0 * nodes,
-               k_output<DIM><<<1024, 256, 0, st>>>(F.g, R.x[p.nlev], h->slot(), h->flag()));
+    if (pending_aug)
+      FMG_LAUNCH(h, st, KC_OUTPUT_UPDATE, p.nlev, interior(F.g, DIM), 16.0 * nodes,
+                 k_output_update<DIM><<<1024, 256, 0, st>>>(F.g, F.aug, h->ns(), R.x[p.nlev], h->slot(), h->flag()));
+    else
+      FMG_LAUNCH(h, st, KC_OUTPUT, p.nlev, interior(F.g, DIM), 16.0 * nodes,
+                 k_output<DIM><<<1024, 256, 0, st>>>(F.g, R.x[p.nlev], h->slot(), h->flag()));
     FMG_LAUNCH(h, st, KC_END, 0, 0, 0.0, k_end_solve<<<1, 64, 0, st>>>(h->rep(), h->flag(), h->slot()));
   }
 }
 
 typedef void (*record_fn)(const fmg_hierarchy*, Roles&, bool, hipStream_t);
-typedef void (*step_fn)(const fmg_hierarchy*, Roles&, int, hipStream_t);
+typedef void (*step_fn)(const fmg_hierarchy*, Roles&, int, hipStream_t, bool, bool);
 
 template <int DIM>
 record_fn pick_record(int kind) {
@@ -491,6 +601,8 @@ void fmg_default_options(int dim, fmg_options* o) {
   o->converged_max_steps = 40;
   o->converged_tol = 1e-13;
   o->use_graph = 1;
+  o->tail_max_nodes = 4096;
+  o->fuse_small_levels = 0;
   (void)dim;
 }
 
@@ -534,6 +646,35 @@ int fmg_create_hierarchy(const fmg_mesh_desc* mesh, const fmg_options* opts, voi
     }
   }
   if (p.off_uprev) k_fill<double><<<1024, 256, 0, s>>>(h->at<double>(p.off_uprev), p.lev[p.nlev].count, 0.0);
+  k_fill<unsigned><<<1, 64, 0, s>>>(h->at<unsigned>(p.off_ticket), 1 + (p.dim == 2 ? p.nH * p.nH : p.nH * p.nH * p.nH), 0u);
+  if (p.tail_top >= 2 && ro.o.fuse_small_levels) {
+    // parameters of the single-workgroup FMG launch over levels 1..T (canonical roles)
+    FmgTailParams P;
+    std::memset(&P, 0, sizeof(P));
+    Roles R;
+    canonical_roles(h, R);
+    const int T = std::min(p.tail_top, p.nlev);
+    if (p.dim == 2) { fill_tail_args<2, double>(h, R, T, P.v64); if (R.xs[1]) fill_tail_args<2, float>(h, R, T, P.v32); }
+    else { fill_tail_args<3, double>(h, R, T, P.v64); if (R.xs[1]) fill_tail_args<3, float>(h, R, T, P.v32); }
+    for (int k = 1; k <= T; ++k) { P.aug[k] = p.lev[k].aug; P.m[k] = p.lev[k].m; }
+    P.A1 = h->at<double>(p.off_A1);
+    P.ns = h->ns();
+    P.rep = h->rep();
+    P.slot = h->slot();
+    P.top = T;
+    P.nlev = p.nlev;
+    P.nf1 = p.lev[p.nlev].g.n + 1;
+    P.m_vcycles = ro.o.m_vcycles;
+    P.p_steps = ro.o.p_steps;
+    P.newton_max = ro.o.newton_max;
+    P.newton_tol = ro.o.newton_tol;
+    if (hipMemcpyAsync(h->at<FmgTailParams>(p.off_fmgtail), &P, sizeof(P), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      (void)hipStreamDestroy(h->cap_stream);
+      delete h;
+      return FMG_E_HIP;
+    }
+  }
   std::vector<double> A, Ainv;
   build_level1(p, A, Ainv);
   std::vector<float> Ainv_f(Ainv.begin(), Ainv.end());
@@ -593,7 +734,7 @@ int fmg_solve(fmg_hierarchy* h, const fmg_problem* prob, double* d_u_out, fmg_re
       const dim3 grid = grid_of(F.g, p.dim);
       if (p.dim == 2) k_copy_interior<2, double><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev);
       else k_copy_interior<3, double><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev);
-      step(h, R, k, s);
+      step(h, R, k, s, false, false);
       if (p.dim == 2) k_diff_norm_partials<2><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev, npart);
       else k_diff_norm_partials<3><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev, npart);
       k_sum_pairs<<<1, kBlock, 0, s>>>(npart, p.norm_blocks, nout);

@@ -12,7 +12,7 @@
 
 namespace fmg {
 
-constexpr int kMaxY = 128;          // max unknowns of the augmented problem (N_1 + 1)
+constexpr int kMaxY = 64;           // max unknowns of the augmented problem (N_1 + 1)
 constexpr int kBlock = 256;         // threads per block of the grid kernels
 
 struct Grid {

@@ -106,28 +106,16 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Grid g, const ProblemSlot* __res
   b[c] = m * (gv - NL<KIND>::f(u[c], slot->param));
 }
 
-// ---------------------------------------------------------------------------
-// Setup pass (once per correction step): per coarse cell
+// Per-cell setup sums for one block's node range:
 //   sum phi_a (A u~)_j, sum u~_j (A u~)_j, sum phi_a g_j, sum u~_j g_j.
-// Block 0 also resets the Newton state to y = (0, ..., 0, 1), i.e. z = u~.
-// ---------------------------------------------------------------------------
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_aug_setup(Grid g, AugShape s, const double* __restrict__ ut,
-                                                      const ProblemSlot* __restrict__ slot, int nf1, int fs,
-                                                      double scale, double* __restrict__ partials,
-                                                      NewtonState* __restrict__ ns, int level) {
+__device__ __forceinline__ void setup_accumulate(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                                 const double* __restrict__ gl, int nf1, int fs, double scale,
+                                                 int cell, int t0, int t1, int tid, int nthreads, double* acc) {
   using AC = Acc<DIM>;
-  __shared__ double lds[(kBlock / 64) * AC::NS];
-  const int cell = blockIdx.x >> s.bpc_log, chunk = blockIdx.x & ((1 << s.bpc_log) - 1);
   int cx, cy, cz;
   cell_of<DIM>(cell, s.nH, cx, cy, cz);
-  double acc[AC::NS];
-#pragma unroll
-  for (int q = 0; q < AC::NS; ++q) acc[q] = 0.0;
-  const int t0 = chunk << s.npb_log;
-  const double* __restrict__ gl = slot->g;
-  for_cell_nodes<DIM>(g, s, cx, cy, cz, t0, t0 + (1 << s.npb_log), threadIdx.x, blockDim.x,
-                      [&](int c, const double* tl, int i, int j, int l) {
+  for_cell_nodes<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, [&](int c, const double* tl, int i, int j, int l) {
     double phi[AC::NV];
     kuhn_phi<DIM>(tl, phi);
     const double u = ut[c];
@@ -141,16 +129,16 @@ __global__ void __launch_bounds__(kBlock) k_aug_setup(Grid g, AugShape s, const 
     acc[AC::S_C] += u * au;
     acc[AC::S_GU] += u * gv;
   });
-  const double tot = block_sum_many<AC::NS>(acc, lds);
-  if (threadIdx.x < AC::NS) partials[(size_t)blockIdx.x * AC::NS + threadIdx.x] = tot;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    for (int q = 0; q < s.N1; ++q) { ns->y[q] = 0.0; ns->ytry[q] = 0.0; ns->d[q] = 0.0; }
-    ns->y[s.N1] = 1.0;
-    ns->ytry[s.N1] = 1.0;
-    ns->d[s.N1] = 0.0;
-    ns->iter = 0; ns->passes = 0; ns->halvings = 0; ns->done = 0; ns->ok = 0; ns->level = level;
-    ns->t = 1.0; ns->E = 0.0; ns->Escale = 0.0; ns->slope = 0.0;
-  }
+}
+
+// Newton state at the start of an augmented solve: y = (0, ..., 0, 1), i.e. z = u~.
+__device__ __forceinline__ void newton_state_reset(NewtonState* ns, int N1, int level) {
+  for (int q = 0; q < N1; ++q) { ns->y[q] = 0.0; ns->ytry[q] = 0.0; ns->d[q] = 0.0; }
+  ns->y[N1] = 1.0;
+  ns->ytry[N1] = 1.0;
+  ns->d[N1] = 0.0;
+  ns->iter = 0; ns->passes = 0; ns->halvings = 0; ns->done = 0; ns->ok = 0; ns->level = level;
+  ns->t = 1.0; ns->E = 0.0; ns->Escale = 0.0; ns->slope = 0.0;
 }
 
 // Per-cell quadrature sums at z = Q w + alpha u~ for one block's node range.
@@ -193,238 +181,326 @@ __device__ __forceinline__ void quad_accumulate(const Grid& g, const AugShape& s
   });
 }
 
-template <int DIM, int KIND>
-__global__ void __launch_bounds__(kBlock) k_aug_quad(Grid g, AugShape s, const double* __restrict__ ut,
-                                                     const ProblemSlot* __restrict__ slot,
-                                                     const NewtonState* __restrict__ ns,
-                                                     double* __restrict__ partials) {
-  using AC = Acc<DIM>;
-  if (ns->done) return;
-  __shared__ double lds[(kBlock / 64) * AC::NQ];
-  const int cell = blockIdx.x >> s.bpc_log, chunk = blockIdx.x & ((1 << s.bpc_log) - 1);
-  double acc[AC::NQ];
-#pragma unroll
-  for (int q = 0; q < AC::NQ; ++q) acc[q] = 0.0;
-  const int t0 = chunk << s.npb_log;
-  quad_accumulate<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cell, t0, t0 + (1 << s.npb_log), threadIdx.x,
-                             blockDim.x, acc);
-  const double tot = block_sum_many<AC::NQ>(acc, lds);
-  if (threadIdx.x < AC::NQ) partials[(size_t)blockIdx.x * AC::NQ + threadIdx.x] = tot;
+// ---------------------------------------------------------------------------
+// Small dense linear algebra in LDS, executed by the first wavefront of the
+// block (n <= 64 = wave size).  Lanes of one wavefront issue their LDS
+// operations in program order; wave_sync() keeps the compiler from moving
+// LDS accesses across the phase boundaries.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
-
-// ---------------------------------------------------------------------------
-// Small dense linear algebra in LDS, one block.
-// ---------------------------------------------------------------------------
 
 // Right-looking Cholesky steps k = 0..kend-1 of the n x n matrix L (row-major,
-// lower part used).  After kend = n-1 steps, L[n-1][n-1] is the Schur
-// complement of the leading block.
-__device__ inline void chol_steps(double* L, int n, int kend) {
+// lower part; lanes own rows).  After kend = n-1 steps, L[n-1][n-1] holds the
+// Schur complement of the leading block.  col: LDS scratch of n doubles
+// holding the current column (kept apart from L so that the row updates of a
+// lane can be issued without waiting on one another).  rdiag receives the
+// reciprocals of the computed diagonal entries.
+__device__ __forceinline__ void chol_steps_wave(double* __restrict__ L, double* __restrict__ col,
+                                       double* __restrict__ rdiag, int n, int kend) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
   for (int k = 0; k < kend; ++k) {
-    __syncthreads();
+    wave_sync();
     const double s = sqrt(L[k * n + k]);
-    __syncthreads();
-    if (threadIdx.x == 0) L[k * n + k] = s;
-    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) L[i * n + k] /= s;
-    __syncthreads();
-    const int m = n - k - 1;
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-      const int i = k + 1 + idx / m, j = k + 1 + idx % m;
-      if (j <= i) L[i * n + j] -= L[i * n + k] * L[j * n + k];
-    }
+    const double rs = 1.0 / s;
+    double lik = 0.0;
+    if (lane > k && lane < n) lik = L[lane * n + k] * rs;
+    if (lane > k && lane < n) { col[lane] = lik; L[lane * n + k] = lik; }
+    if (lane == k) { L[k * n + k] = s; rdiag[k] = rs; }
+    wave_sync();
+    if (lane > k && lane < n)
+      for (int j = k + 1; j <= lane; ++j) L[lane * n + j] -= lik * col[j];
   }
-  __syncthreads();
+  wave_sync();
 }
 
-// Solve L L^T x = rhs for the leading nn rows (thread 0; nn <= 64).
-__device__ inline void chol_solve_serial(const double* L, int n, int nn, double* x) {
-  if (threadIdx.x != 0) return;
-  for (int i = 0; i < nn; ++i) {
-    double s = x[i];
-    for (int j = 0; j < i; ++j) s -= L[i * n + j] * x[j];
-    x[i] = s / L[i * n + i];
+// Solve L L^T x = x for the leading nn rows (nn <= 64), lanes own entries;
+// rdiag holds 1/L[j][j].
+__device__ __forceinline__ void chol_solve_wave(const double* __restrict__ L, const double* __restrict__ rdiag, int n,
+                                       int nn, double* __restrict__ x) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  wave_sync();
+  double v = lane < nn ? x[lane] : 0.0;
+  for (int j = 0; j < nn; ++j) {
+    const double lij = (lane > j && lane < nn) ? L[lane * n + j] : 0.0;
+    if (lane == j) v *= rdiag[j];
+    const double xj = __shfl(v, j, 64);
+    v -= lij * xj;
   }
-  for (int i = nn - 1; i >= 0; --i) {
-    double s = x[i];
-    for (int j = i + 1; j < nn; ++j) s -= L[j * n + i] * x[j];
-    x[i] = s / L[i * n + i];
+  for (int j = nn - 1; j >= 0; --j) {
+    const double lji = lane < j ? L[j * n + lane] : 0.0;
+    if (lane == j) v *= rdiag[j];
+    const double xj = __shfl(v, j, 64);
+    v -= lji * xj;
   }
+  if (lane < nn) x[lane] = v;
+  wave_sync();
+}
+
+// Parallel copy of a trivially copyable struct (multiple of 8 bytes) by the
+// lanes of one wavefront.
+template <typename S>
+__device__ __forceinline__ void wave_copy(S* dst, const S* src) {
+  static_assert(sizeof(S) % 8 == 0, "8-byte words");
+  const double* a = reinterpret_cast<const double*>(src);
+  double* b = reinterpret_cast<double*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(S) / 8); i += 64) b[i] = a[i];
+}
+
+__device__ __forceinline__ double wave_allsum(double v) { return __shfl(wave_sum(v), 0, 64); }
+__device__ __forceinline__ double wave_allmax(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return __shfl(v, 0, 64);
+}
+
+// LDS doubles newton_core needs besides the per-cell sums.
+__host__ __device__ constexpr int newton_scratch_doubles(int N1) {
+  return (int)(sizeof(NewtonState) / 8) + N1 * N1 + (N1 + 1) * (N1 + 1) + 5 * (N1 + 1) + 8;
+}
+
+// Pair index p with {a, b} = {Pairs::a(p), Pairs::b(p)} for comparable cell
+// vertices a, b (one a subset of the other), or -1.
+template <int DIM>
+__device__ __forceinline__ int pair_index(int a, int b) {
+  if (a > b) { const int t = a; a = b; b = t; }
+  if ((a & b) != a) return -1;
+  for (int p = 0; p < Pairs<DIM>::N; ++p)
+    if (Pairs<DIM>::a(p) == a && Pairs<DIM>::b(p) == b) return p;
+  return -1;
+}
+
+// Coarse interior node A (dense index) -> grid coordinates (1-based).
+template <int DIM>
+__device__ __forceinline__ void coarse_coords(int nH, int A, int& x, int& y, int& z) {
+  const int m = nH - 1;
+  x = 1 + A % m;
+  y = 1 + (A / m) % m;
+  z = DIM == 3 ? 1 + A / (m * m) : 0;
 }
 
 // ---------------------------------------------------------------------------
-// Newton step of the augmented problem (one block).  Inputs: per-cell
-// quadrature sums `cs` (LDS, ncell x NQ) at the point ns->ytry.  Implements
-// damped Newton with Armijo backtracking on E as a state machine, one
-// evaluation per call: accept or halve the trial step, test convergence
-// (|t d|_inf <= tol max(1, |y|_inf)), otherwise compute the next direction
-// d = -J^{-1} R (dropping the u~ direction when its Schur complement is
-// <= 1e-12 of J_uu) and the next trial point.
-// LDS scratch `sm`: J (ny*ny) | R (ny) | 8 scalars.
+// Newton step of the augmented problem, executed by the first wavefront of
+// the block (the others return at once; the caller synchronises the block
+// before and after).  Inputs: per-cell quadrature sums `cs` (LDS, ncell x NQ)
+// at the point ns->ytry.  Damped Newton with Armijo backtracking on E as a
+// state machine, one evaluation per call: accept or halve the trial step,
+// test convergence (|t d|_inf <= tol max(1, |y|_inf)), otherwise compute the
+// next direction d = -J^{-1} R (dropping the u~ direction when its Schur
+// complement is <= 1e-12 of J_uu) and the next trial point.  Every entry of
+// J and R gathers the contributions of the (at most 2^d) coarse cells that
+// touch it, cells in ascending order.
+// LDS scratch `sm` (newton_scratch_doubles): state | A_1 | J | R | A_1 w | col | rdiag | 8.
 // ---------------------------------------------------------------------------
 template <int DIM>
-__device__ void newton_core(const AugShape& s, const double* cs, const double* __restrict__ A1, double m,
-                            NewtonState* ns, fmg_report* rep, int newton_max, double tol, double* sm) {
+__device__ __forceinline__ void newton_core(const AugShape& s, const double* cs, const double* __restrict__ A1g, double m,
+                            NewtonState* nsg, fmg_report* rep, int newton_max, double tol, double* sm) {
+  if (threadIdx.x >= 64) return;
   using AC = Acc<DIM>;
-  using PR = Pairs<DIM>;
-  const int N1 = s.N1, ny = N1 + 1;
-  const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
-  double* J = sm;
+  const int lane = threadIdx.x;
+  const int N1 = s.N1, ny = N1 + 1, nH = s.nH;
+  const int ncell = DIM == 2 ? nH * nH : nH * nH * nH;
+  NewtonState* ns = reinterpret_cast<NewtonState*>(sm);
+  double* A1 = sm + sizeof(NewtonState) / 8;
+  double* J = A1 + N1 * N1;
   double* R = J + ny * ny;
-  double* scal = R + ny;   // [0]=Nu [1]=kuu [2]=sumF [3]=E [4]=Escale [5]=schur [6]=Juu [7]=flag
+  double* Aw = R + ny;
+  double* col = Aw + ny;
+  double* rdiag = col + ny;
+  double* dsave = rdiag + ny;
+  wave_copy(ns, nsg);
+  for (int idx = lane; idx < N1 * N1; idx += 64) A1[idx] = A1g[idx];
+  wave_sync();
   const double* y = ns->ytry;
   const double alpha = y[N1];
-
-  // J <- A_1, R <- A_1 w (+ terms below)
-  for (int idx = threadIdx.x; idx < ny * ny; idx += blockDim.x) J[idx] = 0.0;
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < N1 * N1; idx += blockDim.x) {
-    const int a = idx / N1, b = idx % N1;
-    J[a * ny + b] = A1[idx];
-  }
-  for (int a = threadIdx.x; a < N1; a += blockDim.x) {
+  // A_1 w, R_H, J_Hu (lanes over coarse nodes)
+  for (int A = lane; A < N1; A += 64) {
     double t = 0.0;
-    for (int b = 0; b < N1; ++b) t += A1[a * N1 + b] * y[b];
-    R[a] = t + alpha * ns->bH[a] - ns->GH[a];
+    for (int B = 0; B < N1; ++B) t += A1[A * N1 + B] * y[B];
+    Aw[A] = t;
+    int ax, ay, az;
+    coarse_coords<DIM>(nH, A, ax, ay, az);
+    double nh = 0.0, khu = 0.0;
+    for (int e = 0; e < AC::NV; ++e) {     // cells c = A - e containing A as vertex e
+      const int cx = ax - (e & 1), cy = ay - ((e >> 1) & 1), cz = DIM == 3 ? az - ((e >> 2) & 1) : 0;
+      const int cell = cx + nH * (cy + nH * cz);
+      nh += cs[cell * AC::NQ + AC::Q_NH + e];
+      khu += cs[cell * AC::NQ + AC::Q_KHU + e];
+    }
+    R[A] = t + alpha * ns->bH[A] - ns->GH[A] + m * nh;
+    J[A * ny + N1] = ns->bH[A] + m * khu;
+    J[N1 * ny + A] = J[A * ny + N1];
+  }
+  // J_HH = A_1 + m sum f'(z) phi_A phi_B (lanes over entries)
+  for (int idx = lane; idx < N1 * N1; idx += 64) {
+    const int A = idx / N1, B = idx % N1;
+    int ax, ay, az, bx, by, bz;
+    coarse_coords<DIM>(nH, A, ax, ay, az);
+    coarse_coords<DIM>(nH, B, bx, by, bz);
+    double k = 0.0;
+    if (abs(ax - bx) <= 1 && abs(ay - by) <= 1 && abs(az - bz) <= 1) {
+      for (int e = 0; e < AC::NV; ++e) {
+        const int cx = ax - (e & 1), cy = ay - ((e >> 1) & 1), cz = DIM == 3 ? az - ((e >> 2) & 1) : 0;
+        const int fx = bx - cx, fy = by - cy, fz = DIM == 3 ? bz - cz : 0;
+        if (fx < 0 || fx > 1 || fy < 0 || fy > 1 || fz < 0 || fz > 1) continue;
+        const int p = pair_index<DIM>(e, fx | (fy << 1) | (fz << 2));
+        if (p < 0) continue;
+        k += cs[(cx + nH * (cy + nH * cz)) * AC::NQ + AC::Q_K + p];
+      }
+    }
+    J[A * ny + B] = A1[idx] + m * k;
+  }
+  // scalars: sums over cells and over coarse nodes
+  double nu = 0.0, kuu = 0.0, sF = 0.0;
+  for (int c = lane; c < ncell; c += 64) {
+    nu += cs[c * AC::NQ + AC::Q_NU];
+    kuu += cs[c * AC::NQ + AC::Q_KUU];
+    sF += cs[c * AC::NQ + AC::Q_E];
+  }
+  double bw = 0.0, gw = 0.0, wAw = 0.0;
+  for (int A = lane; A < N1; A += 64) {
+    bw += ns->bH[A] * y[A];
+    gw += ns->GH[A] * y[A];
+    wAw += y[A] * Aw[A];
+  }
+  nu = wave_allsum(nu); kuu = wave_allsum(kuu); sF = wave_allsum(sF);
+  bw = wave_allsum(bw); gw = wave_allsum(gw); wAw = wave_allsum(wAw);
+  const double Juu = ns->c + m * kuu;
+  const double Ru = bw + alpha * ns->c + m * nu - ns->Gu;
+  if (lane == 0) { J[N1 * ny + N1] = Juu; R[N1] = Ru; }
+  const double t1 = 0.5 * wAw + alpha * bw + 0.5 * alpha * alpha * ns->c;
+  const double t2 = m * sF;
+  const double t3 = gw + alpha * ns->Gu;
+  const double Etry = t1 + t2 - t3, Stry = fabs(t1) + fabs(t2) + fabs(t3);
+  wave_sync();
+  // ---- state machine (decisions are uniform across the wavefront) ----
+  bool finite = isfinite(Etry);
+  for (int A = lane; A < ny; A += 64) finite = finite && isfinite(R[A]);
+  finite = __all(finite);
+  const int passes = ns->passes, iter = ns->iter;
+  const double E = ns->E, Escale = ns->Escale, slope0 = ns->slope, t = ns->t;
+  int newdir = 0, done = 0, ok = 0, halve = 0;
+  if (!finite) {
+    done = 1;
+  } else if (passes == 0) {
+    newdir = 1;
+  } else if (Etry <= E + kArmijo * t * slope0 + kEnergyRounding * fmax(Escale, Stry)) {
+    double stepmax = 0.0, ymax = 0.0;
+    for (int A = lane; A < ny; A += 64) {
+      stepmax = fmax(stepmax, fabs(t * ns->d[A]));
+      ymax = fmax(ymax, fabs(y[A]));
+    }
+    stepmax = wave_allmax(stepmax);
+    ymax = wave_allmax(ymax);
+    if (stepmax <= tol * fmax(1.0, ymax)) { done = 1; ok = 1; }
+    else newdir = 1;
+  } else {
+    halve = 1;
+  }
+  const bool accept = finite && !halve;
+  if (newdir && iter >= newton_max) { done = 1; ok = 0; newdir = 0; }
+  wave_sync();
+  if (accept)
+    for (int A = lane; A < ny; A += 64) ns->y[A] = y[A];
+  if (halve) {
+    const double tn = 0.5 * t;
+    for (int A = lane; A < ny; A += 64) ns->ytry[A] = ns->y[A] + tn * ns->d[A];
+  }
+  wave_sync();
+  if (lane == 0) {
+    if (accept) { ns->E = Etry; ns->Escale = Stry; }
+    if (halve) {
+      ns->t = 0.5 * t;
+      if (++ns->halvings > kMaxHalvings * newton_max) { done = 1; ok = 0; }
+    }
+    ns->passes = passes + 1;
+  }
+  done = __shfl(done, 0, 64);
+  ok = __shfl(ok, 0, 64);
+  if (lane == 0) {
+    ns->done = done;
+    ns->ok = ok;
+    if (done) {
+      const int k = ns->level - 1;
+      rep->newton_iters[k] = iter;
+      rep->newton_total[k] += iter;
+      rep->alpha[k] = ns->y[N1];
+      if (!finite) report_status(rep, FMG_E_NONFINITE);
+      else if (!ok) report_status(rep, FMG_E_NOT_CONVERGED);
+    }
+  }
+  if (newdir) {
+    // ---- new direction: J d = -R at the accepted point (y == ytry here) ----
+    for (int A = lane; A < ny; A += 64) dsave[A] = -R[A];
+    chol_steps_wave(J, col, rdiag, ny, N1);   // leading block factored, J[N1][N1] = Schur complement
+    const double schur = J[N1 * ny + N1];
+    const bool drop = !(schur > kSchurDrop * Juu);
+    if (!drop && lane == 0) { const double r = sqrt(schur); J[N1 * ny + N1] = r; rdiag[N1] = 1.0 / r; }
+    wave_sync();
+    chol_solve_wave(J, rdiag, ny, drop ? N1 : ny, dsave);
+    if (drop && lane == 0) dsave[N1] = 0.0;
+    wave_sync();
+    double sl = 0.0;
+    for (int A = lane; A < ny; A += 64) {
+      ns->d[A] = dsave[A];
+      sl += R[A] * dsave[A];
+      ns->ytry[A] = ns->y[A] + dsave[A];
+    }
+    sl = wave_allsum(sl);
+    if (lane == 0) { ns->slope = sl; ns->t = 1.0; ns->iter = iter + 1; }
+  }
+  wave_sync();
+  wave_copy(nsg, ns);
+}
+
+// Reduce the per-block partials of one pass into per-cell sums: every
+// (cell, accumulator) item is split into segments of consecutive blocks so
+// that all threads take part; segment sums are combined in a fixed order.
+// tmp: LDS of at least blockDim doubles.
+template <int NACC>
+__device__ __forceinline__ void cell_sums_from_partials(const double* __restrict__ partials, int ncell, int bpc,
+                                               double* cs, double* tmp) {
+  const int W = ncell * NACC;
+  const int S = max(1, min(bpc, (int)blockDim.x / W));
+  const int seg = (bpc + S - 1) / S;
+  for (int idx = threadIdx.x; idx < W * S; idx += blockDim.x) {
+    const int item = idx % W, sg = idx / W;
+    const int cell = item / NACC, q = item % NACC;
+    const int b0 = sg * seg, b1 = min(bpc, b0 + seg);
+    const double* p = partials + ((size_t)cell * bpc) * NACC + q;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    int b = b0;
+    for (; b + 3 < b1; b += 4) {
+      t0 += p[(size_t)b * NACC];
+      t1 += p[(size_t)(b + 1) * NACC];
+      t2 += p[(size_t)(b + 2) * NACC];
+      t3 += p[(size_t)(b + 3) * NACC];
+    }
+    for (; b < b1; ++b) t0 += p[(size_t)b * NACC];
+    const double t = (t0 + t1) + (t2 + t3);
+    if (S == 1) cs[item] = t;
+    else tmp[sg * W + item] = t;
   }
   __syncthreads();
-  // scatter the per-cell sums, cells grouped in 2^d colours (cells of one
-  // colour share no vertex), colours in a fixed order
-  for (int colour = 0; colour < (1 << DIM); ++colour) {
-    const int per = AC::NV + PR::N;
-    for (int idx = threadIdx.x; idx < ncell * per; idx += blockDim.x) {
-      const int cell = idx / per, item = idx % per;
-      int cx, cy, cz;
-      cell_of<DIM>(cell, s.nH, cx, cy, cz);
-      const int col = (cx & 1) | ((cy & 1) << 1) | (DIM == 3 ? (cz & 1) << 2 : 0);
-      if (col != colour) continue;
-      const double* c = cs + cell * AC::NQ;
-      if (item < AC::NV) {
-        const int A = coarse_vertex<DIM>(s.nH, cx, cy, cz, item);
-        if (A >= 0) {
-          R[A] += m * c[AC::Q_NH + item];
-          J[A * ny + N1] += m * c[AC::Q_KHU + item];
-        }
-      } else {
-        const int p = item - AC::NV;
-        const int A = coarse_vertex<DIM>(s.nH, cx, cy, cz, PR::a(p));
-        const int B = coarse_vertex<DIM>(s.nH, cx, cy, cz, PR::b(p));
-        if (A >= 0 && B >= 0) {
-          const double v = m * c[AC::Q_K + p];
-          J[A * ny + B] += v;
-          if (A != B) J[B * ny + A] += v;
-        }
-      }
+  if (S > 1) {
+    for (int item = threadIdx.x; item < W; item += blockDim.x) {
+      double t = 0.0;
+      for (int sg = 0; sg < S; ++sg) t += tmp[sg * W + item];
+      cs[item] = t;
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    double Nu = 0.0, kuu = 0.0, sF = 0.0;
-    for (int cell = 0; cell < ncell; ++cell) {
-      Nu += cs[cell * AC::NQ + AC::Q_NU];
-      kuu += cs[cell * AC::NQ + AC::Q_KUU];
-      sF += cs[cell * AC::NQ + AC::Q_E];
-    }
-    double bw = 0.0, gw = 0.0, wAw = 0.0;
-    for (int a = 0; a < N1; ++a) {
-      bw += ns->bH[a] * y[a];
-      gw += ns->GH[a] * y[a];
-      double t = 0.0;
-      for (int b = 0; b < N1; ++b) t += A1[a * N1 + b] * y[b];
-      wAw += y[a] * t;
-    }
-    for (int a = 0; a < N1; ++a) {
-      J[a * ny + N1] += ns->bH[a];
-      J[N1 * ny + a] = J[a * ny + N1];
-    }
-    J[N1 * ny + N1] = ns->c + m * kuu;
-    R[N1] = bw + alpha * ns->c + m * Nu - ns->Gu;
-    const double t1 = 0.5 * wAw + alpha * bw + 0.5 * alpha * alpha * ns->c;
-    const double t2 = m * sF;
-    const double t3 = gw + alpha * ns->Gu;
-    scal[3] = t1 + t2 - t3;
-    scal[4] = fabs(t1) + fabs(t2) + fabs(t3);
-    scal[6] = J[N1 * ny + N1];
-    // ---- state machine: accept / reject the evaluated point ----
-    int newdir = 0;
-    const double Etry = scal[3], Stry = scal[4];
-    bool finite = isfinite(Etry);
-    for (int a = 0; a < ny; ++a) finite = finite && isfinite(R[a]);
-    if (!finite) {
-      ns->done = 1; ns->ok = 0;
-      report_status(rep, FMG_E_NONFINITE);
-    } else if (ns->passes == 0) {
-      ns->E = Etry; ns->Escale = Stry;
-      newdir = 1;
-    } else if (Etry <= ns->E + kArmijo * ns->t * ns->slope + kEnergyRounding * fmax(ns->Escale, Stry)) {
-      double stepmax = 0.0, ymax = 0.0;
-      for (int a = 0; a < ny; ++a) {
-        ns->y[a] = y[a];
-        stepmax = fmax(stepmax, fabs(ns->t * ns->d[a]));
-        ymax = fmax(ymax, fabs(y[a]));
-      }
-      ns->E = Etry; ns->Escale = Stry;
-      if (stepmax <= tol * fmax(1.0, ymax)) { ns->done = 1; ns->ok = 1; }
-      else newdir = 1;
-    } else {
-      ns->t *= 0.5;
-      if (++ns->halvings > kMaxHalvings * newton_max) { ns->done = 1; ns->ok = 0; }
-      for (int a = 0; a < ny; ++a) ns->ytry[a] = ns->y[a] + ns->t * ns->d[a];
-    }
-    if (newdir && ns->iter >= newton_max) { ns->done = 1; ns->ok = 0; newdir = 0; }
-    scal[7] = newdir;
-    ns->passes += 1;
-    if (ns->done) {
-      const int k = ns->level - 1;
-      rep->newton_iters[k] = ns->iter;
-      rep->newton_total[k] += ns->iter;
-      rep->alpha[k] = ns->y[N1];
-      if (!ns->ok) report_status(rep, FMG_E_NOT_CONVERGED);
-    }
-  }
-  __syncthreads();
-  if (scal[7] == 0.0) return;
-  // ---- new direction: J d = -R at the accepted point (y == ytry here) ----
-  chol_steps(J, ny, N1);                // leading block factored, J[N1][N1] = Schur complement
-  if (threadIdx.x == 0) {
-    const double schur = J[N1 * ny + N1];
-    const bool drop = !(schur > kSchurDrop * scal[6]);
-    scal[5] = drop ? 1.0 : 0.0;
-    if (!drop) J[N1 * ny + N1] = sqrt(schur);
-    for (int a = 0; a < ny; ++a) ns->d[a] = -R[a];
-    const int nn = drop ? N1 : ny;
-    chol_solve_serial(J, ny, nn, ns->d);
-    if (drop) ns->d[N1] = 0.0;
-    double slope = 0.0;
-    for (int a = 0; a < ny; ++a) slope += R[a] * ns->d[a];
-    ns->slope = slope;
-    ns->t = 1.0;
-    ns->iter += 1;
-    for (int a = 0; a < ny; ++a) ns->ytry[a] = ns->y[a] + ns->d[a];
-  }
-  __syncthreads();
 }
 
-// Reduce the per-block partials of one pass into per-cell sums (fixed order).
-template <int NACC>
-__device__ inline void cell_sums_from_partials(const double* __restrict__ partials, int ncell, int bpc,
-                                               double* cs) {
-  for (int idx = threadIdx.x; idx < ncell * NACC; idx += blockDim.x) {
-    const int cell = idx / NACC, q = idx % NACC;
-    double t = 0.0;
-    const double* p = partials + (size_t)cell * bpc * NACC + q;
-    for (int b = 0; b < bpc; ++b) t += p[(size_t)b * NACC];
-    cs[idx] = t;
-  }
-  __syncthreads();
-}
-
-// Fold the setup partials into Q^T A u~, u~^T A u~, Q^T M g, u~^T M g.
+// Fold per-cell setup sums into Q^T A u~, u~^T A u~, Q^T M g, u~^T M g.
 template <int DIM>
-__device__ inline void setup_reduce(const AugShape& s, const double* __restrict__ partials_s, double m,
-                                    NewtonState* ns, double* cs) {
+__device__ __forceinline__ void setup_scatter(const AugShape& s, const double* cs, double m, NewtonState* ns) {
   using AC = Acc<DIM>;
   const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
-  cell_sums_from_partials<AC::NS>(partials_s, ncell, 1 << s.bpc_log, cs);
   for (int a = threadIdx.x; a < s.N1; a += blockDim.x) { ns->bH[a] = 0.0; ns->GH[a] = 0.0; }
   __syncthreads();
   for (int colour = 0; colour < (1 << DIM); ++colour) {
@@ -453,61 +529,199 @@ __device__ inline void setup_reduce(const AugShape& s, const double* __restrict_
   __syncthreads();
 }
 
-// One Newton step from the partials of the preceding quadrature pass.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_newton_step(AugShape s, const double* __restrict__ partials_q,
-                                                     const double* __restrict__ partials_s,
-                                                     const double* __restrict__ A1, double m,
-                                                     NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
-                                                     int newton_max, double tol) {
+__device__ __forceinline__ void setup_reduce(const AugShape& s, const double* __restrict__ partials_s, double m,
+                                    NewtonState* ns, double* cs, double* tmp) {
   using AC = Acc<DIM>;
-  if (ns->done) return;
-  extern __shared__ double smem[];
   const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
-  double* cs = smem;                        // ncell * max(NQ, NS)
-  double* sm = smem + ncell * AC::NQ;
-  if (ns->passes == 0) setup_reduce<DIM>(s, partials_s, m, ns, cs);
-  cell_sums_from_partials<AC::NQ>(partials_q, ncell, 1 << s.bpc_log, cs);
+  cell_sums_from_partials<AC::NS>(partials_s, ncell, 1 << s.bpc_log, cs, tmp);
+  setup_scatter<DIM>(s, cs, m, ns);
+}
+
+// LDS doubles of k_newton_step / k_newton_finish for a block of `threads`.
+__host__ __device__ constexpr int newton_kernel_lds_doubles(int ncell, int NQ, int N1, int threads) {
+  return ncell * NQ + newton_scratch_doubles(N1) + threads;
+}
+
+// One pass of the augmented Newton iteration in one launch.  Every block
+// accumulates its share of the fine quadrature sums at ns->ytry (SETUP: the
+// setup sums plus the sums at y0 = (0,..,0,1), i.e. z = u~) and writes them
+// as per-block partials.  The last block of each coarse cell (atomic ticket,
+// release/acquire at device scope) reduces that cell's partials in a fixed
+// order into the cell sums; the last cell to finish performs the Newton step.
+// tickets: [0] global, [1 + cell] per cell; all zero between launches.
+// LDS: newton_kernel_lds_doubles(ncell, NQ, N1, blockDim).
+template <int DIM, int KIND, bool SETUP>
+__global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
+                                                     const ProblemSlot* __restrict__ slot, int nf1, int fs,
+                                                     double scale, double m, const double* __restrict__ A1,
+                                                     NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
+                                                     double* __restrict__ pq, double* __restrict__ ps,
+                                                     double* __restrict__ cellsum, unsigned* __restrict__ tickets,
+                                                     int level, int newton_max, double tol) {
+  using AC = Acc<DIM>;
+  constexpr int W = AC::NQ + (SETUP ? AC::NS : 0);
+  extern __shared__ double smem[];
+  __shared__ int is_last;
+  __shared__ double y0[kMaxY];
+  if (!SETUP && ns->done) return;
+  const int bpc = 1 << s.bpc_log;
+  const int cell = blockIdx.x >> s.bpc_log, chunk = blockIdx.x & (bpc - 1);
+  const int t0 = chunk << s.npb_log, t1 = t0 + (1 << s.npb_log);
+  const double* ytry = ns->ytry;
+  if (SETUP) {
+    for (int a = threadIdx.x; a <= s.N1; a += blockDim.x) y0[a] = a == s.N1 ? 1.0 : 0.0;
+    __syncthreads();
+    ytry = y0;
+    double acc[AC::NS];
+#pragma unroll
+    for (int q = 0; q < AC::NS; ++q) acc[q] = 0.0;
+    setup_accumulate<DIM>(g, s, ut, slot->g, nf1, fs, scale, cell, t0, t1, threadIdx.x, blockDim.x, acc);
+    const double tot = block_sum_many<AC::NS>(acc, smem);
+    if (threadIdx.x < AC::NS) ps[(size_t)blockIdx.x * AC::NS + threadIdx.x] = tot;
+  }
+  {
+    double acc[AC::NQ];
+#pragma unroll
+    for (int q = 0; q < AC::NQ; ++q) acc[q] = 0.0;
+    quad_accumulate<DIM, KIND>(g, s, ut, ytry, slot->param, cell, t0, t1, threadIdx.x, blockDim.x, acc);
+    const double tot = block_sum_many<AC::NQ>(acc, smem);
+    if (threadIdx.x < AC::NQ) pq[(size_t)blockIdx.x * AC::NQ + threadIdx.x] = tot;
+  }
+  // ---- level 1: the last block of this cell reduces the cell's partials ----
+  __syncthreads();
+  if (threadIdx.x == 0)
+    is_last = __hip_atomic_fetch_add(&tickets[1 + cell], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
+              (unsigned)(bpc - 1);
+  __syncthreads();
+  if (!is_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  {
+    const int S = max(1, min(bpc, (int)blockDim.x / W));
+    const int seg = (bpc + S - 1) / S;
+    double* tmp = smem;   // W * S <= blockDim doubles
+    for (int idx = threadIdx.x; idx < W * S; idx += blockDim.x) {
+      const int item = idx % W, sg = idx / W;
+      const bool quad = item < AC::NQ;
+      const int q = quad ? item : item - AC::NQ, n = quad ? AC::NQ : AC::NS;
+      const double* p = (quad ? pq : ps) + ((size_t)cell * bpc) * n + q;
+      const int b0 = sg * seg, b1 = min(bpc, b0 + seg);
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int b = b0;
+      for (; b + 3 < b1; b += 4) {
+        a0 += p[(size_t)b * n];
+        a1 += p[(size_t)(b + 1) * n];
+        a2 += p[(size_t)(b + 2) * n];
+        a3 += p[(size_t)(b + 3) * n];
+      }
+      for (; b < b1; ++b) a0 += p[(size_t)b * n];
+      tmp[sg * W + item] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+    for (int item = threadIdx.x; item < W; item += blockDim.x) {
+      double t = 0.0;
+      for (int sg = 0; sg < S; ++sg) t += tmp[sg * W + item];
+      cellsum[(size_t)cell * (AC::NQ + AC::NS) + item] = t;
+    }
+  }
+  // ---- level 2: the last cell performs the Newton step ----
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&tickets[1 + cell], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = __hip_atomic_fetch_add(&tickets[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
+              (unsigned)(DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH) - 1u;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
+  double* cs = smem;
+  double* sm = cs + ncell * AC::NQ;
+  if (SETUP) {
+    for (int idx = threadIdx.x; idx < ncell * AC::NS; idx += blockDim.x)
+      cs[idx] = cellsum[(size_t)(idx / AC::NS) * (AC::NQ + AC::NS) + AC::NQ + idx % AC::NS];
+    if (threadIdx.x == 0) newton_state_reset(ns, s.N1, level);
+    __syncthreads();
+    setup_scatter<DIM>(s, cs, m, ns);
+  }
+  for (int idx = threadIdx.x; idx < ncell * AC::NQ; idx += blockDim.x)
+    cs[idx] = cellsum[(size_t)(idx / AC::NQ) * (AC::NQ + AC::NS) + idx % AC::NQ];
+  __syncthreads();
   newton_core<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
+  if (threadIdx.x == 0) __hip_atomic_store(&tickets[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-cell quadrature sums of all cells by one block: wavefront w reduces
+// cells w, w + nwaves, ... (no block barrier inside).
+template <int DIM, int KIND>
+__device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                           const double* ytry, double param, double* cs) {
+  using AC = Acc<DIM>;
+  const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int nodes = 1 << (DIM * s.log2r);
+  for (int cell = wave; cell < ncell; cell += nw) {
+    double acc[AC::NQ];
+#pragma unroll
+    for (int q = 0; q < AC::NQ; ++q) acc[q] = 0.0;
+    quad_accumulate<DIM, KIND>(g, s, ut, ytry, param, cell, 0, nodes, lane, 64, acc);
+#pragma unroll
+    for (int q = 0; q < AC::NQ; ++q) {
+      const double v = wave_sum(acc[q]);
+      if (lane == 0) cs[cell * AC::NQ + q] = v;
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIM>
+__device__ __forceinline__ void setup_cells_by_waves(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                            const double* __restrict__ gl, int nf1, int fs, double scale,
+                                            double* cs) {
+  using AC = Acc<DIM>;
+  const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int nodes = 1 << (DIM * s.log2r);
+  for (int cell = wave; cell < ncell; cell += nw) {
+    double acc[AC::NS];
+#pragma unroll
+    for (int q = 0; q < AC::NS; ++q) acc[q] = 0.0;
+    setup_accumulate<DIM>(g, s, ut, gl, nf1, fs, scale, cell, 0, nodes, lane, 64, acc);
+#pragma unroll
+    for (int q = 0; q < AC::NS; ++q) {
+      const double v = wave_sum(acc[q]);
+      if (lane == 0) cs[cell * AC::NS + q] = v;
+    }
+  }
+  __syncthreads();
 }
 
 // Completes a Newton solve that the fixed number of passes did not finish:
-// one block evaluates the fine quadrature itself, cell by cell.
+// one block evaluates the fine quadrature itself.
 template <int DIM, int KIND>
-__global__ void __launch_bounds__(256) k_newton_finish(Grid g, AugShape s, const double* __restrict__ ut,
-                                                       const ProblemSlot* __restrict__ slot,
-                                                       const double* __restrict__ A1, double m,
-                                                       NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
-                                                       int newton_max, double tol) {
+__global__ void __launch_bounds__(1024) k_newton_finish(Grid g, AugShape s, const double* __restrict__ ut,
+                                                        const ProblemSlot* __restrict__ slot,
+                                                        const double* __restrict__ A1, double m,
+                                                        NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
+                                                        int newton_max, double tol) {
   using AC = Acc<DIM>;
   extern __shared__ double smem[];
   const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
   double* cs = smem;
   double* sm = smem + ncell * AC::NQ;
-  double* red = sm + (s.N1 + 1) * (s.N1 + 1) + (s.N1 + 1) + 8;   // (256/64) * NQ
-  const int nodes = 1 << (DIM * s.log2r);
   while (true) {
     __syncthreads();
     if (ns->done) return;
-    for (int cell = 0; cell < ncell; ++cell) {
-      double acc[AC::NQ];
-#pragma unroll
-      for (int q = 0; q < AC::NQ; ++q) acc[q] = 0.0;
-      quad_accumulate<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cell, 0, nodes, threadIdx.x, blockDim.x, acc);
-      const double tot = block_sum_many<AC::NQ>(acc, red);
-      if (threadIdx.x < AC::NQ) cs[cell * AC::NQ + threadIdx.x] = tot;
-    }
-    __syncthreads();
+    quad_cells_by_waves<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cs);
     newton_core<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   }
 }
 
-// u = Q w + alpha u~ at the fine interior nodes (in place on u~).
+// z = Q w + alpha u~ at node (i, j, l) of the level (0 on the boundary, where
+// u~ and every interior coarse hat function vanish).
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_aug_update(Grid g, AugShape s, const NewtonState* __restrict__ ns,
-                                                       double* __restrict__ ut) {
-  int i, j, l;
-  if (!node_of_thread<DIM>(g, i, j, l)) return;
+__device__ __forceinline__ double aug_value(const Grid& g, const AugShape& s, const double* __restrict__ y,
+                                            const double* __restrict__ ut, int i, int j, int l) {
   using AC = Acc<DIM>;
   const int r = 1 << s.log2r;
   const double inv_r = 1.0 / r;
@@ -516,34 +730,77 @@ __global__ void __launch_bounds__(kBlock) k_aug_update(Grid g, AugShape s, const
   double tl[3] = {(i - cx * r) * inv_r, (j - cy * r) * inv_r, DIM == 3 ? (l - cz * r) * inv_r : 0.0};
   double phi[AC::NV];
   kuhn_phi<DIM>(tl, phi);
-  const int c = gidx<DIM>(g, i, j, l);
-  double z = ns->y[s.N1] * ut[c];
+  double z = y[s.N1] * ut[gidx<DIM>(g, i, j, l)];
 #pragma unroll
   for (int a = 0; a < AC::NV; ++a) {
     const int gi = coarse_vertex<DIM>(s.nH, cx, cy, cz, a);
-    if (gi >= 0) z += ns->y[gi] * phi[a];
+    if (gi >= 0) z += y[gi] * phi[a];
   }
-  ut[c] = z;
+  return z;
+}
+
+// Level transition of Algorithm 3.2: u_k^(0) = P u_{k-1} (natural inclusion)
+// and b_k = M_k (g - f(u_k^(0))).  With use_aug, u_{k-1} is the result of the
+// last correction step on level k-1, Q w + alpha u~, evaluated where read.
+template <int DIM, int KIND>
+__global__ void __launch_bounds__(kBlock) k_transition(Grid gc, AugShape sc, const NewtonState* __restrict__ ns,
+                                                       const double* __restrict__ uc, int use_aug, Grid gf,
+                                                       double* __restrict__ uf, double* __restrict__ bf,
+                                                       const ProblemSlot* __restrict__ slot, int nf1, int fs,
+                                                       double m) {
+  int i, j, l;
+  if (!node_of_thread<DIM>(gf, i, j, l)) return;
+  const int si = i & 1, sj = j & 1, sl = DIM == 3 ? (l & 1) : 0;
+  const int pi = i >> 1, pj = j >> 1, pl = l >> 1;
+  auto coarse = [&](int a, int b, int c) {
+    return use_aug ? aug_value<DIM>(gc, sc, ns->y, uc, a, b, c) : uc[gidx<DIM>(gc, a, b, c)];
+  };
+  double v = coarse(pi, pj, pl);
+  if (si | sj | sl) v = 0.5 * (v + coarse(pi + si, pj + sj, pl + sl));
+  const int q = gidx<DIM>(gf, i, j, l);
+  uf[q] = v;
+  bf[q] = m * (slot->g[fine_load_index(nf1, fs, i, j, l)] - NL<KIND>::f(v, slot->param));
+}
+
+// u = Q w + alpha u~ at fine interior node (i, j, l) (in place on u~).
+template <int DIM>
+__device__ __forceinline__ void update_node(const Grid& g, const AugShape& s, const NewtonState* __restrict__ ns,
+                                            double* __restrict__ ut, int i, int j, int l) {
+  const double z = aug_value<DIM>(g, s, ns->y, ut, i, j, l);
+  ut[gidx<DIM>(g, i, j, l)] = z;
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_aug_update(Grid g, AugShape s, const NewtonState* __restrict__ ns,
+                                                       double* __restrict__ ut) {
+  int i, j, l;
+  if (!node_of_thread<DIM>(g, i, j, l)) return;
+  update_node<DIM>(g, s, ns, ut, i, j, l);
 }
 
 // ---------------------------------------------------------------------------
 // Algorithm 3.2, step 1: Newton on A_1 U + m_1 f(U) = m_1 g on level 1 (one
 // block; same damping and stopping rules as the augmented solve).
 // ---------------------------------------------------------------------------
+// LDS doubles of level1_newton_dev.
+__host__ __device__ constexpr int level1_lds_doubles(int N1) { return 2 * N1 * N1 + 8 * N1 + 4; }
+
 template <int DIM, int KIND>
-__global__ void __launch_bounds__(256) k_level1_newton(Grid g1, int N1, const double* __restrict__ A1, double m1,
-                                                       const ProblemSlot* __restrict__ slot, int nf1, int fs,
-                                                       double* __restrict__ x1, fmg_report* __restrict__ rep,
-                                                       int newton_max, double tol) {
-  extern __shared__ double smem[];
-  double* J = smem;                 // N1*N1
+__device__ __forceinline__ void level1_newton_dev(const Grid& g1, int N1, const double* __restrict__ A1g, double m1,
+                                  const ProblemSlot* __restrict__ slot, int nf1, int fs, double* __restrict__ x1,
+                                  fmg_report* __restrict__ rep, int newton_max, double tol, double* smem) {
+  double* A1 = smem;                // N1*N1
+  double* J = A1 + N1 * N1;         // N1*N1
   double* R = J + N1 * N1;          // N1
   double* U = R + N1;               // N1
   double* G = U + N1;               // N1 (m g)
   double* D = G + N1;               // N1
   double* T = D + N1;               // N1 trial
-  double* sc = T + N1;              // scalars: [0]=E [1]=scale [2]=done [3]=it
+  double* col = T + N1;             // N1 Cholesky column
+  double* rdiag = col + N1;         // N1 reciprocal pivots
+  double* sc = rdiag + N1;          // scalars: [0]=E [1]=scale [2]=done
   const double q = slot->param;
+  for (int idx = threadIdx.x; idx < N1 * N1; idx += blockDim.x) A1[idx] = A1g[idx];
   for (int r = threadIdx.x; r < N1; r += blockDim.x) {
     const int mm = g1.n - 1;
     const int i = 1 + r % mm, j = 1 + (r / mm) % mm, l = DIM == 3 ? 1 + r / (mm * mm) : 0;
@@ -551,7 +808,7 @@ __global__ void __launch_bounds__(256) k_level1_newton(Grid g1, int N1, const do
     U[r] = 0.0;
   }
   __syncthreads();
-  auto energy = [&](const double* V, double& E, double& S) {   // thread 0
+  auto energy = [&](const double* V, double& E, double& S) {   // one thread
     double t1 = 0.0, t2 = 0.0, t3 = 0.0;
     for (int a = 0; a < N1; ++a) {
       double t = 0.0;
@@ -569,7 +826,6 @@ __global__ void __launch_bounds__(256) k_level1_newton(Grid g1, int N1, const do
   if (threadIdx.x == 0) {
     energy(U, sc[0], sc[1]);
     sc[2] = 0.0;
-    sc[3] = 0.0;
   }
   __syncthreads();
   int it = 0;
@@ -584,12 +840,13 @@ __global__ void __launch_bounds__(256) k_level1_newton(Grid g1, int N1, const do
       NL<KIND>::all(U[a], q, f, df, F);
       R[a] = t + m1 * f - G[a];
       J[a * N1 + a] += m1 * df;
+      D[a] = -R[a];
     }
     __syncthreads();
-    chol_steps(J, N1, N1);
+    chol_steps_wave(J, col, rdiag, N1, N1);
+    chol_solve_wave(J, rdiag, N1, N1, D);
+    __syncthreads();
     if (threadIdx.x == 0) {
-      for (int a = 0; a < N1; ++a) D[a] = -R[a];
-      chol_solve_serial(J, N1, N1, D);
       double slope = 0.0;
       for (int a = 0; a < N1; ++a) slope += R[a] * D[a];
       double t = 1.0, E = sc[0], S = sc[1], Et = 0.0, St = 0.0;
@@ -617,6 +874,16 @@ __global__ void __launch_bounds__(256) k_level1_newton(Grid g1, int N1, const do
     rep->level1_iters = ok ? it : newton_max;
     if (!ok) report_status(rep, sc[2] == 2.0 ? FMG_E_NONFINITE : FMG_E_NOT_CONVERGED);
   }
+  __syncthreads();
+}
+
+template <int DIM, int KIND>
+__global__ void __launch_bounds__(256) k_level1_newton(Grid g1, int N1, const double* __restrict__ A1, double m1,
+                                                       const ProblemSlot* __restrict__ slot, int nf1, int fs,
+                                                       double* __restrict__ x1, fmg_report* __restrict__ rep,
+                                                       int newton_max, double tol) {
+  extern __shared__ double smem[];
+  level1_newton_dev<DIM, KIND>(g1, N1, A1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -651,6 +918,26 @@ __global__ void k_output(Grid g, const double* __restrict__ x, const ProblemSlot
     const int i = (int)(p % n1), j = (int)((p / n1) % n1), l = DIM == 3 ? (int)(p / ((size_t)n1 * n1)) : 0;
     const bool bnd = i == 0 || j == 0 || i == g.n || j == g.n || (DIM == 3 && (l == 0 || l == g.n));
     const double v = bnd ? 0.0 : x[gidx<DIM>(g, i, j, l)];
+    bad |= !isfinite(v);
+    out[p] = v;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+// Output of the final level when its last update was deferred: writes
+// Q w + alpha u~ directly in the packed layout.
+template <int DIM>
+__global__ void k_output_update(Grid g, AugShape s, const NewtonState* __restrict__ ns,
+                                const double* __restrict__ ut, const ProblemSlot* __restrict__ slot,
+                                int* __restrict__ flag) {
+  const int n1 = g.n + 1;
+  const size_t total = DIM == 2 ? (size_t)n1 * n1 : (size_t)n1 * n1 * n1;
+  double* __restrict__ out = slot->u_out;
+  int bad = 0;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(p % n1), j = (int)((p / n1) % n1), l = DIM == 3 ? (int)(p / ((size_t)n1 * n1)) : 0;
+    const bool bnd = i == 0 || j == 0 || i == g.n || j == g.n || (DIM == 3 && (l == 0 || l == g.n));
+    const double v = bnd ? 0.0 : aug_value<DIM>(g, s, ns->y, ut, i, j, l);
     bad |= !isfinite(v);
     out[p] = v;
   }

@@ -1,0 +1,144 @@
+// Single-workgroup "tail" of the V-cycle: every level at or below a small
+// level T (a few thousand nodes) is processed by one workgroup in one launch,
+// with workgroup barriers between the phases, instead of one grid launch per
+// sweep/transfer.  The arithmetic is the same as the grid kernels' (same
+// stencil helper, same operation order per node), so results are identical.
+#pragma once
+
+#include "fmg_device.h"
+#include "fmg_kernels_mg.h"
+
+namespace fmg {
+
+constexpr int kTailThreads = 1024;
+constexpr int kTailLevels = 8;   // deepest level a tail launch may start from
+constexpr int kTailSweeps = 8;   // max sweeps per level in a tail launch
+
+template <typename T>
+struct TailArgs {
+  T* x[FMG_MAX_LEVELS + 1];     // current iterate of each level (roles as on entry)
+  T* t[FMG_MAX_LEVELS + 1];     // spare array of each level
+  T* b[FMG_MAX_LEVELS + 1];     // right-hand sides
+  Grid g[FMG_MAX_LEVELS + 1];
+  T scale[FMG_MAX_LEVELS + 1];  // h^{d-2}
+  T wdpre[kTailLevels + 1][kTailSweeps];   // omega_i / D_k per level and sweep
+  T wdpost[kTailLevels + 1][kTailSweeps];
+  const T* ainv;                // A_1^{-1}, dense N1 x N1
+  int N1, top, npre, npost, zero_top;
+};
+
+template <int DIM>
+__device__ __forceinline__ int interior_count(const Grid& g) {
+  const int m = g.n - 1;
+  return DIM == 2 ? m * m : m * m * m;
+}
+
+template <int DIM>
+__device__ __forceinline__ int interior_node(const Grid& g, int t) {
+  const int m = g.n - 1;
+  const int i = 1 + t % m, j = 1 + (t / m) % m, l = DIM == 3 ? 1 + t / (m * m) : 0;
+  return gidx<DIM>(g, i, j, l);
+}
+
+template <int DIM, typename T, bool ZERO>
+__device__ __forceinline__ void blk_smooth(const Grid& g, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ out,
+                           T wd, T scale) {
+  const int total = interior_count<DIM>(g);
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int c = interior_node<DIM>(g, t);
+    if (ZERO) out[c] = wd * b[c];
+    else out[c] = x[c] + wd * (b[c] - apply_A_at<DIM>(x, c, g, scale));
+  }
+  __syncthreads();
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void blk_fill_interior(const Grid& g, T* __restrict__ x) {
+  const int total = interior_count<DIM>(g);
+  for (int t = threadIdx.x; t < total; t += blockDim.x) x[interior_node<DIM>(g, t)] = T(0);
+  __syncthreads();
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void blk_resid_restrict(const Grid& f, const Grid& cg, const T* __restrict__ x, const T* __restrict__ b,
+                                   T* __restrict__ bc, T scale) {
+  const int total = interior_count<DIM>(cg);
+  const int m = cg.n - 1;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int i = 1 + t % m, j = 1 + (t / m) % m, l = DIM == 3 ? 1 + t / (m * m) : 0;
+    const int q = gidx<DIM>(f, 2 * i, 2 * j, 2 * l);
+    auto r = [&](int p) { return b[p] - apply_A_at<DIM>(x, p, f, scale); };
+    const int dx = 1, dy = f.px;
+    T h = (r(q + dx) + r(q - dx)) + (r(q + dy) + r(q - dy)) + (r(q + dx + dy) + r(q - dx - dy));
+    if (DIM == 3) {
+      const int dz = f.pz;
+      h += (r(q + dz) + r(q - dz)) + (r(q + dx + dz) + r(q - dx - dz)) +
+           (r(q + dy + dz) + r(q - dy - dz)) + (r(q + dx + dy + dz) + r(q - dx - dy - dz));
+    }
+    bc[gidx<DIM>(cg, i, j, l)] = r(q) + T(0.5) * h;
+  }
+  __syncthreads();
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void blk_prolong_add(const Grid& cg, const Grid& f, const T* __restrict__ xc, T* __restrict__ xf) {
+  const int total = interior_count<DIM>(f);
+  const int m = f.n - 1;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int i = 1 + t % m, j = 1 + (t / m) % m, l = DIM == 3 ? 1 + t / (m * m) : 0;
+    const int si = i & 1, sj = j & 1, sl = DIM == 3 ? (l & 1) : 0;
+    const int pi = i >> 1, pj = j >> 1, pl = l >> 1;
+    T v = xc[gidx<DIM>(cg, pi, pj, pl)];
+    if (si | sj | sl) v = T(0.5) * (v + xc[gidx<DIM>(cg, pi + si, pj + sj, pl + sl)]);
+    const int q = gidx<DIM>(f, i, j, l);
+    xf[q] = xf[q] + v;
+  }
+  __syncthreads();
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void blk_coarse_solve(const Grid& g1, int N1, const T* __restrict__ Ainv, const T* __restrict__ b,
+                                 T* __restrict__ x) {
+  for (int r = threadIdx.x; r < N1; r += blockDim.x) {
+    T s = 0;
+    for (int c = 0; c < N1; ++c) s += Ainv[r * N1 + c] * b[level1_node<DIM>(g1, c)];
+    x[level1_node<DIM>(g1, r)] = s;
+  }
+  __syncthreads();
+}
+
+// V-cycle on levels top..1 with right-hand side b[top] and initial iterate
+// x[top] (zero if zero_top).  Roles of x/t are swapped after every sweep, as
+// the host-side launch sequence does; x[] and t[] are updated in place.
+template <int DIM, typename T>
+__device__ __forceinline__ void vcycle_tail_dev(const TailArgs<T>& a, T** x, T** t, int top, bool zero_top) {
+  for (int k = top; k >= 2; --k) {
+    const bool zero = k < top || zero_top;
+    if (zero && a.npre == 0) blk_fill_interior<DIM, T>(a.g[k], x[k]);
+    for (int i = 0; i < a.npre; ++i) {
+      const T wd = a.wdpre[k][i];
+      if (zero && i == 0) blk_smooth<DIM, T, true>(a.g[k], x[k], a.b[k], t[k], wd, a.scale[k]);
+      else blk_smooth<DIM, T, false>(a.g[k], x[k], a.b[k], t[k], wd, a.scale[k]);
+      T* s = x[k]; x[k] = t[k]; t[k] = s;
+    }
+    blk_resid_restrict<DIM, T>(a.g[k], a.g[k - 1], x[k], a.b[k], a.b[k - 1], a.scale[k]);
+  }
+  blk_coarse_solve<DIM, T>(a.g[1], a.N1, a.ainv, a.b[1], x[1]);
+  for (int k = 2; k <= top; ++k) {
+    blk_prolong_add<DIM, T>(a.g[k - 1], a.g[k], x[k - 1], x[k]);
+    for (int i = 0; i < a.npost; ++i) {
+      blk_smooth<DIM, T, false>(a.g[k], x[k], a.b[k], t[k], a.wdpost[k][i], a.scale[k]);
+      T* s = x[k]; x[k] = t[k]; t[k] = s;
+    }
+  }
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailArgs<T> a) {
+  T* x[kTailLevels + 1];
+  T* t[kTailLevels + 1];
+  for (int k = 1; k <= a.top; ++k) { x[k] = a.x[k]; t[k] = a.t[k]; }
+  vcycle_tail_dev<DIM, T>(a, x, t, a.top, a.zero_top != 0);
+}
+
+}  // namespace fmg
