@@ -104,6 +104,8 @@ typedef struct {
                            run together in one single-workgroup launch (0: off) */
     int fuse_small_levels; /* 1: run Algorithm 3.2 on those small levels (all
                               steps, incl. the Newton solves) in one launch */
+    int aug_max_blocks; /* workgroups per fine quadrature pass of the augmented
+                           problem (upper bound; 64..16384)                  */
 } fmg_options;
 
 typedef struct {

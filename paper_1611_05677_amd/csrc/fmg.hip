@@ -16,13 +16,14 @@
 #include "fmg_kernels_mg.h"
 #include "fmg_kernels_tail.h"
 #include "fmg_kernels_fmgtail.h"
+#include "fmg_kernels_fused2d.h"
+#include "fmg_newton_reg.h"
 
 using namespace fmg;
 
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxAugBlocks = 2048;   // target number of blocks of the augmented passes
 constexpr int kNormBlocksMax = 1 << 20;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -72,6 +73,7 @@ int resolve(int dim, const fmg_options* in, Resolved& r) {
   if (o.mode != FMG_PAPER && o.mode != FMG_CONVERGED) return FMG_E_INVALID;
   if (o.mode == FMG_CONVERGED && (o.converged_max_steps < 1 || !(o.converged_tol > 0))) return FMG_E_INVALID;
   if (o.tail_max_nodes < 0 || (o.fuse_small_levels != 0 && o.fuse_small_levels != 1)) return FMG_E_INVALID;
+  if (o.aug_max_blocks < 64 || o.aug_max_blocks > 16384) return FMG_E_INVALID;
   r.o = o;
   r.smoother = o.smoother ? o.smoother : (dim == 2 ? FMG_JACOBI : FMG_CHEBYSHEV);
   if (r.smoother == FMG_JACOBI) {
@@ -124,7 +126,7 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p) {
     L.m = d == 2 ? h * h : h * h * h;
     if (k >= 2) {
       const int nodes_log = d * (k - 1);
-      const int cap_log = ilog2(std::max(1, kMaxAugBlocks / ncell));
+      const int cap_log = ilog2(std::max(1, ro.o.aug_max_blocks / ncell));
       const int bpc_log = std::max(0, std::min(nodes_log - 8, cap_log));
       L.aug.nH = p.nH;
       L.aug.log2r = k - 1;
@@ -200,14 +202,15 @@ enum KernelClass {
   KC_SMOOTH32, KC_SMOOTH32_ZERO, KC_RESTRICT32, KC_PROLONG32_ADD, KC_COARSE32,
   KC_TRANSITION, KC_RHS, KC_RESID_F32, KC_ADD_F32, KC_AUG_PASS0, KC_AUG_PASS, KC_OUTPUT_UPDATE,
   KC_NEWTON_FINISH, KC_AUG_UPDATE, KC_LEVEL1, KC_BEGIN, KC_OUTPUT, KC_END, KC_FILL,
-  KC_VCYCLE_TAIL64, KC_VCYCLE_TAIL32, KC_FMG_TAIL, KC_COUNT
+  KC_VCYCLE_TAIL64, KC_VCYCLE_TAIL32, KC_FMG_TAIL, KC_PRE2D64, KC_POST2D64, KC_PRE2D32, KC_POST2D32, KC_COUNT
 };
 const char* const kKernelNames[KC_COUNT] = {
   "smooth_f64", "smooth_f64_from_zero", "resid_restrict_f64", "prolong_add_f64", "coarse_solve_f64",
   "smooth_f32", "smooth_f32_from_zero", "resid_restrict_f32", "prolong_add_f32", "coarse_solve_f32",
   "transition", "rhs", "resid_to_f32", "add_f32", "aug_pass0_setup", "aug_pass", "output_update",
   "newton_finish", "aug_update", "level1_newton", "begin_solve", "output", "end_solve", "fill",
-  "vcycle_tail_f64", "vcycle_tail_f32", "fmg_tail"};
+  "vcycle_tail_f64", "vcycle_tail_f32", "fmg_tail", "pre_sweeps_restrict_2d_f64", "prolong_post_sweeps_2d_f64",
+  "pre_sweeps_restrict_2d_f32", "prolong_post_sweeps_2d_f32"};
 
 // Event pairs around launches (fmg_profile_solve only).
 struct Prof {
@@ -328,6 +331,25 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
   const T scale = (T)L.scale;
   const double D = 2.0 * DIM * L.scale;
   const int npre = h->ro.o.nu_pre, npost = h->ro.o.nu_post;
+  if (DIM == 2 && npre == 2 && npost == 2) {
+    // fused level kernels: two sweeps + residual + restriction, then
+    // correction + two sweeps (each writes the spare array: one role swap)
+    const LevelInfo& C = p.lev[k - 1];
+    const long long Nc = interior(C.g, DIM);
+    const dim3 tiles((L.g.n + kFTX - 1) / kFTX, (L.g.n + kFTY - 1) / kFTY);
+    const int kc2 = Sel<T>::kc ? (KC_PRE2D32 - KC_PRE2D64) : 0;
+    FMG_LAUNCH(h, st, KC_PRE2D64 + kc2, k, N, s * ((zero_init ? 2 : 3) * N + Nc),
+               k_pre2d<T><<<tiles, kBlock, pre2d_lds_bytes<T>(), st>>>(
+                   L.g, C.g, x, b, t, Sel<T>::b(h, k - 1), (T)(h->ro.pre[0] / D), (T)(h->ro.pre[1] / D), scale,
+                   zero_init ? 1 : 0));
+    std::swap(x, t);
+    vcycle<DIM, T>(h, R, k - 1, true, st);
+    FMG_LAUNCH(h, st, KC_POST2D64 + kc2, k, N, s * (3 * N + Nc),
+               k_post2d<T><<<tiles, kBlock, post2d_lds_bytes<T>(), st>>>(
+                   C.g, L.g, x, Sel<T>::x(R, k - 1), b, t, (T)(h->ro.post[0] / D), (T)(h->ro.post[1] / D), scale));
+    std::swap(x, t);
+    return;
+  }
   if (zero_init && npre == 0)
     FMG_LAUNCH(h, st, KC_FILL, k, N, s * L.count, k_fill<T><<<256, 256, 0, st>>>(x, L.count, T(0)));
   for (int i = 0; i < npre; ++i) {
@@ -601,8 +623,9 @@ void fmg_default_options(int dim, fmg_options* o) {
   o->converged_max_steps = 40;
   o->converged_tol = 1e-13;
   o->use_graph = 1;
-  o->tail_max_nodes = 4096;
+  o->tail_max_nodes = 1024;
   o->fuse_small_levels = 0;
+  o->aug_max_blocks = 512;
   (void)dim;
 }
 

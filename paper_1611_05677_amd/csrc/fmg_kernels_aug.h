@@ -543,6 +543,11 @@ __host__ __device__ constexpr int newton_kernel_lds_doubles(int ncell, int NQ, i
   return ncell * NQ + newton_scratch_doubles(N1) + threads;
 }
 
+template <int DIM>
+__device__ __forceinline__ void newton_step_dev(const AugShape& s, const double* cs, const double* __restrict__ A1,
+                                                double m, NewtonState* ns, fmg_report* rep, int newton_max,
+                                                double tol, double* sm);
+
 // One pass of the augmented Newton iteration in one launch.  Every block
 // accumulates its share of the fine quadrature sums at ns->ytry (SETUP: the
 // setup sums plus the sums at y0 = (0,..,0,1), i.e. z = u~) and writes them
@@ -590,12 +595,14 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
   }
   // ---- level 1: the last block of this cell reduces the cell's partials ----
   __syncthreads();
-  if (threadIdx.x == 0)
-    is_last = __hip_atomic_fetch_add(&tickets[1 + cell], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
-              (unsigned)(bpc - 1);
-  __syncthreads();
-  if (!is_last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (bpc > 1) {
+    if (threadIdx.x == 0)
+      is_last = __hip_atomic_fetch_add(&tickets[1 + cell], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
+                (unsigned)(bpc - 1);
+    __syncthreads();
+    if (!is_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
   {
     const int S = max(1, min(bpc, (int)blockDim.x / W));
     const int seg = (bpc + S - 1) / S;
@@ -627,7 +634,7 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
   // ---- level 2: the last cell performs the Newton step ----
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_store(&tickets[1 + cell], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (bpc > 1) __hip_atomic_store(&tickets[1 + cell], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = __hip_atomic_fetch_add(&tickets[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
               (unsigned)(DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH) - 1u;
   }
@@ -647,7 +654,7 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
   for (int idx = threadIdx.x; idx < ncell * AC::NQ; idx += blockDim.x)
     cs[idx] = cellsum[(size_t)(idx / AC::NQ) * (AC::NQ + AC::NS) + idx % AC::NQ];
   __syncthreads();
-  newton_core<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
+  newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   if (threadIdx.x == 0) __hip_atomic_store(&tickets[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -713,7 +720,7 @@ __global__ void __launch_bounds__(1024) k_newton_finish(Grid g, AugShape s, cons
     __syncthreads();
     if (ns->done) return;
     quad_cells_by_waves<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cs);
-    newton_core<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
+    newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   }
 }
 
@@ -875,15 +882,6 @@ __device__ __forceinline__ void level1_newton_dev(const Grid& g1, int N1, const 
     if (!ok) report_status(rep, sc[2] == 2.0 ? FMG_E_NONFINITE : FMG_E_NOT_CONVERGED);
   }
   __syncthreads();
-}
-
-template <int DIM, int KIND>
-__global__ void __launch_bounds__(256) k_level1_newton(Grid g1, int N1, const double* __restrict__ A1, double m1,
-                                                       const ProblemSlot* __restrict__ slot, int nf1, int fs,
-                                                       double* __restrict__ x1, fmg_report* __restrict__ rep,
-                                                       int newton_max, double tol) {
-  extern __shared__ double smem[];
-  level1_newton_dev<DIM, KIND>(g1, N1, A1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
 }
 
 // ---------------------------------------------------------------------------

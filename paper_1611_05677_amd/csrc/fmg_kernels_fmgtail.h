@@ -7,6 +7,7 @@
 
 #include "fmg_kernels_aug.h"
 #include "fmg_kernels_tail.h"
+#include "fmg_newton_reg.h"
 
 namespace fmg {
 
@@ -93,7 +94,7 @@ __device__ __forceinline__ void aug_solve_dev(const Grid& g, const AugShape& s, 
     __syncthreads();
     if (ns->done) break;
     quad_cells_by_waves<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cs);
-    newton_core<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
+    newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   }
   __syncthreads();
   const int total = interior_count<DIM>(g);
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(kTailThreads) k_fmg_tail(const FmgTailParams* 
   }
   const TailArgs<double>& V = P->v64;
   // Algorithm 3.2, step 1
-  level1_newton_dev<DIM, KIND>(V.g[1], V.N1, P->A1, P->m[1], P->slot, P->nf1, 1 << (P->nlev - 1), x64[1], P->rep,
+  level1_dispatch<DIM, KIND>(V.g[1], V.N1, P->A1, P->m[1], P->slot, P->nf1, 1 << (P->nlev - 1), x64[1], P->rep,
                                P->newton_max, P->newton_tol, smem);
   // step 2 on levels 2..top
   for (int k = 2; k <= top; ++k) {

@@ -1,0 +1,363 @@
+// Register-resident small dense Newton solves for a coarse grid of 4 cells per
+// side (N_1 = 9 unknowns in 2D, 27 in 3D), executed by one wavefront.  Lane A
+// owns coarse unknown A (and lane N_1 the coefficient alpha of u~): its row
+// of the Newton matrix lives in registers, A_1 w comes from the coarse
+// stencil through lane shuffles, the Cholesky factorisation broadcasts
+// columns with shuffles, and one LDS transpose serves the backward solve.
+// Same damping, stopping and degenerate-direction rules as newton_core.
+#pragma once
+
+#include "fmg_kernels_aug.h"
+
+namespace fmg {
+
+// Coarse-stencil product (A_1 v)_A = s1 (2d v_A - sum of axis neighbours) for
+// the lane's own node A (mm = nH - 1 nodes per side); lanes >= N1 return 0.
+template <int DIM>
+__device__ __forceinline__ double stencil_shfl(double v, int A, int ax, int ay, int az, int mm, bool node,
+                                               double s1) {
+  const int lane = threadIdx.x;
+  auto sh = [&](int src, bool ok) {
+    const double r = __shfl(v, ok ? src : lane, 64);
+    return ok ? r : 0.0;
+  };
+  double nb = (sh(A - 1, ax > 1) + sh(A + 1, ax < mm)) + (sh(A - mm, ay > 1) + sh(A + mm, ay < mm));
+  if (DIM == 3) nb += sh(A - mm * mm, az > 1) + sh(A + mm * mm, az < mm);
+  return node ? s1 * (2.0 * DIM * v - nb) : 0.0;
+}
+
+// Cholesky of the NY x NY matrix whose row `lane` is jr[] (lower part used),
+// steps k = 0..NY-2; returns through jr the factor rows and through myrd the
+// reciprocal of the lane's pivot.  The Schur complement of the last row is
+// left in lane NY-1's jr[NY-1] (not square-rooted).
+template <int NY>
+__device__ __forceinline__ void chol_reg(double (&jr)[NY], double& myrd) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < NY - 1; ++k) {
+    const double dkk = __shfl(jr[k], k, 64);
+    const double sk = sqrt(dkk);
+    const double rk = 1.0 / sk;
+    const double lik = lane > k ? jr[k] * rk : 0.0;
+    if (lane == k) { jr[k] = sk; myrd = rk; }
+    if (lane > k) jr[k] = lik;
+#pragma unroll
+    for (int j = k + 1; j < NY; ++j) {
+      const double ljk = __shfl(lik, j, 64);
+      if (lane >= j) jr[j] -= lik * ljk;
+    }
+  }
+}
+
+// Solve L L^T x = b for the leading nn unknowns (v holds b_lane on entry and
+// x_lane on exit).  Lt: LDS scratch of NY*NY doubles for the transpose.
+template <int NY>
+__device__ __forceinline__ double chol_solve_reg(const double (&jr)[NY], double myrd, int nn, double v,
+                                                 double* __restrict__ Lt) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < NY; ++j)
+    if (lane < NY && j <= lane) Lt[lane * NY + j] = jr[j];
+  wave_sync();
+  double colr[NY];
+#pragma unroll
+  for (int j = 0; j < NY; ++j) colr[j] = (lane < NY && j > lane) ? Lt[j * NY + lane] : 0.0;
+#pragma unroll
+  for (int j = 0; j < NY; ++j) {
+    if (j < nn) {
+      if (lane == j) v *= myrd;
+      const double xj = __shfl(v, j, 64);
+      if (lane > j && lane < nn) v -= jr[j] * xj;
+    }
+  }
+#pragma unroll
+  for (int j = NY - 1; j >= 0; --j) {
+    if (j < nn) {
+      if (lane == j) v *= myrd;
+      const double xj = __shfl(v, j, 64);
+      if (lane < j) v -= colr[j] * xj;
+    }
+  }
+  wave_sync();
+  return lane < nn ? v : 0.0;
+}
+
+// Pair index of cell vertices (a, b), a subset of b, as a constant expression.
+template <int DIM>
+__host__ __device__ constexpr int pair_of(int a, int b) {
+  int p = 0;
+  for (int x = 0; x < (1 << DIM); ++x)
+    for (int y = x; y < (1 << DIM); ++y)
+      if ((x & y) == x) {
+        if (x == a && y == b) return p;
+        ++p;
+      }
+  return -1;
+}
+
+// Newton step (see newton_core) with the state in registers.  LDS: J (NY*NY).
+template <int DIM, int NY>
+__device__ __forceinline__ void newton_core_reg(const AugShape& s, const double* cs, double m, NewtonState* nsg,
+                                                fmg_report* rep, int newton_max, double tol, double* sm) {
+  if (threadIdx.x >= 64) return;
+  using AC = Acc<DIM>;
+  constexpr int N1 = NY - 1;
+  constexpr int NV = AC::NV;
+  const int lane = threadIdx.x;
+  const int nH = s.nH, mm = nH - 1;
+  const int ncell = DIM == 2 ? nH * nH : nH * nH * nH;
+  const double s1 = DIM == 2 ? 1.0 : 1.0 / nH;
+  const bool act = lane < NY, node = lane < N1;
+  double* J = sm;
+  // ---- state ----
+  const double yt = act ? nsg->ytry[lane] : 0.0;
+  const double yold = act ? nsg->y[lane] : 0.0;
+  const double dold = act ? nsg->d[lane] : 0.0;
+  const double bh = node ? nsg->bH[lane] : 0.0;
+  const double gh = node ? nsg->GH[lane] : 0.0;
+  const double c = nsg->c, Gu = nsg->Gu, E = nsg->E, Escale = nsg->Escale, slope0 = nsg->slope, t = nsg->t;
+  const int iter = nsg->iter, passes = nsg->passes;
+  const double alpha = __shfl(yt, N1, 64);
+  const double w = node ? yt : 0.0;
+  const int A = node ? lane : 0;
+  int ax, ay, az;
+  coarse_coords<DIM>(nH, A, ax, ay, az);
+  // ---- residual and the J column of u~ ----
+  const double Aw = stencil_shfl<DIM>(w, A, ax, ay, az, mm, node, s1);
+  double nh = 0.0, khu = 0.0;
+  double st[DIM == 2 ? 9 : 27];   // m f' phi_A phi_B by offset B - A in {-1,0,1}^d
+#pragma unroll
+  for (int q = 0; q < (DIM == 2 ? 9 : 27); ++q) st[q] = 0.0;
+  if (node) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int cx = ax - (e & 1), cy = ay - ((e >> 1) & 1), cz = DIM == 3 ? az - ((e >> 2) & 1) : 0;
+      const double* cc = cs + (cx + nH * (cy + nH * cz)) * AC::NQ;
+      nh += cc[AC::Q_NH + e];
+      khu += cc[AC::Q_KHU + e];
+#pragma unroll
+      for (int f = 0; f < NV; ++f) {
+        const int lo = e < f ? e : f, hi = e < f ? f : e;
+        if ((lo & hi) != lo) continue;                  // not in a common simplex
+        const int p = pair_of<DIM>(lo, hi);
+        const int dx = (f & 1) - (e & 1), dy = ((f >> 1) & 1) - ((e >> 1) & 1),
+                  dz = DIM == 3 ? ((f >> 2) & 1) - ((e >> 2) & 1) : 0;
+        const int q = (dx + 1) + 3 * (dy + 1) + (DIM == 3 ? 9 * (dz + 1) : 0);
+        st[q] += cc[AC::Q_K + p];
+      }
+    }
+  }
+  const double R = node ? Aw + alpha * bh - gh + m * nh : 0.0;
+  const double jAu = node ? bh + m * khu : 0.0;      // J[A][N1]
+  // ---- scalars (wave sums) ----
+  double nu = 0.0, kuu = 0.0, sF = 0.0;
+  for (int cidx = lane; cidx < ncell; cidx += 64) {
+    nu += cs[cidx * AC::NQ + AC::Q_NU];
+    kuu += cs[cidx * AC::NQ + AC::Q_KUU];
+    sF += cs[cidx * AC::NQ + AC::Q_E];
+  }
+  nu = wave_allsum(nu); kuu = wave_allsum(kuu); sF = wave_allsum(sF);
+  const double bw = wave_allsum(bh * w), gw = wave_allsum(gh * w), wAw = wave_allsum(w * Aw);
+  const double Juu = c + m * kuu;
+  const double Ru = bw + alpha * c + m * nu - Gu;
+  const double Rl = lane == N1 ? Ru : R;
+  const double t1 = 0.5 * wAw + alpha * bw + 0.5 * alpha * alpha * c;
+  const double t2 = m * sF;
+  const double t3 = gw + alpha * Gu;
+  const double Etry = t1 + t2 - t3, Stry = fabs(t1) + fabs(t2) + fabs(t3);
+  // ---- state machine (uniform decisions) ----
+  const bool finite = __all(isfinite(Etry) && isfinite(Rl));
+  int newdir = 0, done = 0, ok = 0, halve = 0;
+  if (!finite) {
+    done = 1;
+  } else if (passes == 0) {
+    newdir = 1;
+  } else if (Etry <= E + kArmijo * t * slope0 + kEnergyRounding * fmax(Escale, Stry)) {
+    const double stepmax = wave_allmax(act ? fabs(t * dold) : 0.0);
+    const double ymax = wave_allmax(act ? fabs(yt) : 0.0);
+    if (stepmax <= tol * fmax(1.0, ymax)) { done = 1; ok = 1; }
+    else newdir = 1;
+  } else {
+    halve = 1;
+  }
+  if (newdir && iter >= newton_max) { done = 1; ok = 0; newdir = 0; }
+  const bool accept = finite && !halve;
+  double ynew = accept ? yt : yold;                  // accepted iterate
+  double ytry_new = yt, dnew = dold, tnew = t, slope = slope0;
+  int halvings = nsg->halvings;
+  if (halve) {
+    tnew = 0.5 * t;
+    ytry_new = ynew + tnew * dold;
+    if (++halvings > kMaxHalvings * newton_max) { done = 1; ok = 0; }
+  }
+  if (newdir) {
+    // rows of J in LDS, then in registers
+    if (node) {
+#pragma unroll
+      for (int B = 0; B < NY; ++B) J[A * NY + B] = 0.0;
+    }
+    wave_sync();
+    if (node) {
+#pragma unroll
+      for (int q = 0; q < (DIM == 2 ? 9 : 27); ++q) {
+        const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = DIM == 3 ? q / 9 - 1 : 0;
+        const int bx = ax + dx, by = ay + dy, bz = az + dz;
+        if (bx < 1 || bx > mm || by < 1 || by > mm || (DIM == 3 && (bz < 1 || bz > mm))) continue;
+        const int B = A + dx + mm * dy + mm * mm * dz;
+        const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+        const double a1 = nz == 0 ? 2.0 * DIM * s1 : (nz == 1 ? -s1 : 0.0);
+        J[A * NY + B] = a1 + m * st[q];
+      }
+      J[A * NY + N1] = jAu;
+    }
+    {
+#pragma unroll
+      for (int B = 0; B < N1; ++B) {
+        const double v = __shfl(jAu, B, 64);
+        if (lane == N1) J[N1 * NY + B] = v;
+      }
+      if (lane == N1) J[N1 * NY + N1] = Juu;
+    }
+    wave_sync();
+    double jr[NY];
+#pragma unroll
+    for (int B = 0; B < NY; ++B) jr[B] = act ? J[lane * NY + B] : 0.0;
+    wave_sync();
+    double myrd = 0.0;
+    chol_reg<NY>(jr, myrd);
+    const double schur = __shfl(jr[N1], N1, 64);
+    const bool drop = !(schur > kSchurDrop * Juu);
+    if (!drop && lane == N1) { jr[N1] = sqrt(schur); myrd = 1.0 / jr[N1]; }
+    const double dv = chol_solve_reg<NY>(jr, myrd, drop ? N1 : NY, act ? -Rl : 0.0, J);
+    dnew = dv;
+    slope = wave_allsum(Rl * dv);
+    tnew = 1.0;
+    ytry_new = ynew + dv;
+  }
+  // ---- write back ----
+  if (act) {
+    nsg->y[lane] = ynew;
+    nsg->ytry[lane] = ytry_new;
+    nsg->d[lane] = dnew;
+  }
+  const double alpha_new = __shfl(ynew, N1, 64);
+  if (lane == 0) {
+    if (accept) { nsg->E = Etry; nsg->Escale = Stry; }
+    nsg->t = tnew;
+    nsg->slope = slope;
+    nsg->halvings = halvings;
+    nsg->passes = passes + 1;
+    nsg->iter = iter + (newdir ? 1 : 0);
+    nsg->done = done;
+    nsg->ok = ok;
+    if (done) {
+      const int k = nsg->level - 1;
+      rep->newton_iters[k] = iter;
+      rep->newton_total[k] += iter;
+      rep->alpha[k] = alpha_new;
+      if (!finite) report_status(rep, FMG_E_NONFINITE);
+      else if (!ok) report_status(rep, FMG_E_NOT_CONVERGED);
+    }
+  }
+}
+
+// Algorithm 3.2, step 1 with the state in registers (see level1_newton_dev):
+// lane A owns U_A; N1 = 9 (2D) or 27 (3D), i.e. 4 coarse cells per side.
+template <int DIM, int KIND, int N1>
+__device__ __forceinline__ void level1_newton_reg(const Grid& g1, double m1, const ProblemSlot* __restrict__ slot,
+                                                  int nf1, int fs, double* __restrict__ x1,
+                                                  fmg_report* __restrict__ rep, int newton_max, double tol,
+                                                  double* sm) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  const bool node = lane < N1;
+  const int nH = g1.n, mm = nH - 1;
+  const double s1 = DIM == 2 ? 1.0 : 1.0 / nH;
+  const double q = slot->param;
+  const int A = node ? lane : 0;
+  int ax, ay, az;
+  coarse_coords<DIM>(nH, A, ax, ay, az);
+  const double G = node ? m1 * slot->g[fine_load_index(nf1, fs, ax, ay, az)] : 0.0;
+  auto energy = [&](double V, double& Eo, double& So) {
+    const double AV = stencil_shfl<DIM>(V, A, ax, ay, az, mm, node, s1);
+    double f, df, F;
+    NL<KIND>::all(V, q, f, df, F);
+    const double t1 = 0.5 * wave_allsum(node ? V * AV : 0.0);
+    const double t2 = m1 * wave_allsum(node ? F : 0.0);
+    const double t3 = wave_allsum(G * V);
+    Eo = t1 + t2 - t3;
+    So = fabs(t1) + fabs(t2) + fabs(t3);
+  };
+  double U = 0.0, E, S;
+  energy(U, E, S);
+  int it = 0, status = 0;   // 1 converged, 2 non-finite
+  for (it = 1; it <= newton_max; ++it) {
+    double f, df, F;
+    NL<KIND>::all(U, q, f, df, F);
+    const double R = node ? stencil_shfl<DIM>(U, A, ax, ay, az, mm, node, s1) + m1 * f - G : 0.0;
+    double jr[N1];
+#pragma unroll
+    for (int B = 0; B < N1; ++B) {
+      const int bx = 1 + B % 3, by = 1 + (B / 3) % 3, bz = DIM == 3 ? 1 + B / 9 : 0;
+      const int nz = abs(bx - ax) + abs(by - ay) + abs(bz - az);
+      jr[B] = !node ? 0.0 : (nz == 0 ? 2.0 * DIM * s1 + m1 * df : (nz == 1 ? -s1 : 0.0));
+    }
+    double myrd = 0.0;
+    chol_reg<N1>(jr, myrd);
+    if (lane == N1 - 1) { jr[N1 - 1] = sqrt(jr[N1 - 1]); myrd = 1.0 / jr[N1 - 1]; }
+    const double D = chol_solve_reg<N1>(jr, myrd, N1, node ? -R : 0.0, sm);
+    const double slope = wave_allsum(R * D);
+    double t = 1.0, Et = 0.0, St = 0.0, T = U;
+    for (int h = 0; h < kMaxHalvings; ++h) {
+      T = U + t * D;
+      energy(T, Et, St);
+      if (Et <= E + kArmijo * t * slope + kEnergyRounding * fmax(S, St)) break;
+      t *= 0.5;
+    }
+    const double stepmax = wave_allmax(node ? fabs(T - U) : 0.0);
+    U = T;
+    const double umax = wave_allmax(node ? fabs(U) : 0.0);
+    E = Et;
+    S = St;
+    if (!isfinite(Et)) { status = 2; break; }
+    if (stepmax <= tol * fmax(1.0, umax)) { status = 1; break; }
+  }
+  if (node) x1[gidx<DIM>(g1, ax, ay, az)] = U;
+  if (lane == 0) {
+    rep->level1_iters = status == 1 ? it : newton_max;
+    if (status != 1) report_status(rep, status == 2 ? FMG_E_NONFINITE : FMG_E_NOT_CONVERGED);
+  }
+}
+
+template <int DIM, int KIND>
+__device__ __forceinline__ void level1_dispatch(const Grid& g1, int N1, const double* __restrict__ A1g, double m1,
+                                                const ProblemSlot* __restrict__ slot, int nf1, int fs,
+                                                double* __restrict__ x1, fmg_report* __restrict__ rep,
+                                                int newton_max, double tol, double* smem) {
+  if (DIM == 2 && N1 == 9) level1_newton_reg<DIM, KIND, 9>(g1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
+  else if (DIM == 3 && N1 == 27)
+    level1_newton_reg<DIM, KIND, 27>(g1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
+  else level1_newton_dev<DIM, KIND>(g1, N1, A1g, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
+  __syncthreads();
+}
+
+// Dispatch: register-resident step for the 4-cell coarse grids, LDS step otherwise.
+template <int DIM>
+__device__ __forceinline__ void newton_step_dev(const AugShape& s, const double* cs, const double* __restrict__ A1,
+                                                double m, NewtonState* ns, fmg_report* rep, int newton_max,
+                                                double tol, double* sm) {
+  if (DIM == 2 && s.N1 == 9) newton_core_reg<DIM, 10>(s, cs, m, ns, rep, newton_max, tol, sm);
+  else if (DIM == 3 && s.N1 == 27) newton_core_reg<DIM, 28>(s, cs, m, ns, rep, newton_max, tol, sm);
+  else newton_core<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
+}
+
+template <int DIM, int KIND>
+__global__ void __launch_bounds__(256) k_level1_newton(Grid g1, int N1, const double* __restrict__ A1, double m1,
+                                                       const ProblemSlot* __restrict__ slot, int nf1, int fs,
+                                                       double* __restrict__ x1, fmg_report* __restrict__ rep,
+                                                       int newton_max, double tol) {
+  extern __shared__ double smem[];
+  level1_dispatch<DIM, KIND>(g1, N1, A1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
+}
+
+}  // namespace fmg

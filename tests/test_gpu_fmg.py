@@ -211,3 +211,14 @@ def test_tail_kernel_matches_grid_launches(P, precision):
     u_grid, r2 = gpu_solve(P, precision=precision, tail_max_nodes=0)
     assert r1["status"] == 0 and r2["status"] == 0
     assert rel(u_tail, u_grid) <= (1e-13 if precision == B.FMG_FP64 else 1e-9)
+
+
+@pytest.mark.parametrize("blocks", [64, 16384])
+def test_quadrature_block_count_does_not_change_result(blocks):
+    """Splitting the fine quadrature over more or fewer workgroups only changes
+    the (fixed) summation order."""
+    P = W.square_cubic_sin_expx(6)
+    u, rep = gpu_solve(P, aug_max_blocks=blocks)
+    u0, _ = gpu_solve(P)
+    assert rep["status"] == 0
+    assert rel(u, u0) <= 1e-12
