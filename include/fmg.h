@@ -106,6 +106,9 @@ typedef struct {
                               steps, incl. the Newton solves) in one launch */
     int aug_max_blocks; /* workgroups per fine quadrature pass of the augmented
                            problem (upper bound; 64..16384)                  */
+    int aug_small_nodes; /* levels with at most this many interior nodes solve
+                            the augmented problem in one single-workgroup
+                            launch (0: never)                                */
 } fmg_options;
 
 typedef struct {

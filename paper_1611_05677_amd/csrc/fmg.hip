@@ -73,7 +73,7 @@ int resolve(int dim, const fmg_options* in, Resolved& r) {
   if (o.mode != FMG_PAPER && o.mode != FMG_CONVERGED) return FMG_E_INVALID;
   if (o.mode == FMG_CONVERGED && (o.converged_max_steps < 1 || !(o.converged_tol > 0))) return FMG_E_INVALID;
   if (o.tail_max_nodes < 0 || (o.fuse_small_levels != 0 && o.fuse_small_levels != 1)) return FMG_E_INVALID;
-  if (o.aug_max_blocks < 64 || o.aug_max_blocks > 16384) return FMG_E_INVALID;
+  if (o.aug_max_blocks < 64 || o.aug_max_blocks > 16384 || o.aug_small_nodes < 0) return FMG_E_INVALID;
   r.o = o;
   r.smoother = o.smoother ? o.smoother : (dim == 2 ? FMG_JACOBI : FMG_CHEBYSHEV);
   if (r.smoother == FMG_JACOBI) {
@@ -202,14 +202,14 @@ enum KernelClass {
   KC_SMOOTH32, KC_SMOOTH32_ZERO, KC_RESTRICT32, KC_PROLONG32_ADD, KC_COARSE32,
   KC_TRANSITION, KC_RHS, KC_RESID_F32, KC_ADD_F32, KC_AUG_PASS0, KC_AUG_PASS, KC_OUTPUT_UPDATE,
   KC_NEWTON_FINISH, KC_AUG_UPDATE, KC_LEVEL1, KC_BEGIN, KC_OUTPUT, KC_END, KC_FILL,
-  KC_VCYCLE_TAIL64, KC_VCYCLE_TAIL32, KC_FMG_TAIL, KC_PRE2D64, KC_POST2D64, KC_PRE2D32, KC_POST2D32, KC_COUNT
+  KC_VCYCLE_TAIL64, KC_VCYCLE_TAIL32, KC_FMG_TAIL, KC_AUG_SMALL, KC_PRE2D64, KC_POST2D64, KC_PRE2D32, KC_POST2D32, KC_COUNT
 };
 const char* const kKernelNames[KC_COUNT] = {
   "smooth_f64", "smooth_f64_from_zero", "resid_restrict_f64", "prolong_add_f64", "coarse_solve_f64",
   "smooth_f32", "smooth_f32_from_zero", "resid_restrict_f32", "prolong_add_f32", "coarse_solve_f32",
   "transition", "rhs", "resid_to_f32", "add_f32", "aug_pass0_setup", "aug_pass", "output_update",
   "newton_finish", "aug_update", "level1_newton", "begin_solve", "output", "end_solve", "fill",
-  "vcycle_tail_f64", "vcycle_tail_f32", "fmg_tail", "pre_sweeps_restrict_2d_f64", "prolong_post_sweeps_2d_f64",
+  "vcycle_tail_f64", "vcycle_tail_f32", "fmg_tail", "aug_solve_small", "pre_sweeps_restrict_2d_f64", "prolong_post_sweeps_2d_f64",
   "pre_sweeps_restrict_2d_f32", "prolong_post_sweeps_2d_f32"};
 
 // Event pairs around launches (fmg_profile_solve only).
@@ -437,6 +437,14 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   unsigned* ticket = h->at<unsigned>(p.off_ticket);
   double* cellsum = h->at<double>(p.off_cellsum);
   const double* A1 = h->at<double>(p.off_A1);
+  if (N <= o.aug_small_nodes) {
+    // the whole augmented solve (and the update unless deferred) by one workgroup
+    FMG_LAUNCH(h, st, KC_AUG_SMALL, k, N, 0.0,
+               (k_aug_solve_small<DIM, KIND><<<1, kTailThreads, fmg_tail_lds_bytes(p), st>>>(
+                   L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), k, o.newton_max,
+                   o.newton_tol, defer_update ? 0 : 1)));
+    return;
+  }
   const size_t lds = aug_pass_lds_bytes(p);
   FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
              (k_aug_pass<DIM, KIND, true><<<L.aug_blocks, kBlock, lds, st>>>(
@@ -626,6 +634,7 @@ void fmg_default_options(int dim, fmg_options* o) {
   o->tail_max_nodes = 1024;
   o->fuse_small_levels = 0;
   o->aug_max_blocks = 512;
+  o->aug_small_nodes = 4096;
   (void)dim;
 }
 

@@ -137,14 +137,45 @@ template <int DIM> struct Acc {
 };
 
 // ---------------------------------------------------------------------------
-// Reductions: wave64 shuffle tree, then LDS across the block's waves.  The
-// order of additions is fixed by the launch shape, so results are bitwise
-// reproducible run to run.
+// Cross-lane operations on doubles.  Reductions use DPP data movement (VALU
+// operands permuted within quads, rotated within 16-lane rows, and broadcast
+// from row to row) instead of LDS-routed shuffles; broadcasts from a fixed
+// lane use v_readlane.  All 64 lanes must be active.  The order of additions
+// is fixed, so results are bitwise reproducible run to run.
 // ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, returned to every lane.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
+  v += dpp_move<0xb1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);         // quad_perm [2,3,0,1]: quad sums
+  v += dpp_move<0x124>(v);        // row_ror 4
+  v += dpp_move<0x128>(v);        // row_ror 8: 16-lane row sums in every lane
+  v += dpp_move<0x142, 0xa>(v);   // row_bcast 15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);   // row_bcast 31 into rows 2 and 3: lane 63 holds the total
+  return lane_value(v, 63);
+}
+
+// Maximum over the 64 lanes (inputs >= 0), returned to every lane.
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+  v = fmax(v, dpp_move<0xb1>(v));
+  v = fmax(v, dpp_move<0x4e>(v));
+  v = fmax(v, dpp_move<0x124>(v));
+  v = fmax(v, dpp_move<0x128>(v));
+  v = fmax(v, dpp_move<0x142, 0xa>(v));
+  v = fmax(v, dpp_move<0x143, 0xc>(v));
+  return lane_value(v, 63);
 }
 
 // Sum NACC per-thread accumulators over the block; thread t < NACC receives

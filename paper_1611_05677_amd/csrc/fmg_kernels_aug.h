@@ -228,13 +228,13 @@ __device__ __forceinline__ void chol_solve_wave(const double* __restrict__ L, co
   for (int j = 0; j < nn; ++j) {
     const double lij = (lane > j && lane < nn) ? L[lane * n + j] : 0.0;
     if (lane == j) v *= rdiag[j];
-    const double xj = __shfl(v, j, 64);
+    const double xj = lane_value(v, j);
     v -= lij * xj;
   }
   for (int j = nn - 1; j >= 0; --j) {
     const double lji = lane < j ? L[j * n + lane] : 0.0;
     if (lane == j) v *= rdiag[j];
-    const double xj = __shfl(v, j, 64);
+    const double xj = lane_value(v, j);
     v -= lji * xj;
   }
   if (lane < nn) x[lane] = v;
@@ -251,12 +251,8 @@ __device__ __forceinline__ void wave_copy(S* dst, const S* src) {
   for (int i = threadIdx.x; i < (int)(sizeof(S) / 8); i += 64) b[i] = a[i];
 }
 
-__device__ __forceinline__ double wave_allsum(double v) { return __shfl(wave_sum(v), 0, 64); }
-__device__ __forceinline__ double wave_allmax(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-  return __shfl(v, 0, 64);
-}
+__device__ __forceinline__ double wave_allsum(double v) { return wave_sum(v); }
+__device__ __forceinline__ double wave_allmax(double v) { return wave_max_nonneg(v); }
 
 // LDS doubles newton_core needs besides the per-cell sums.
 __host__ __device__ constexpr int newton_scratch_doubles(int N1) {
@@ -419,8 +415,8 @@ __device__ __forceinline__ void newton_core(const AugShape& s, const double* cs,
     }
     ns->passes = passes + 1;
   }
-  done = __shfl(done, 0, 64);
-  ok = __shfl(ok, 0, 64);
+  done = __builtin_amdgcn_readlane(done, 0);
+  ok = __builtin_amdgcn_readlane(ok, 0);
   if (lane == 0) {
     ns->done = done;
     ns->ok = ok;

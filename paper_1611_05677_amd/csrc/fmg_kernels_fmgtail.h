@@ -81,7 +81,7 @@ template <int DIM, int KIND>
 __device__ __forceinline__ void aug_solve_dev(const Grid& g, const AugShape& s, double* __restrict__ ut,
                               const ProblemSlot* __restrict__ slot, int nf1, int fs, double scale, double m,
                               const double* __restrict__ A1, NewtonState* ns, fmg_report* rep, int level,
-                              int newton_max, double tol, double* smem) {
+                              int newton_max, double tol, double* smem, bool do_update = true) {
   using AC = Acc<DIM>;
   const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
   double* cs = smem;
@@ -97,6 +97,7 @@ __device__ __forceinline__ void aug_solve_dev(const Grid& g, const AugShape& s, 
     newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   }
   __syncthreads();
+  if (!do_update) return;
   const int total = interior_count<DIM>(g);
   const int mm = g.n - 1;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
@@ -104,6 +105,21 @@ __device__ __forceinline__ void aug_solve_dev(const Grid& g, const AugShape& s, 
     update_node<DIM>(g, s, ns, ut, i, j, l);
   }
   __syncthreads();
+}
+
+// The augmented problem of one correction step on a small level, solved by
+// one workgroup in one launch (setup sums, every Newton iteration, and the
+// update unless the caller defers it).
+template <int DIM, int KIND>
+__global__ void __launch_bounds__(kTailThreads) k_aug_solve_small(Grid g, AugShape s, double* __restrict__ ut,
+                                                                  const ProblemSlot* __restrict__ slot, int nf1,
+                                                                  int fs, double scale, double m,
+                                                                  const double* __restrict__ A1, NewtonState* ns,
+                                                                  fmg_report* rep, int level, int newton_max,
+                                                                  double tol, int do_update) {
+  extern __shared__ double smem[];
+  aug_solve_dev<DIM, KIND>(g, s, ut, slot, nf1, fs, scale, m, A1, ns, rep, level, newton_max, tol, smem,
+                           do_update != 0);
 }
 
 template <int DIM, int KIND, bool MIXED>

@@ -35,7 +35,7 @@ __device__ __forceinline__ void chol_reg(double (&jr)[NY], double& myrd) {
   const int lane = threadIdx.x;
 #pragma unroll
   for (int k = 0; k < NY - 1; ++k) {
-    const double dkk = __shfl(jr[k], k, 64);
+    const double dkk = lane_value(jr[k], k);
     const double sk = sqrt(dkk);
     const double rk = 1.0 / sk;
     const double lik = lane > k ? jr[k] * rk : 0.0;
@@ -43,7 +43,7 @@ __device__ __forceinline__ void chol_reg(double (&jr)[NY], double& myrd) {
     if (lane > k) jr[k] = lik;
 #pragma unroll
     for (int j = k + 1; j < NY; ++j) {
-      const double ljk = __shfl(lik, j, 64);
+      const double ljk = lane_value(lik, j);
       if (lane >= j) jr[j] -= lik * ljk;
     }
   }
@@ -66,7 +66,7 @@ __device__ __forceinline__ double chol_solve_reg(const double (&jr)[NY], double 
   for (int j = 0; j < NY; ++j) {
     if (j < nn) {
       if (lane == j) v *= myrd;
-      const double xj = __shfl(v, j, 64);
+      const double xj = lane_value(v, j);
       if (lane > j && lane < nn) v -= jr[j] * xj;
     }
   }
@@ -74,7 +74,7 @@ __device__ __forceinline__ double chol_solve_reg(const double (&jr)[NY], double 
   for (int j = NY - 1; j >= 0; --j) {
     if (j < nn) {
       if (lane == j) v *= myrd;
-      const double xj = __shfl(v, j, 64);
+      const double xj = lane_value(v, j);
       if (lane < j) v -= colr[j] * xj;
     }
   }
@@ -117,7 +117,7 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
   const double gh = node ? nsg->GH[lane] : 0.0;
   const double c = nsg->c, Gu = nsg->Gu, E = nsg->E, Escale = nsg->Escale, slope0 = nsg->slope, t = nsg->t;
   const int iter = nsg->iter, passes = nsg->passes;
-  const double alpha = __shfl(yt, N1, 64);
+  const double alpha = lane_value(yt, N1);
   const double w = node ? yt : 0.0;
   const int A = node ? lane : 0;
   int ax, ay, az;
@@ -213,7 +213,7 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
     {
 #pragma unroll
       for (int B = 0; B < N1; ++B) {
-        const double v = __shfl(jAu, B, 64);
+        const double v = lane_value(jAu, B);
         if (lane == N1) J[N1 * NY + B] = v;
       }
       if (lane == N1) J[N1 * NY + N1] = Juu;
@@ -225,7 +225,7 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
     wave_sync();
     double myrd = 0.0;
     chol_reg<NY>(jr, myrd);
-    const double schur = __shfl(jr[N1], N1, 64);
+    const double schur = lane_value(jr[N1], N1);
     const bool drop = !(schur > kSchurDrop * Juu);
     if (!drop && lane == N1) { jr[N1] = sqrt(schur); myrd = 1.0 / jr[N1]; }
     const double dv = chol_solve_reg<NY>(jr, myrd, drop ? N1 : NY, act ? -Rl : 0.0, J);
@@ -240,7 +240,7 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
     nsg->ytry[lane] = ytry_new;
     nsg->d[lane] = dnew;
   }
-  const double alpha_new = __shfl(ynew, N1, 64);
+  const double alpha_new = lane_value(ynew, N1);
   if (lane == 0) {
     if (accept) { nsg->E = Etry; nsg->Escale = Stry; }
     nsg->t = tnew;
