@@ -108,7 +108,10 @@ typedef struct {
                            problem (upper bound; 64..16384)                  */
     int aug_small_nodes; /* levels with at most this many interior nodes solve
                             the augmented problem in one single-workgroup
-                            launch (0: never)                                */
+                            launch (0: never; default 4096 in 2D, 0 in 3D)   */
+    int sweep_rows;     /* 2D V(2,2) levels: rows marched by each wavefront of
+                           the register-streaming level kernels (4..4096);
+                           0 = chosen per level; -1 = LDS-tiled kernels     */
 } fmg_options;
 
 typedef struct {

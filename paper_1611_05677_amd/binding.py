@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
                 ("converged_max_steps", ctypes.c_int), ("converged_tol", ctypes.c_double),
                 ("use_graph", ctypes.c_int), ("tail_max_nodes", ctypes.c_int),
                 ("fuse_small_levels", ctypes.c_int), ("aug_max_blocks", ctypes.c_int),
-                ("aug_small_nodes", ctypes.c_int)]
+                ("aug_small_nodes", ctypes.c_int), ("sweep_rows", ctypes.c_int)]
 
 
 class ProblemC(ctypes.Structure):

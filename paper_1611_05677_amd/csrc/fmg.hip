@@ -17,6 +17,7 @@
 #include "fmg_kernels_tail.h"
 #include "fmg_kernels_fmgtail.h"
 #include "fmg_kernels_fused2d.h"
+#include "fmg_kernels_stream2d.h"
 #include "fmg_newton_reg.h"
 
 using namespace fmg;
@@ -74,6 +75,7 @@ int resolve(int dim, const fmg_options* in, Resolved& r) {
   if (o.mode == FMG_CONVERGED && (o.converged_max_steps < 1 || !(o.converged_tol > 0))) return FMG_E_INVALID;
   if (o.tail_max_nodes < 0 || (o.fuse_small_levels != 0 && o.fuse_small_levels != 1)) return FMG_E_INVALID;
   if (o.aug_max_blocks < 64 || o.aug_max_blocks > 16384 || o.aug_small_nodes < 0) return FMG_E_INVALID;
+  if (o.sweep_rows < -1 || (o.sweep_rows > 0 && o.sweep_rows < 4) || o.sweep_rows > 4096) return FMG_E_INVALID;
   r.o = o;
   r.smoother = o.smoother ? o.smoother : (dim == 2 ? FMG_JACOBI : FMG_CHEBYSHEV);
   if (r.smoother == FMG_JACOBI) {
@@ -202,7 +204,8 @@ enum KernelClass {
   KC_SMOOTH32, KC_SMOOTH32_ZERO, KC_RESTRICT32, KC_PROLONG32_ADD, KC_COARSE32,
   KC_TRANSITION, KC_RHS, KC_RESID_F32, KC_ADD_F32, KC_AUG_PASS0, KC_AUG_PASS, KC_OUTPUT_UPDATE,
   KC_NEWTON_FINISH, KC_AUG_UPDATE, KC_LEVEL1, KC_BEGIN, KC_OUTPUT, KC_END, KC_FILL,
-  KC_VCYCLE_TAIL64, KC_VCYCLE_TAIL32, KC_FMG_TAIL, KC_AUG_SMALL, KC_PRE2D64, KC_POST2D64, KC_PRE2D32, KC_POST2D32, KC_COUNT
+  KC_VCYCLE_TAIL64, KC_VCYCLE_TAIL32, KC_FMG_TAIL, KC_AUG_SMALL, KC_PRE2D64, KC_POST2D64, KC_PRE2D32, KC_POST2D32,
+  KC_PRE2S64, KC_POST2S64, KC_PRE2S32, KC_POST2S32, KC_COUNT
 };
 const char* const kKernelNames[KC_COUNT] = {
   "smooth_f64", "smooth_f64_from_zero", "resid_restrict_f64", "prolong_add_f64", "coarse_solve_f64",
@@ -210,7 +213,9 @@ const char* const kKernelNames[KC_COUNT] = {
   "transition", "rhs", "resid_to_f32", "add_f32", "aug_pass0_setup", "aug_pass", "output_update",
   "newton_finish", "aug_update", "level1_newton", "begin_solve", "output", "end_solve", "fill",
   "vcycle_tail_f64", "vcycle_tail_f32", "fmg_tail", "aug_solve_small", "pre_sweeps_restrict_2d_f64", "prolong_post_sweeps_2d_f64",
-  "pre_sweeps_restrict_2d_f32", "prolong_post_sweeps_2d_f32"};
+  "pre_sweeps_restrict_2d_f32", "prolong_post_sweeps_2d_f32",
+  "pre_sweeps_restrict_2d_stream_f64", "prolong_post_sweeps_2d_stream_f64",
+  "pre_sweeps_restrict_2d_stream_f32", "prolong_post_sweeps_2d_stream_f32"};
 
 // Event pairs around launches (fmg_profile_solve only).
 struct Prof {
@@ -336,8 +341,26 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
     // correction + two sweeps (each writes the spare array: one role swap)
     const LevelInfo& C = p.lev[k - 1];
     const long long Nc = interior(C.g, DIM);
-    const dim3 tiles((L.g.n + kFTX - 1) / kFTX, (L.g.n + kFTY - 1) / kFTY);
     const int kc2 = Sel<T>::kc ? (KC_PRE2D32 - KC_PRE2D64) : 0;
+    const int rows = stream_rows(h->ro.o.sweep_rows, L.g.n);
+    if (rows > 0) {
+      int nch_pre = 0, nch_post = 0;
+      const int gpre = stream_blocks(L.g.n, kPreStrip, rows, nch_pre);
+      const int gpost = stream_blocks(L.g.n, kPostStrip, rows, nch_post);
+      FMG_LAUNCH(h, st, KC_PRE2S64 + kc2, k, N, s * ((zero_init ? 2 : 3) * N + Nc),
+                 k_pre2s<T><<<gpre, 64 * kStreamWaves, 0, st>>>(
+                     L.g, C.g, x, b, t, Sel<T>::b(h, k - 1), (T)(h->ro.pre[0] / D), (T)(h->ro.pre[1] / D), scale,
+                     zero_init ? 1 : 0, rows, nch_pre));
+      std::swap(x, t);
+      vcycle<DIM, T>(h, R, k - 1, true, st);
+      FMG_LAUNCH(h, st, KC_POST2S64 + kc2, k, N, s * (3 * N + Nc),
+                 k_post2s<T><<<gpost, 64 * kStreamWaves, 0, st>>>(C.g, L.g, x, Sel<T>::x(R, k - 1), b, t,
+                                                                   (T)(h->ro.post[0] / D),
+                                                                   (T)(h->ro.post[1] / D), scale, rows, nch_post));
+      std::swap(x, t);
+      return;
+    }
+    const dim3 tiles((L.g.n + kFTX - 1) / kFTX, (L.g.n + kFTY - 1) / kFTY);
     FMG_LAUNCH(h, st, KC_PRE2D64 + kc2, k, N, s * ((zero_init ? 2 : 3) * N + Nc),
                k_pre2d<T><<<tiles, kBlock, pre2d_lds_bytes<T>(), st>>>(
                    L.g, C.g, x, b, t, Sel<T>::b(h, k - 1), (T)(h->ro.pre[0] / D), (T)(h->ro.pre[1] / D), scale,
@@ -634,8 +657,10 @@ void fmg_default_options(int dim, fmg_options* o) {
   o->tail_max_nodes = 1024;
   o->fuse_small_levels = 0;
   o->aug_max_blocks = 512;
-  o->aug_small_nodes = 4096;
-  (void)dim;
+  // the single-workgroup augmented solve pays off for the 10 unknowns of the
+  // 2D problem; the 28 of 3D run faster through the multi-workgroup passes
+  o->aug_small_nodes = dim == 2 ? 4096 : 0;
+  o->sweep_rows = 0;
 }
 
 size_t fmg_workspace_bytes(const fmg_mesh_desc* mesh, const fmg_options* opts) {

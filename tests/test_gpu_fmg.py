@@ -222,3 +222,30 @@ def test_quadrature_block_count_does_not_change_result(blocks):
     u0, _ = gpu_solve(P)
     assert rep["status"] == 0
     assert rel(u, u0) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", [B.FMG_FP64, B.FMG_MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("rows", [4, 12, 37, 4096])
+def test_streaming_level_kernels_match_lds_tiles(precision, rows):
+    """The register-streaming 2D level kernels (any rows per wavefront,
+    including chunks that end in a ragged tail and levels narrower than one
+    strip) compute the same V-cycles as the LDS-tiled kernels: to float64
+    rounding, or in mixed mode to float32 rounding of the corrections."""
+    P = W.square_cubic_sin_expx(7)
+    u_s, r1 = gpu_solve(P, precision=precision, sweep_rows=rows, tail_max_nodes=0)
+    u_t, r2 = gpu_solve(P, precision=precision, sweep_rows=-1, tail_max_nodes=0)
+    assert r1["status"] == 0 and r2["status"] == 0
+    assert rel(u_s, u_t) <= (1e-13 if precision == B.FMG_FP64 else 1e-9)
+    if precision == B.FMG_FP64 and rows == 12:
+        expect = o2_fmg(o2_hier(P), P.g_nodes, Nonlinearity(P.f_kind, P.f_param)).full()
+        assert rel(u_s, expect) <= PARITY
+
+
+def test_streaming_kernels_on_wide_level_match_replica():
+    """Default launch shape on a level wide enough to use several strips and
+    row chunks (n = 512, 2D), against the oracle's replica."""
+    P = W.fourier_problem("wide", 2, 4, 7, W.F_CUBIC, [6, 1])
+    u, rep = gpu_solve(P)
+    assert rep["status"] == 0
+    expect = o2_fmg(o2_hier(P), P.g_nodes, Nonlinearity(P.f_kind)).full()
+    assert rel(u, expect) <= PARITY
