@@ -161,11 +161,17 @@ int fmg_solve(fmg_hierarchy *h, const fmg_problem *prob, double *d_u_out,
 /* Copy the report of the last solve to host memory (synchronises `stream`). */
 int fmg_get_report(fmg_hierarchy *h, fmg_report *host_report, void *stream);
 
-/* Solve `count` independent problems, each on its own hierarchy (distinct
- * workspaces, any mix of depths, dimensions and nonlinearities), with the
- * launches of all of them interleaved phase by phase on one stream so that
- * their work overlaps on the device.  outs[i] and reports[i] as in fmg_solve
- * (reports may be NULL). */
+/* Solve `count` independent problems, each on its own hierarchy (any mix of
+ * depths, dimensions and nonlinearities), as ONE graph launch on `stream`:
+ * the graph holds one branch per problem (its captured solve), and the
+ * branches share no memory, so the device runs them side by side.  The
+ * executable graph is cached per list of (hierarchy, nonlinearity) pairs
+ * (a few lists are kept; fmg_destroy of a member drops them), so repeated
+ * batches over the same hierarchies only update the problem arguments.
+ * outs[i] and reports[i] as in fmg_solve (reports may be NULL).
+ * Errors: FMG_E_INVALID for NULL arguments, a hierarchy or output listed
+ * twice; problem errors as in fmg_solve.  Hierarchies in FMG_CONVERGED mode
+ * or without graphs make the call solve the list one after another. */
 int fmg_solve_batch(fmg_hierarchy *const *hs, const fmg_problem *probs,
                     double *const *outs, fmg_report *const *reports, int count,
                     void *stream);

@@ -189,22 +189,26 @@ class Hierarchy:
         k = self.levels if level is None else level
         return (self.coarse_cells * 2 ** (k - 1) + 1) ** self.dim
 
-    def solve_async(self, g, kind: int, param: float = 0.0, out=None, report_ptr: int = 0):
-        """Enqueue one solve on the stream; returns the output tensor."""
+    def solve_async(self, g, kind: int, param: float = 0.0, out=None, report_ptr: int = 0, stream=None):
+        """Enqueue one solve on `stream` (default: the hierarchy's stream, else
+        torch's current one); returns the output tensor."""
         import torch
         if out is None:
             out = torch.empty(self.nodes(), dtype=torch.float64, device=g.device)
         if g.dtype != torch.float64 or not g.is_contiguous() or g.numel() != self.nodes():
             raise ValueError("g must be a contiguous float64 tensor with (n+1)^d entries")
         prob = ProblemC(int(kind), float(param), ctypes.c_void_p(g.data_ptr()))
+        st = stream if stream is not None else self.stream
         _check(LIB.fmg_solve(self.handle, ctypes.byref(prob), ctypes.c_void_p(out.data_ptr()),
-                             ctypes.c_void_p(report_ptr), ctypes.c_void_p(_stream_ptr(self.stream))),
+                             ctypes.c_void_p(report_ptr), ctypes.c_void_p(_stream_ptr(st))),
                "fmg_solve")
         return out
 
-    def report(self) -> dict:
+    def report(self, stream=None) -> dict:
+        """Report of the last solve (synchronises `stream`)."""
         r = Report()
-        _check(LIB.fmg_get_report(self.handle, ctypes.byref(r), ctypes.c_void_p(_stream_ptr(self.stream))),
+        st = stream if stream is not None else self.stream
+        _check(LIB.fmg_get_report(self.handle, ctypes.byref(r), ctypes.c_void_p(_stream_ptr(st))),
                "fmg_get_report")
         return r.as_dict()
 
@@ -236,7 +240,8 @@ class Hierarchy:
 
 
 def solve_batch(hs: list, gs: list, kinds: list, params: list, outs: list, stream=None):
-    """Enqueue several independent solves, interleaved on one stream."""
+    """Enqueue several independent solves (distinct hierarchies and outputs) as
+    one graph launch on `stream`; the solves run side by side on the device."""
     n = len(hs)
     H = (ctypes.c_void_p * n)(*[h.handle for h in hs])
     P = (ProblemC * n)(*[ProblemC(int(k), float(p), ctypes.c_void_p(g.data_ptr()))

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -181,9 +182,6 @@ struct fmg_hierarchy {
   size_t ws_bytes;
   hipStream_t cap_stream;
   hipGraphExec_t graph[7];
-  // final roles of the level buffers after a recorded solve (x = current iterate)
-  double* x_final[FMG_MAX_LEVELS + 1];
-  double* t_final[FMG_MAX_LEVELS + 1];
   Prof* prof;              // set only while fmg_profile_solve records
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   NewtonState* ns() const { return at<NewtonState>(plan.off_state); }
@@ -633,6 +631,111 @@ void build_level1(const Plan& p, std::vector<double>& A, std::vector<double>& Ai
 
 }  // namespace
 
+namespace {
+
+// Capture the solve for nonlinearity `kind` once (paper mode) and keep both the
+// graph and its executable form.
+int ensure_graph(fmg_hierarchy* h, int kind) {
+  if (h->graph[kind]) return FMG_OK;
+  const Plan& p = h->plan;
+  record_fn rec = p.dim == 2 ? pick_record<2>(kind) : pick_record<3>(kind);
+  Roles R;
+  canonical_roles(h, R);
+  hipGraph_t graph;
+  if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return FMG_E_HIP;
+  rec(h, R, true, h->cap_stream);
+  if (hipStreamEndCapture(h->cap_stream, &graph) != hipSuccess) return FMG_E_HIP;
+  hipGraphExec_t ex;
+  const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return FMG_E_HIP;
+  h->graph[kind] = ex;
+  return FMG_OK;
+}
+
+// Batched solves: one executable graph per distinct (hierarchies, kinds)
+// list.  It is captured from one fork-join recording: a root kernel copies
+// each problem's slot from a small device table, then every hierarchy records
+// its solve on its own capture stream, so the graph holds one independent
+// branch per problem.  Branches share no memory and the device runs them side
+// by side.  Later calls with the same list refresh the table (one small
+// host-to-device copy, stream-ordered before the launch) and launch again.
+struct SlotDesc {
+  ProblemSlot* slot;
+  const double* g;
+  double* out;
+  fmg_report* rep;
+  double param;
+  int kind;
+  int pad;
+};
+
+__global__ void k_set_slots(const SlotDesc* __restrict__ d, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    ProblemSlot* s = d[i].slot;
+    s->g = d[i].g; s->u_out = d[i].out; s->rep_out = d[i].rep; s->param = d[i].param; s->kind = d[i].kind;
+  }
+}
+
+struct BatchGraph {
+  std::vector<fmg_hierarchy*> hs;
+  std::vector<int> kinds;
+  std::vector<SlotDesc> host;
+  SlotDesc* table = nullptr;       // device copy of `host`
+  hipGraphExec_t exec = nullptr;
+  unsigned long long stamp = 0;
+};
+std::mutex g_batch_mu;
+std::vector<BatchGraph*> g_batches;
+unsigned long long g_batch_clock = 0;
+constexpr size_t kBatchCacheMax = 8;
+
+void destroy_batch(BatchGraph* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->table) (void)hipFree(b->table);
+  delete b;
+}
+
+int build_batch(BatchGraph* b) {
+  const int count = (int)b->hs.size();
+  if (hipMalloc(&b->table, sizeof(SlotDesc) * count) != hipSuccess) { b->table = nullptr; return FMG_E_HIP; }
+  hipStream_t s0;
+  if (hipStreamCreateWithFlags(&s0, hipStreamNonBlocking) != hipSuccess) return FMG_E_HIP;
+  std::vector<hipEvent_t> ev(count + 1, nullptr);
+  int st = FMG_OK;
+  for (auto& e : ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { e = nullptr; st = FMG_E_HIP; }
+  hipGraph_t graph = nullptr;
+  if (st == FMG_OK && hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    k_set_slots<<<1, 64, 0, s0>>>(b->table, count);
+    (void)hipEventRecord(ev[count], s0);
+    for (int i = 0; i < count; ++i) {
+      fmg_hierarchy* h = b->hs[i];
+      (void)hipStreamWaitEvent(h->cap_stream, ev[count], 0);
+      record_fn rec = h->plan.dim == 2 ? pick_record<2>(b->kinds[i]) : pick_record<3>(b->kinds[i]);
+      Roles R;
+      canonical_roles(h, R);
+      rec(h, R, true, h->cap_stream);
+      (void)hipEventRecord(ev[i], h->cap_stream);
+      (void)hipStreamWaitEvent(s0, ev[i], 0);
+    }
+    if (hipStreamEndCapture(s0, &graph) != hipSuccess) { graph = nullptr; st = FMG_E_HIP; }
+  } else {
+    st = FMG_E_HIP;
+  }
+  if (st == FMG_OK && hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    b->exec = nullptr;
+    st = FMG_E_HIP;
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  (void)hipStreamDestroy(s0);
+  return st;
+}
+
+}  // namespace
+
 extern "C" {
 
 void fmg_default_options(int dim, fmg_options* o) {
@@ -762,18 +865,8 @@ int fmg_solve(fmg_hierarchy* h, const fmg_problem* prob, double* d_u_out, fmg_re
   Roles R;
   canonical_roles(h, R);
   if (o.mode == FMG_PAPER && o.use_graph) {
-    hipGraphExec_t& ex = h->graph[prob->kind];
-    if (!ex) {
-      hipGraph_t graph;
-      if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return FMG_E_HIP;
-      rec(h, R, true, h->cap_stream);
-      if (hipStreamEndCapture(h->cap_stream, &graph) != hipSuccess) return FMG_E_HIP;
-      const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) { ex = nullptr; return FMG_E_HIP; }
-      for (int k = 1; k <= p.nlev; ++k) { h->x_final[k] = R.x[k]; h->t_final[k] = R.t[k]; }
-    }
-    if (hipGraphLaunch(ex, s) != hipSuccess) return FMG_E_HIP;
+    if ((st = ensure_graph(h, prob->kind)) != FMG_OK) return st;
+    if (hipGraphLaunch(h->graph[prob->kind], s) != hipSuccess) return FMG_E_HIP;
     return hipGetLastError() == hipSuccess ? FMG_OK : FMG_E_HIP;
   }
   const bool converged = o.mode == FMG_CONVERGED;
@@ -882,17 +975,79 @@ int fmg_get_report(fmg_hierarchy* h, fmg_report* host_report, void* stream) {
 int fmg_solve_batch(fmg_hierarchy* const* hs, const fmg_problem* probs, double* const* outs,
                     fmg_report* const* reports, int count, void* stream) {
   if (count < 0 || (count > 0 && (!hs || !probs || !outs))) return FMG_E_INVALID;
+  bool graphs = true;
   for (int i = 0; i < count; ++i) {
-    const int st = fmg_solve(hs[i], &probs[i], outs[i], reports ? reports[i] : nullptr, stream);
+    if (!hs[i] || !outs[i]) return FMG_E_INVALID;
+    const int st = check_problem(&probs[i]);
     if (st != FMG_OK) return st;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i] || outs[j] == outs[i]) return FMG_E_INVALID;
+    graphs = graphs && hs[i]->ro.o.mode == FMG_PAPER && hs[i]->ro.o.use_graph;
   }
-  return FMG_OK;
+  if (count == 0) return FMG_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!graphs) {
+    for (int i = 0; i < count; ++i) {
+      const int st = fmg_solve(hs[i], &probs[i], outs[i], reports ? reports[i] : nullptr, stream);
+      if (st != FMG_OK) return st;
+    }
+    return FMG_OK;
+  }
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  BatchGraph* b = nullptr;
+  for (BatchGraph* c : g_batches) {
+    if ((int)c->hs.size() != count) continue;
+    bool same = true;
+    for (int i = 0; i < count && same; ++i) same = c->hs[i] == hs[i] && c->kinds[i] == probs[i].kind;
+    if (same) { b = c; break; }
+  }
+  if (!b) {
+    b = new (std::nothrow) BatchGraph();
+    if (!b) return FMG_E_INVALID;
+    b->hs.assign(hs, hs + count);
+    for (int i = 0; i < count; ++i) b->kinds.push_back(probs[i].kind);
+    const int st = build_batch(b);
+    if (st != FMG_OK) { destroy_batch(b); return st; }
+    if (g_batches.size() >= kBatchCacheMax) {
+      auto oldest = std::min_element(g_batches.begin(), g_batches.end(),
+                                     [](const BatchGraph* x, const BatchGraph* y) { return x->stamp < y->stamp; });
+      // the evicted graph may still run on a stream: wait for the device first
+      (void)hipDeviceSynchronize();
+      destroy_batch(*oldest);
+      g_batches.erase(oldest);
+    }
+    g_batches.push_back(b);
+  }
+  b->host.resize(count);
+  for (int i = 0; i < count; ++i) {
+    SlotDesc& d = b->host[i];
+    d.slot = hs[i]->slot(); d.g = probs[i].g_nodes; d.out = outs[i];
+    d.rep = reports ? reports[i] : nullptr; d.param = probs[i].param; d.kind = probs[i].kind; d.pad = 0;
+  }
+  if (hipMemcpyAsync(b->table, b->host.data(), sizeof(SlotDesc) * count, hipMemcpyHostToDevice, s) != hipSuccess)
+    return FMG_E_HIP;
+  b->stamp = ++g_batch_clock;
+  if (hipGraphLaunch(b->exec, s) != hipSuccess) return FMG_E_HIP;
+  return hipGetLastError() == hipSuccess ? FMG_OK : FMG_E_HIP;
 }
 
 int fmg_destroy(fmg_hierarchy* h) {
   if (!h) return FMG_E_INVALID;
+  {
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    for (size_t i = 0; i < g_batches.size();) {
+      BatchGraph* b = g_batches[i];
+      if (std::find(b->hs.begin(), b->hs.end(), h) != b->hs.end()) {
+        destroy_batch(b);
+        g_batches.erase(g_batches.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+  }
   for (auto& g : h->graph)
     if (g) (void)hipGraphExecDestroy(g);
+
   (void)hipStreamDestroy(h->cap_stream);
   delete h;
   return FMG_OK;

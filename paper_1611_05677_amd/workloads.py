@@ -224,6 +224,30 @@ def fourier_load_nodes(coef: np.ndarray, n: int) -> np.ndarray:
     raise ValueError(dim)
 
 
+def fourier_load_device(coef: np.ndarray, n: int, device, stream=None):
+    """fourier_load_nodes evaluated with torch float64 products on `device`
+    (same sums, possibly another rounding order).  Used where loads are made
+    per request on the GPU instead of being shipped from the host."""
+    import torch
+    dim = coef.ndim
+    modes = coef.shape[0]
+    t = torch.arange(n + 1, dtype=torch.float64, device=device) / n
+    k = torch.arange(1, modes + 1, dtype=torch.float64, device=device)
+    S = torch.sin(PI * torch.outer(k, t))                      # (modes, n+1)
+    C = torch.as_tensor(coef, dtype=torch.float64).to(device)
+    if dim == 2:
+        G = S.t().contiguous() @ C.t().contiguous() @ S       # (y, x)
+        return G.reshape(-1).contiguous()
+    if dim == 3:
+        m, N = modes, n + 1
+        St = S.t().contiguous()                                # (N, m)
+        X = (St @ C.reshape(m, m * m)).reshape(N, m, m)        # X[i, b, c]
+        Y = (X.permute(0, 2, 1).contiguous().reshape(N * m, m) @ S).reshape(N, m, N)   # Y[i, c, j]
+        Z = (Y.permute(0, 2, 1).contiguous().reshape(N * N, m) @ S).reshape(N, N, N)   # Z[i, j, l]
+        return Z.permute(2, 1, 0).contiguous().reshape(-1)     # (l, j, i): x fastest
+    raise ValueError(dim)
+
+
 def fourier_problem(name: str, dim: int, coarse_cells: int, refinements: int,
                     f_kind: int, seed, modes: int = 16, f_param: float = 0.0) -> Problem:
     coef = fourier_coefficients(dim, modes, seed)
@@ -274,12 +298,18 @@ def cube_example2(refinements: int) -> Problem:
 BATCH_SEED = 161105677
 
 
-def batched_problems(count: int = 64, depth_lo: int = 6, depth_hi: int = 10,
-                     seed: int = BATCH_SEED) -> list[Problem]:
+def batched_specs(count: int = 64, depth_lo: int = 6, depth_hi: int = 10,
+                  seed: int = BATCH_SEED) -> list[tuple[int, list]]:
+    """(depth, coefficient seed) of each problem of the batched workload."""
     rng = np.random.default_rng(seed)
     depths = rng.integers(depth_lo, depth_hi + 1, size=count)
-    return [fourier_problem(f"batch_{i}", 2, 4, int(depths[i]), F_CUBIC, [seed, i])
-            for i in range(count)]
+    return [(int(depths[i]), [seed, i]) for i in range(count)]
+
+
+def batched_problems(count: int = 64, depth_lo: int = 6, depth_hi: int = 10,
+                     seed: int = BATCH_SEED) -> list[Problem]:
+    return [fourier_problem(f"batch_{i}", 2, 4, d, F_CUBIC, sd)
+            for i, (d, sd) in enumerate(batched_specs(count, depth_lo, depth_hi, seed))]
 
 
 # Served workload: Poisson arrivals (rate 200/s) of mixed 2D/3D solves.

@@ -1,0 +1,123 @@
+"""Batched solves (one graph launch for many problems) and served solves
+(continuous batching over streams) through the C ABI.
+
+The kernels reduce in a fixed order, so a problem's result does not depend
+on what else runs on the device: results in a batch or in the served mix
+must equal the same problem solved alone, bit for bit."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from oracle.nonlinear import Nonlinearity  # noqa: E402
+from oracle.o2 import Hierarchy as O2H  # noqa: E402
+from oracle.o2 import fmg as o2_fmg  # noqa: E402
+from paper_1611_05677_amd import binding as B  # noqa: E402
+from paper_1611_05677_amd import serving as S  # noqa: E402
+from paper_1611_05677_amd import workloads as W  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def alone(P, precision):
+    H = B.Hierarchy(P.dim, P.coarse_cells, P.refinements, B.default_options(P.dim, precision=precision),
+                    device=DEV)
+    u, rep = H.solve(torch.from_numpy(P.g_nodes).to(DEV), P.f_kind, P.f_param)
+    H.close()
+    return u, rep
+
+
+BATCH = [W.fourier_problem("b0", 2, 4, 3, W.F_CUBIC, [5, 0]),
+         W.fourier_problem("b1", 2, 4, 6, W.F_CUBIC, [5, 1]),
+         W.fourier_problem("b2", 3, 4, 2, W.F_U_PLUS_SIN, [5, 2]),
+         W.fourier_problem("b3", 2, 4, 5, W.F_ABS_U_U, [5, 3]),
+         W.fourier_problem("b4", 3, 4, 3, W.F_CUBIC, [5, 4]),
+         W.fourier_problem("b5", 2, 4, 4, W.F_CUBIC, [5, 5])]
+
+
+@pytest.mark.parametrize("precision", [B.FMG_FP64, B.FMG_MIXED], ids=["fp64", "mixed"])
+def test_batch_equals_each_problem_alone(precision):
+    hs = [B.Hierarchy(P.dim, 4, P.refinements, B.default_options(P.dim, precision=precision), device=DEV)
+          for P in BATCH]
+    gs = [torch.from_numpy(P.g_nodes).to(DEV) for P in BATCH]
+    outs = [torch.empty(h.nodes(), dtype=torch.float64, device=DEV) for h in hs]
+    ref = [alone(P, precision)[0] for P in BATCH]
+    for rep in range(2):                      # second call: cached batch graph
+        for o in outs:
+            o.fill_(np.nan)
+        B.solve_batch(hs, gs, [P.f_kind for P in BATCH], [P.f_param for P in BATCH], outs)
+        torch.cuda.synchronize()
+        for o, r, h in zip(outs, ref, hs):
+            assert torch.equal(o, r)
+            assert h.report()["status"] == 0
+    # new loads through the cached graph
+    P2 = [W.fourier_problem(f"c{i}", P.dim, 4, P.refinements, P.f_kind, [6, i]) for i, P in enumerate(BATCH)]
+    g2 = [torch.from_numpy(P.g_nodes).to(DEV) for P in P2]
+    B.solve_batch(hs, g2, [P.f_kind for P in P2], [0.0] * len(P2), outs)
+    torch.cuda.synchronize()
+    for o, P in zip(outs, P2):
+        assert torch.equal(o, alone(P, precision)[0])
+    if precision == B.FMG_FP64:
+        P = P2[1]
+        expect = o2_fmg(O2H(2, 4, P.refinements), P.g_nodes, Nonlinearity(P.f_kind)).full()
+        u = outs[1].cpu().numpy()
+        assert np.linalg.norm(u - expect) <= 1e-10 * np.linalg.norm(expect)
+    # dropping a member invalidates the cached graph; the rest still batch
+    hs[0].close()
+    B.solve_batch(hs[1:], gs[1:], [P.f_kind for P in BATCH[1:]], [0.0] * 5, outs[1:])
+    torch.cuda.synchronize()
+    for o, r in zip(outs[1:], ref[1:]):
+        assert torch.equal(o, r)
+    for h in hs:
+        h.close()
+
+
+def test_batch_rejects_repeated_hierarchy():
+    P = BATCH[0]
+    h = B.Hierarchy(2, 4, P.refinements, device=DEV)
+    g = torch.from_numpy(P.g_nodes).to(DEV)
+    o1 = torch.empty(h.nodes(), dtype=torch.float64, device=DEV)
+    o2 = torch.empty_like(o1)
+    with pytest.raises(B.FMGError):
+        B.solve_batch([h, h], [g, g], [P.f_kind] * 2, [0.0] * 2, [o1, o2])
+    h.close()
+
+
+def test_served_results_equal_alone_and_overlap():
+    """A burst of mixed 2D/3D requests with different depths and
+    nonlinearities: admitted as slots free up, run side by side, and each
+    result is bitwise the result of the same request solved alone."""
+    trace = W.serving_trace(count=24, rate_hz=4000.0, depths2d=(3, 6), depths3d=(2, 3))
+    reqs = S.requests_from_trace(trace)
+    ex = S.DeviceExecutor(B.FMG_MIXED, DEV, max_inflight=4)
+    srv = S.Server(ex, budget_bytes=2 << 30, max_inflight=4, keep_results=True)
+    out = srv.run(reqs)
+    torch.cuda.synchronize()
+    assert all(r.status == 0 for r in out)
+    assert srv.max_concurrent >= 2
+    for r in out:
+        g = W.fourier_load_device(r.coef, 4 * 2 ** r.refinements, DEV)
+        H = B.Hierarchy(r.dim, 4, r.refinements, B.default_options(r.dim, precision=B.FMG_MIXED), device=DEV)
+        u, rep = H.solve(g, r.f_kind)
+        H.close()
+        assert rep["status"] == 0
+        assert torch.equal(u, r.result), r.rid
+    srv.close()
+
+
+def test_served_requests_wait_for_memory():
+    """A budget that holds one hierarchy at a time still serves every request."""
+    reqs = [S.ServedRequest(i, 0.0, 2, 4, W.F_CUBIC, 0.0, W.fourier_coefficients(2, 16, [7, i]))
+            for i in range(6)]
+    ex = S.DeviceExecutor(B.FMG_FP64, DEV, max_inflight=4)
+    budget = ex.footprint((2, 4))
+    srv = S.Server(ex, budget_bytes=budget, max_inflight=4, keep_results=True)
+    out = srv.run(reqs)
+    assert all(r.status == 0 for r in out)
+    assert srv.max_concurrent == 1
+    assert srv.pool.stats.peak_bytes <= budget and srv.pool.stats.created == 1
+    srv.close()
