@@ -121,28 +121,55 @@ def profile_mode(B, H, P, g, torch):
     return prof.total_ms, rows
 
 
-def roofline_from_profile(rows, finest):
-    """Dominant bandwidth kernel (most event time among the kernels that stream
-    nodal arrays) and its launches on the finest level."""
-    by_kernel, streaming = {}, {}
+# dominant streaming kernel per dimension (the V-cycle level kernel that moves
+# the most bytes) and the source file that defines it
+ROOF_KERNEL = {2: ("pre_sweeps_restrict_2d_stream_f64", "fmg_kernels_stream2d.h"),
+               3: ("smooth_f64", "fmg_kernels_mg.h")}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+
+
+def kernel_source_hash(fname):
+    import hashlib
+    path = os.path.join(ROOT, "paper_1611_05677_amd", "csrc", fname)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, fname):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current source of the kernel."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    for e in rec.get("entries", []):
+        if e["kernel"] == kernel and e["workload"] == workload and e["source_sha256_16"] == kernel_source_hash(fname):
+            return e["hbm_bytes_per_launch"]
+    return None
+
+
+def roofline_live(B, H, dim, workload, reps, stream=None):
+    """Mean launch duration of the dominant kernel at the finest level, timed
+    with HIP events around `reps` back-to-back launches on the bench stream."""
+    name, fname = ROOF_KERNEL[dim]
+    ms, nbytes = B.time_level_kernel(H, name, H.levels, reps, stream)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(name, workload, fname)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": name, "level": H.levels,
+            "launches_timed": reps, "avg_launch_us": ms * 1e3, "bytes_per_launch": nbytes,
+            "bytes_model": "each nodal array of the launch read or written once: "
+                           + ("s(3N + N_c), N, N_c interior nodes of the level and of the next coarser"
+                              if dim == 2 else "3sN, N interior nodes of the level"),
+            "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT) if traffic is not None else None}
+
+
+def roofline_from_profile(rows):
+    """Device time per kernel class from the event-bracketed profile (each
+    launch inflated by the event pair: shares, not durations)."""
+    by_kernel = {}
     for r in rows:
         by_kernel[r["kernel"]] = by_kernel.get(r["kernel"], 0.0) + r["ms"]
-        if r["bytes"] > 0:
-            streaming[r["kernel"]] = streaming.get(r["kernel"], 0.0) + r["ms"]
-    total = sum(by_kernel.values())
-    dominant = max(streaming, key=streaming.get)
-    fine = [r for r in rows if r["kernel"] == dominant and r["level"] == finest]
-    if not fine or fine[0]["bytes"] <= 0:
-        return None, by_kernel, total
-    f = fine[0]
-    avg_s = f["ms"] / f["launches"] / 1e3
-    bytes_per_launch = f["bytes"] / f["launches"]
-    achieved = bytes_per_launch / avg_s / 1e9
-    roof = {"bound": "hbm", "kernel": dominant, "level": finest, "launches_timed": f["launches"],
-            "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "share_of_solve_time": by_kernel[dominant] / total}
-    return roof, by_kernel, total
+    return by_kernel
 
 
 def cpu_baseline(P, W):
@@ -281,6 +308,23 @@ def serve_mode(args, B, W, torch):
     }
 
 
+def roofline_leg(args, B, torch, factory, depth):
+    """The dominant kernel alone (same launches as the bench's roofline) and a
+    plain device copy of known size, for the counter runs: the copy's
+    FETCH_SIZE / WRITE_SIZE against its known bytes calibrate the counters."""
+    dim = 3 if factory.startswith("cube") else 2
+    H = B.Hierarchy(dim, 4, depth, B.default_options(dim), device="cuda:0")
+    roof = roofline_live(B, H, dim, args.workload, args.roof_reps)
+    n = 1 << 25                                   # 32 Mi doubles = 256 MiB each way
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    H.close()
+    print(json.dumps({"roofline": roof, "copy_bytes_each_way": 8 * n, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,6 +335,9 @@ def main():
     ap.add_argument("--workload", default="square2048", choices=sorted(WORKLOADS) + ["batch64", "serve"])
     ap.add_argument("--requests", type=int, default=1200, help="serve: requests in the trace")
     ap.add_argument("--inflight", type=int, default=8, help="serve: concurrent solves")
+    ap.add_argument("--roof-reps", type=int, default=200, help="launches timed for the roofline kernel")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the roofline leg (dominant kernel + a reference copy), for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver runs on a single "
@@ -310,6 +357,9 @@ def main():
         print(json.dumps(line), flush=True)
         return
     desc, factory, depth, gkey, disc_scale = WORKLOADS[args.workload]
+    if args.roofline_only:
+        roofline_leg(args, B, torch, factory, depth)
+        return
     golden = json.load(open(GOLDEN))[gkey]
     P = getattr(W, factory)(depth)
     g = torch.from_numpy(P.g_nodes).to("cuda:0")
@@ -322,18 +372,17 @@ def main():
         hier[name] = H
         log(f"{name}: {res['ms_per_solve']:.3f} ms/solve, {res['dof_per_s'] / 1e9:.3f} GDOF/s, "
             f"p50 {res['latency_ms_p50']:.3f} ms p99 {res['latency_ms_p99']:.3f} ms, gate {res['gate_pass']}")
-    roof = None
     if not args.no_profile:
         for name in ("fp64", "mixed"):
             total_ms, rows = profile_mode(B, hier[name], P, g, torch)
-            r, by_kernel, tot = roofline_from_profile(rows, P.n_levels)
+            by_kernel = roofline_from_profile(rows)
             modes[name]["profile_event_ms_total"] = total_ms
             modes[name]["profile_rows"] = sorted(rows, key=lambda r: -r["ms"])[:40]
             modes[name]["profile_ms_by_kernel"] = {k: round(v, 4) for k, v in
                                                    sorted(by_kernel.items(), key=lambda kv: -kv[1])}
-            if name == "fp64":
-                roof = r
-            modes[name]["roofline_dominant"] = r
+    roof = roofline_live(B, hier["fp64"], P.dim, args.workload, args.roof_reps)
+    log(f"roofline: {roof['kernel']} level {roof['level']}: {roof['avg_launch_us']:.2f} us/launch, "
+        f"{roof['achieved']:.0f} GB/s = {100 * roof['frac']:.1f}% of {HBM_PEAK_GBS:.0f} GB/s")
     primary = modes["fp64"]
     line = {
         "metric": METRIC, "value": primary["dof_per_s"], "unit": "DOF/s", "n_gpus": 1,

@@ -198,6 +198,24 @@ int fmg_level_op(fmg_hierarchy *h, int op, int level, int precision,
                  const double *in0, const double *in1, double *out, double omega,
                  void *stream);
 
+/* Diagnostic (measurement): time one of the solve's level kernels on its own.
+ * `kernel` is a kernel class as reported by fmg_profile_solve and named by
+ * fmg_kernel_name; supported: the fused 2D V(2,2) level kernels
+ * ("pre_sweeps_restrict_2d*", "prolong_post_sweeps_2d*", whichever variant
+ * the hierarchy's options select) and the separate sweep
+ * ("smooth_f64/f32"), residual-restriction and prolongation-correction
+ * kernels, in float64 or (mixed-mode hierarchies) float32.  The kernel is
+ * launched with the solve's launch shape on level `level` (2..levels) of the
+ * hierarchy's own buffers, which it overwrites (no solve may be in flight on
+ * `h`): once untimed, then `reps` times back to back on `stream` between two
+ * HIP events.  Writes the mean time per launch (ms) and the algorithmic bytes
+ * of one launch (each nodal array read or written once).  Synchronises
+ * `stream`.  Errors: FMG_E_INVALID (NULL, level or reps out of range),
+ * FMG_E_UNSUPPORTED (class not launched this way by this hierarchy). */
+int fmg_time_level_kernel(fmg_hierarchy *h, int kernel, int level, int reps,
+                          void *stream, double *ms_per_launch,
+                          double *bytes_per_launch);
+
 /* Measurement: one solve with plain (uncaptured) launches and a pair of
  * hipEvents recorded on `stream` around every kernel launch.  Entries are
  * aggregated per (kernel class, level): launches, summed milliseconds and

@@ -26,7 +26,7 @@ FMG_OP_APPLY_A, FMG_OP_SMOOTH, FMG_OP_RESTRICT, FMG_OP_PROLONG, FMG_OP_COARSE = 
 
 EXPORTED = ("fmg_default_options", "fmg_workspace_bytes", "fmg_create_hierarchy", "fmg_solve",
             "fmg_get_report", "fmg_solve_batch", "fmg_destroy", "fmg_status_str", "fmg_level_op",
-            "fmg_profile_solve", "fmg_kernel_name")
+            "fmg_profile_solve", "fmg_kernel_name", "fmg_time_level_kernel")
 
 
 class MeshDesc(ctypes.Structure):
@@ -107,6 +107,9 @@ def _load():
     lib.fmg_profile_solve.restype = ctypes.c_int
     lib.fmg_kernel_name.argtypes = [ctypes.c_int]
     lib.fmg_kernel_name.restype = ctypes.c_char_p
+    lib.fmg_time_level_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                          P(ctypes.c_double), P(ctypes.c_double)]
+    lib.fmg_time_level_kernel.restype = ctypes.c_int
     return lib
 
 
@@ -248,6 +251,26 @@ def solve_batch(hs: list, gs: list, kinds: list, params: list, outs: list, strea
                          for g, k, p in zip(gs, kinds, params)])
     O = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
     _check(LIB.fmg_solve_batch(H, P, O, None, n, ctypes.c_void_p(_stream_ptr(stream))), "fmg_solve_batch")
+
+
+def kernel_id(name: str) -> int:
+    """Kernel class id of a kernel name reported by fmg_kernel_name."""
+    for k in range(256):
+        nm = kernel_name(k)
+        if nm == name:
+            return k
+        if nm == "unknown":
+            break
+    raise KeyError(name)
+
+
+def time_level_kernel(h: "Hierarchy", name: str, level: int, reps: int, stream=None) -> tuple[float, float]:
+    """(ms per launch, algorithmic bytes per launch) of one level kernel."""
+    ms, nb = ctypes.c_double(), ctypes.c_double()
+    _check(LIB.fmg_time_level_kernel(h.handle, kernel_id(name), int(level), int(reps),
+                                     ctypes.c_void_p(_stream_ptr(stream if stream is not None else h.stream)),
+                                     ctypes.byref(ms), ctypes.byref(nb)), "fmg_time_level_kernel")
+    return ms.value, nb.value
 
 
 def exported_symbols() -> list[str]:

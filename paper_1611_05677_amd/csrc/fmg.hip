@@ -301,6 +301,61 @@ void fill_tail_args(const fmg_hierarchy* h, Roles& R, int top, TailArgs<T>& a) {
   a.zero_top = 0;
 }
 
+// Launches of the fused 2D V(2,2) level kernels on level k (register-streaming
+// or LDS-tiled, per the options); shared by the V-cycle and the kernel timer.
+// Returns the algorithmic bytes of the launch.
+template <typename T>
+double launch_pre2(const fmg_hierarchy* h, int k, const T* x, const T* b, T* t, T* bc, bool zero_init,
+                   hipStream_t st) {
+  const Plan& p = h->plan;
+  const LevelInfo& L = p.lev[k];
+  const LevelInfo& C = p.lev[k - 1];
+  const long long N = interior(L.g, 2), Nc = interior(C.g, 2);
+  const double s = sizeof(T), D = 4.0 * L.scale;
+  const double bytes = s * ((zero_init ? 2 : 3) * N + Nc);
+  const T wd1 = (T)(h->ro.pre[0] / D), wd2 = (T)(h->ro.pre[1] / D), scale = (T)L.scale;
+  const int kc2 = Sel<T>::kc ? (KC_PRE2D32 - KC_PRE2D64) : 0;
+  const int rows = stream_rows(h->ro.o.sweep_rows, L.g.n);
+  if (rows > 0) {
+    int nch = 0;
+    const int blocks = stream_blocks(L.g.n, kPreStrip, rows, nch);
+    FMG_LAUNCH(h, st, KC_PRE2S64 + kc2, k, N, bytes,
+               k_pre2s<T><<<blocks, 64 * kStreamWaves, 0, st>>>(L.g, C.g, x, b, t, bc, wd1, wd2, scale,
+                                                               zero_init ? 1 : 0, rows, nch));
+  } else {
+    const dim3 tiles((L.g.n + kFTX - 1) / kFTX, (L.g.n + kFTY - 1) / kFTY);
+    FMG_LAUNCH(h, st, KC_PRE2D64 + kc2, k, N, bytes,
+               k_pre2d<T><<<tiles, kBlock, pre2d_lds_bytes<T>(), st>>>(L.g, C.g, x, b, t, bc, wd1, wd2, scale,
+                                                                      zero_init ? 1 : 0));
+  }
+  return bytes;
+}
+
+template <typename T>
+double launch_post2(const fmg_hierarchy* h, int k, const T* x, const T* xc, const T* b, T* t, hipStream_t st) {
+  const Plan& p = h->plan;
+  const LevelInfo& L = p.lev[k];
+  const LevelInfo& C = p.lev[k - 1];
+  const long long N = interior(L.g, 2), Nc = interior(C.g, 2);
+  const double s = sizeof(T), D = 4.0 * L.scale;
+  const double bytes = s * (3 * N + Nc);
+  const T wd1 = (T)(h->ro.post[0] / D), wd2 = (T)(h->ro.post[1] / D), scale = (T)L.scale;
+  const int kc2 = Sel<T>::kc ? (KC_PRE2D32 - KC_PRE2D64) : 0;
+  const int rows = stream_rows(h->ro.o.sweep_rows, L.g.n);
+  if (rows > 0) {
+    int nch = 0;
+    const int blocks = stream_blocks(L.g.n, kPostStrip, rows, nch);
+    FMG_LAUNCH(h, st, KC_POST2S64 + kc2, k, N, bytes,
+               k_post2s<T><<<blocks, 64 * kStreamWaves, 0, st>>>(C.g, L.g, x, xc, b, t, wd1, wd2, scale, rows,
+                                                                nch));
+  } else {
+    const dim3 tiles((L.g.n + kFTX - 1) / kFTX, (L.g.n + kFTY - 1) / kFTY);
+    FMG_LAUNCH(h, st, KC_POST2D64 + kc2, k, N, bytes,
+               k_post2d<T><<<tiles, kBlock, post2d_lds_bytes<T>(), st>>>(C.g, L.g, x, xc, b, t, wd1, wd2, scale));
+  }
+  return bytes;
+}
+
 template <int DIM, typename T>
 void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t st) {
   const Plan& p = h->plan;
@@ -337,37 +392,10 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
   if (DIM == 2 && npre == 2 && npost == 2) {
     // fused level kernels: two sweeps + residual + restriction, then
     // correction + two sweeps (each writes the spare array: one role swap)
-    const LevelInfo& C = p.lev[k - 1];
-    const long long Nc = interior(C.g, DIM);
-    const int kc2 = Sel<T>::kc ? (KC_PRE2D32 - KC_PRE2D64) : 0;
-    const int rows = stream_rows(h->ro.o.sweep_rows, L.g.n);
-    if (rows > 0) {
-      int nch_pre = 0, nch_post = 0;
-      const int gpre = stream_blocks(L.g.n, kPreStrip, rows, nch_pre);
-      const int gpost = stream_blocks(L.g.n, kPostStrip, rows, nch_post);
-      FMG_LAUNCH(h, st, KC_PRE2S64 + kc2, k, N, s * ((zero_init ? 2 : 3) * N + Nc),
-                 k_pre2s<T><<<gpre, 64 * kStreamWaves, 0, st>>>(
-                     L.g, C.g, x, b, t, Sel<T>::b(h, k - 1), (T)(h->ro.pre[0] / D), (T)(h->ro.pre[1] / D), scale,
-                     zero_init ? 1 : 0, rows, nch_pre));
-      std::swap(x, t);
-      vcycle<DIM, T>(h, R, k - 1, true, st);
-      FMG_LAUNCH(h, st, KC_POST2S64 + kc2, k, N, s * (3 * N + Nc),
-                 k_post2s<T><<<gpost, 64 * kStreamWaves, 0, st>>>(C.g, L.g, x, Sel<T>::x(R, k - 1), b, t,
-                                                                   (T)(h->ro.post[0] / D),
-                                                                   (T)(h->ro.post[1] / D), scale, rows, nch_post));
-      std::swap(x, t);
-      return;
-    }
-    const dim3 tiles((L.g.n + kFTX - 1) / kFTX, (L.g.n + kFTY - 1) / kFTY);
-    FMG_LAUNCH(h, st, KC_PRE2D64 + kc2, k, N, s * ((zero_init ? 2 : 3) * N + Nc),
-               k_pre2d<T><<<tiles, kBlock, pre2d_lds_bytes<T>(), st>>>(
-                   L.g, C.g, x, b, t, Sel<T>::b(h, k - 1), (T)(h->ro.pre[0] / D), (T)(h->ro.pre[1] / D), scale,
-                   zero_init ? 1 : 0));
+    launch_pre2<T>(h, k, x, b, t, Sel<T>::b(h, k - 1), zero_init, st);
     std::swap(x, t);
     vcycle<DIM, T>(h, R, k - 1, true, st);
-    FMG_LAUNCH(h, st, KC_POST2D64 + kc2, k, N, s * (3 * N + Nc),
-               k_post2d<T><<<tiles, kBlock, post2d_lds_bytes<T>(), st>>>(
-                   C.g, L.g, x, Sel<T>::x(R, k - 1), b, t, (T)(h->ro.post[0] / D), (T)(h->ro.post[1] / D), scale));
+    launch_post2<T>(h, k, x, Sel<T>::x(R, k - 1), b, t, st);
     std::swap(x, t);
     return;
   }
@@ -1147,6 +1175,100 @@ int level_op_impl(fmg_hierarchy* h, int op, int k, int prec, const double* in0, 
   return hipGetLastError() == hipSuccess ? FMG_OK : FMG_E_HIP;
 }
 }  // namespace
+
+namespace {
+
+// One launch of a timed level kernel on the hierarchy's own level-k buffers.
+template <int DIM, typename T>
+int time_launch(fmg_hierarchy* h, int base, int k, hipStream_t st, double& bytes) {
+  const Plan& p = h->plan;
+  Roles R;
+  canonical_roles(h, R);
+  T* x = Sel<T>::x(R, k);
+  T* t = Sel<T>::t(R, k);
+  T* b = Sel<T>::b(h, k);
+  const LevelInfo& L = p.lev[k];
+  const LevelInfo& C = p.lev[k - 1];
+  const long long N = interior(L.g, DIM), Nc = interior(C.g, DIM);
+  const double s = sizeof(T), D = 2.0 * DIM * L.scale;
+  const T scale = (T)L.scale;
+  const int rows = stream_rows(h->ro.o.sweep_rows, L.g.n);
+  switch (base) {
+    case KC_PRE2S64: case KC_PRE2D64:
+      if (DIM != 2 || (base == KC_PRE2S64) != (rows > 0)) return FMG_E_UNSUPPORTED;
+      bytes = launch_pre2<T>(h, k, x, b, t, Sel<T>::b(h, k - 1), false, st);
+      return FMG_OK;
+    case KC_POST2S64: case KC_POST2D64:
+      if (DIM != 2 || (base == KC_POST2S64) != (rows > 0)) return FMG_E_UNSUPPORTED;
+      bytes = launch_post2<T>(h, k, x, Sel<T>::x(R, k - 1), b, t, st);
+      return FMG_OK;
+    case KC_SMOOTH64:
+      bytes = 3 * s * N;
+      k_smooth<DIM, T, false><<<grid_of(L.g, DIM), kBlock, 0, st>>>(L.g, x, b, t, (T)(h->ro.pre[0] / D), scale);
+      return FMG_OK;
+    case KC_RESTRICT64:
+      bytes = s * (2 * N + Nc);
+      k_resid_restrict<DIM, T><<<grid_of(C.g, DIM), kBlock, 0, st>>>(L.g, C.g, x, b, Sel<T>::b(h, k - 1), scale);
+      return FMG_OK;
+    case KC_PROLONG64_ADD:
+      bytes = s * (2 * N + Nc);
+      k_prolong<DIM, T, true><<<grid_of(L.g, DIM), kBlock, 0, st>>>(C.g, L.g, Sel<T>::x(R, k - 1), x);
+      return FMG_OK;
+    default:
+      return FMG_E_UNSUPPORTED;
+  }
+}
+
+template <int DIM>
+int time_launch_any(fmg_hierarchy* h, int kernel, int k, hipStream_t st, double& bytes) {
+  // classes come in float64 / float32 pairs at a fixed distance
+  const int d_mg = KC_SMOOTH32 - KC_SMOOTH64, d_2d = KC_PRE2D32 - KC_PRE2D64;
+  switch (kernel) {
+    case KC_SMOOTH64: case KC_RESTRICT64: case KC_PROLONG64_ADD:
+    case KC_PRE2D64: case KC_POST2D64: case KC_PRE2S64: case KC_POST2S64:
+      return time_launch<DIM, double>(h, kernel, k, st, bytes);
+    case KC_SMOOTH32: case KC_RESTRICT32: case KC_PROLONG32_ADD:
+      if (!h->plan.off_xs[k]) return FMG_E_UNSUPPORTED;
+      return time_launch<DIM, float>(h, kernel - d_mg, k, st, bytes);
+    case KC_PRE2D32: case KC_POST2D32: case KC_PRE2S32: case KC_POST2S32:
+      if (!h->plan.off_xs[k]) return FMG_E_UNSUPPORTED;
+      return time_launch<DIM, float>(h, kernel - d_2d, k, st, bytes);
+    default:
+      return FMG_E_UNSUPPORTED;
+  }
+}
+
+}  // namespace
+
+extern "C" int fmg_time_level_kernel(fmg_hierarchy* h, int kernel, int level, int reps, void* stream,
+                                     double* ms_per_launch, double* bytes_per_launch) {
+  if (!h || !ms_per_launch || !bytes_per_launch || reps < 1 || reps > 100000 || level < 2 ||
+      level > h->plan.nlev)
+    return FMG_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double bytes = 0.0;
+  auto once = [&]() {
+    return h->plan.dim == 2 ? time_launch_any<2>(h, kernel, level, s, bytes)
+                            : time_launch_any<3>(h, kernel, level, s, bytes);
+  };
+  int st = once();            // warm-up launch; also validates the request
+  if (st != FMG_OK) return st;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return FMG_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return FMG_E_HIP; }
+  (void)hipEventRecord(e0, s);
+  for (int i = 0; i < reps; ++i) (void)once();
+  (void)hipEventRecord(e1, s);
+  float ms = 0.f;
+  if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+      hipGetLastError() != hipSuccess)
+    st = FMG_E_HIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_per_launch = ms / reps;
+  *bytes_per_launch = bytes;
+  return st;
+}
 
 extern "C" int fmg_level_op(fmg_hierarchy* h, int op, int level, int precision, const double* in0, const double* in1,
                  double* out, double omega, void* stream) {

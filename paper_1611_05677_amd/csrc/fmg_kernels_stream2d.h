@@ -26,12 +26,17 @@ constexpr int kPostHalo = 2;       // sweep, sweep
 constexpr int kPreStrip = 64 - 2 * kPreHalo;
 constexpr int kPostStrip = 64 - 2 * kPostHalo;
 
-// Value held by lane l-1 (0 in lane 0) / lane l+1 (0 in lane 63).
+// Value held by lane l-1 (0 in lane 0) / lane l+1 (0 in lane 63): DPP moves
+// with bound control, so lanes without a source read 0.
 template <int CTRL>
-__device__ __forceinline__ double wave_shift(double v) { return dpp_move<CTRL>(v); }
+__device__ __forceinline__ double wave_shift(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
 template <int CTRL>
 __device__ __forceinline__ float wave_shift(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 template <typename T> __device__ __forceinline__ T from_left(T v) { return wave_shift<0x138>(v); }   // wave_shr:1
 template <typename T> __device__ __forceinline__ T from_right(T v) { return wave_shift<0x130>(v); }  // wave_shl:1
@@ -57,17 +62,32 @@ __device__ __forceinline__ bool stream_block(int nlogical, int gx, int& sx, int&
   return true;
 }
 
+// Loads are issued unconditionally from clamped (always in-bounds) addresses,
+// so that the register queue is filled without branches and the wait for a
+// row's data is left until the row is used; the value is masked at use.
+__device__ __forceinline__ int clamp_row(int y, int n) { return y < 0 ? 0 : (y > n ? n : y); }
+
 template <typename T>
-__device__ __forceinline__ T stream_load(const T* __restrict__ p, const Grid& g, int X, bool col_ok, int y) {
-  return (col_ok && y >= 0 && y <= g.n) ? p[y * g.px + X] : T(0);
+__device__ __forceinline__ T stream_raw(const T* __restrict__ p, const Grid& g, int Xc, int y) {
+  return p[clamp_row(y, g.n) * g.px + Xc];
+}
+template <typename T>
+__device__ __forceinline__ T stream_mask(T raw, bool col_ok, int y, int n) {
+  return (col_ok && y >= 0 && y <= n) ? raw : T(0);
 }
 
 // Two sweeps from x0 (or from zero), then r = b - A x and bc = P^T r on the
-// coarse nodes 2p inside the owned rows / columns.  R rows per wave.
-template <typename T, bool ZERO>
+// coarse nodes 2p inside the owned rows / columns.  R rows per wave, marched
+// upwards (UP) or downwards.  Vertically adjacent chunks march in opposite
+// directions, so the halo rows two chunks share are read by both at about the
+// same time (both at the start, or both at the end of their marches) and the
+// second read is served from L2.  The stencil sums are symmetric in the two
+// vertical neighbours, so the direction does not change any result.
+template <typename T, bool ZERO, bool UP>
 __device__ __forceinline__ void pre2s_wave(const Grid& f, const Grid& cg, const T* __restrict__ x0,
                                            const T* __restrict__ b, T* __restrict__ xout, T* __restrict__ bc,
                                            T wd1, T wd2, T scale, int strip, int Y0, int R) {
+  constexpr int D = UP ? 1 : -1;
   const int lane = threadIdx.x & 63;
   const int n = f.n;
   const int X = strip * kPreStrip - kPreHalo + lane;
@@ -75,45 +95,57 @@ __device__ __forceinline__ void pre2s_wave(const Grid& f, const Grid& cg, const 
   const bool col_in = X >= 1 && X <= n - 1;
   const bool own = lane >= kPreHalo && lane < 64 - kPreHalo && col_in;
   const bool own_c = own && !(X & 1) && X >= 2 && X <= n - 2;
+  const int Xc = X < 0 ? 0 : (X > n ? n : X);
   const int Yend = min(Y0 + R, n);          // owned rows [Y0, Yend)
   const int ylo = Y0 - kPreHalo, yhi = Yend + kPreHalo - 1;
-  // windows: x0 rows y-2, y-1; b rows y-1..y-3; sweep-1 rows y-3, y-2; sweep-2
-  // rows y-4, y-3; residual rows y-5, y-4 (+ their lane shifts)
+  const int ystart = UP ? ylo : yhi;
+  const int steps = yhi - ylo + 1;
+  // windows (y = row just loaded, D = march direction): x0 rows y-2D, y-D;
+  // b rows y-D..y-3D; sweep-1 rows y-3D, y-2D; sweep-2 rows y-4D, y-3D;
+  // residual rows y-5D, y-4D (+ their lane shifts)
   T xa = 0, xb = 0, b1 = 0, b2 = 0, b3 = 0, s1a = 0, s1b = 0, s2a = 0, s2b = 0;
-  T ra = 0, rb = 0, raL = 0, rbL = 0, rbR = 0;
+  T ra = 0, rb = 0, raL = 0, raR = 0, rbL = 0, rbR = 0;
+  // rows are processed in groups of kStreamQueue; the loads of the next group
+  // are issued when a group starts, so they have a whole group of work to land
   T qx[kStreamQueue], qb[kStreamQueue];
 #pragma unroll
   for (int q = 0; q < kStreamQueue; ++q) {
-    qx[q] = ZERO ? T(0) : stream_load(x0, f, X, col_ok, ylo + q);
-    qb[q] = stream_load(b, f, X, col_ok, ylo + q);
+    qx[q] = ZERO ? T(0) : stream_raw(x0, f, Xc, ystart + D * q);
+    qb[q] = stream_raw(b, f, Xc, ystart + D * q);
   }
-  for (int y0 = ylo; y0 <= yhi; y0 += kStreamQueue) {
+  for (int i0 = 0; i0 < steps; i0 += kStreamQueue) {
+    T nx[kStreamQueue], nb[kStreamQueue];
+#pragma unroll
+    for (int q = 0; q < kStreamQueue; ++q) {     // past the end: clamped, unused rows
+      const int yn = ystart + D * (i0 + kStreamQueue + q);
+      nx[q] = ZERO ? T(0) : stream_raw(x0, f, Xc, yn);
+      nb[q] = stream_raw(b, f, Xc, yn);
+    }
 #pragma unroll
     for (int q = 0; q < kStreamQueue; ++q) {
-      const int y = y0 + q;
-      const T xc = qx[q], b0 = qb[q];
-      const int yn = y + kStreamQueue;
-      if (yn <= yhi) {
-        if (!ZERO) qx[q] = stream_load(x0, f, X, col_ok, yn);
-        qb[q] = stream_load(b, f, X, col_ok, yn);
-      }
-      // sweep 1 at row y-1
-      const bool in1 = col_in && y - 1 >= 1 && y - 1 <= n - 1;
+      const int i = i0 + q;
+      const int y = ystart + D * i;
+      const T xc = ZERO ? T(0) : stream_mask(qx[q], col_ok, y, n);
+      const T b0 = stream_mask(qb[q], col_ok, y, n);
+      // sweep 1 at row y-D
+      const int y1 = y - D, y2 = y - 2 * D, y3 = y - 3 * D, yr = y - 4 * D;
+      const bool in1 = col_in && y1 >= 1 && y1 <= n - 1;
       T s1c;
       if (ZERO) s1c = in1 ? wd1 * b1 : T(0);
       else s1c = stream_sweep(xa, xb, xc, b1, wd1, scale, in1);
-      // sweep 2 at row y-2
-      const bool in2 = col_in && y - 2 >= 1 && y - 2 <= n - 1;
+      // sweep 2 at row y-2D
+      const bool in2 = col_in && y2 >= 1 && y2 <= n - 1;
       const T s2c = stream_sweep(s1a, s1b, s1c, b2, wd2, scale, in2);
-      if (own && y - 2 >= Y0 && y - 2 < Yend && in2) xout[(y - 2) * f.px + X] = s2c;
-      // residual at row y-3
-      const bool in3 = col_in && y - 3 >= 1 && y - 3 <= n - 1;
+      if (own && y2 >= Y0 && y2 < Yend && in2) xout[y2 * f.px + X] = s2c;
+      // residual at row y-3D
+      const bool in3 = col_in && y3 >= 1 && y3 <= n - 1;
       const T ssum = (from_left(s2b) + from_right(s2b)) + (s2a + s2c);
       const T rc = in3 ? b3 - scale * (T(4) * s2b - ssum) : T(0);
       const T rcL = from_left(rc), rcR = from_right(rc);
-      // restriction at row y-4 (residual rows y-5, y-4, y-3)
-      const int yr = y - 4;
-      const T h = ((rbR + rbL) + (rc + ra)) + (rcR + raL);
+      // restriction at row yr (residual rows yr-D, yr, yr+D); the diagonal
+      // pair is r(x+1, yr+1) + r(x-1, yr-1)
+      const T diag = UP ? (rcR + raL) : (raR + rcL);
+      const T h = ((rbR + rbL) + (rc + ra)) + diag;
       if (own_c && !(yr & 1) && yr >= Y0 && yr < Yend && yr >= 2 && yr <= n - 2)
         bc[(yr >> 1) * cg.px + (X >> 1)] = rb + T(0.5) * h;
       // advance the windows
@@ -121,9 +153,11 @@ __device__ __forceinline__ void pre2s_wave(const Grid& f, const Grid& cg, const 
       b3 = b2; b2 = b1; b1 = b0;
       s1a = s1b; s1b = s1c;
       s2a = s2b; s2b = s2c;
-      ra = rb; raL = rbL;
+      ra = rb; raL = rbL; raR = rbR;
       rb = rc; rbL = rcL; rbR = rcR;
     }
+#pragma unroll
+    for (int q = 0; q < kStreamQueue; ++q) { qx[q] = nx[q]; qb[q] = nb[q]; }
   }
 }
 
@@ -137,58 +171,78 @@ __global__ void __launch_bounds__(64 * kStreamWaves)
   if (!stream_block(gx * nchunk, gx, sx, cy)) return;
   const int strip = sx * kStreamWaves + (threadIdx.x >> 6);
   if (strip >= nstrip) return;            // whole wavefront leaves together
-  if (zero_init) pre2s_wave<T, true>(f, cg, x0, b, xout, bc, wd1, wd2, scale, strip, cy * R, R);
-  else pre2s_wave<T, false>(f, cg, x0, b, xout, bc, wd1, wd2, scale, strip, cy * R, R);
+  const bool up = !(cy & 1);
+  if (zero_init) {
+    if (up) pre2s_wave<T, true, true>(f, cg, x0, b, xout, bc, wd1, wd2, scale, strip, cy * R, R);
+    else pre2s_wave<T, true, false>(f, cg, x0, b, xout, bc, wd1, wd2, scale, strip, cy * R, R);
+  } else {
+    if (up) pre2s_wave<T, false, true>(f, cg, x0, b, xout, bc, wd1, wd2, scale, strip, cy * R, R);
+    else pre2s_wave<T, false, false>(f, cg, x0, b, xout, bc, wd1, wd2, scale, strip, cy * R, R);
+  }
 }
 
-// x + P xc on level f (coarse cg), then two sweeps; R rows per wave.
-template <typename T>
+// x + P xc on level f (coarse cg), then two sweeps; R rows per wave, marched
+// upwards or downwards (alternating by chunk, as in the pre-smoothing kernel).
+template <typename T, bool UP>
 __device__ __forceinline__ void post2s_wave(const Grid& cg, const Grid& f, const T* __restrict__ x,
                                             const T* __restrict__ xc, const T* __restrict__ b,
                                             T* __restrict__ xout, T wd1, T wd2, T scale, int strip, int Y0,
                                             int R) {
+  constexpr int D = UP ? 1 : -1;
   const int lane = threadIdx.x & 63;
   const int n = f.n;
   const int X = strip * kPostStrip - kPostHalo + lane;
   const bool col_ok = X >= 0 && X <= n;
   const bool col_in = X >= 1 && X <= n - 1;
   const bool own = lane >= kPostHalo && lane < 64 - kPostHalo && col_in;
-  const int ci = X >> 1, si = X & 1;
+  const int Xc = X < 0 ? 0 : (X > n ? n : X);
+  const int ci = Xc >> 1, si = Xc & 1;
   const int Yend = min(Y0 + R, n);
   const int ylo = Y0 - kPostHalo, yhi = Yend + kPostHalo - 1;
-  // queue entries: x, b and the two coarse values of row y
-  T qx[kStreamQueue], qb[kStreamQueue], qc0[kStreamQueue], qc1[kStreamQueue];
-  auto fetch = [&](int q, int y) {
-    qx[q] = stream_load(x, f, X, col_ok, y);
-    qb[q] = stream_load(b, f, X, col_ok, y);
-    const bool in = col_in && y >= 1 && y <= n - 1;
-    const int cj = y >> 1, sj = y & 1;
-    qc0[q] = in ? xc[cj * cg.px + ci] : T(0);
-    qc1[q] = (in && (si | sj)) ? xc[(cj + sj) * cg.px + ci + si] : T(0);
+  const int ystart = UP ? ylo : yhi;
+  const int steps = yhi - ylo + 1;
+  // queue entries: x, b and the two coarse values of row y; groups of rows as
+  // in the pre-smoothing kernel (next group's loads issued at group start)
+  struct Q4 { T x[kStreamQueue], b[kStreamQueue], c0[kStreamQueue], c1[kStreamQueue]; };
+  // (coarse reads clamped into the coarse grid: ci + si <= n/2 for every column)
+  auto fetch = [&](Q4& qq, int q, int y) {
+    const int yc = clamp_row(y, n);
+    qq.x[q] = x[yc * f.px + Xc];
+    qq.b[q] = b[yc * f.px + Xc];
+    const int cj = yc >> 1, sj = yc & 1;
+    qq.c0[q] = xc[cj * cg.px + ci];
+    qq.c1[q] = xc[min(cj + sj, cg.n) * cg.px + min(ci + si, cg.n)];
   };
+  Q4 cur;
 #pragma unroll
-  for (int q = 0; q < kStreamQueue; ++q) fetch(q, ylo + q);
-  // windows: corrected x rows y-2, y-1; b rows y-1, y-2; sweep-1 rows y-3, y-2
+  for (int q = 0; q < kStreamQueue; ++q) fetch(cur, q, ystart + D * q);
+  // windows: corrected x rows y-2D, y-D; b rows y-D, y-2D; sweep-1 rows y-3D, y-2D
   T xa = 0, xb = 0, b1 = 0, b2 = 0, s1a = 0, s1b = 0;
-  for (int y0 = ylo; y0 <= yhi; y0 += kStreamQueue) {
+  for (int i0 = 0; i0 < steps; i0 += kStreamQueue) {
+    Q4 nxt;
+#pragma unroll
+    for (int q = 0; q < kStreamQueue; ++q) fetch(nxt, q, ystart + D * (i0 + kStreamQueue + q));
 #pragma unroll
     for (int q = 0; q < kStreamQueue; ++q) {
-      const int y = y0 + q;
+      const int i = i0 + q;
+      const int y = ystart + D * i;
       const bool in0 = col_in && y >= 1 && y <= n - 1;
-      T v = qc0[q];
-      if (si | (y & 1)) v = T(0.5) * (v + qc1[q]);
-      const T xcor = in0 ? qx[q] + v : qx[q];
-      const T b0 = qb[q];
-      if (y + kStreamQueue <= yhi) fetch(q, y + kStreamQueue);
-      const bool in1 = col_in && y - 1 >= 1 && y - 1 <= n - 1;
+      T v = cur.c0[q];
+      if (si | (y & 1)) v = T(0.5) * (v + cur.c1[q]);
+      const T xr = stream_mask(cur.x[q], col_ok, y, n);
+      const T xcor = in0 ? xr + v : xr;
+      const T b0 = stream_mask(cur.b[q], col_ok, y, n);
+      const int y1 = y - D, y2 = y - 2 * D;
+      const bool in1 = col_in && y1 >= 1 && y1 <= n - 1;
       const T s1c = stream_sweep(xa, xb, xcor, b1, wd1, scale, in1);
-      const bool in2 = col_in && y - 2 >= 1 && y - 2 <= n - 1;
+      const bool in2 = col_in && y2 >= 1 && y2 <= n - 1;
       const T s2c = stream_sweep(s1a, s1b, s1c, b2, wd2, scale, in2);
-      if (own && y - 2 >= Y0 && y - 2 < Yend && in2) xout[(y - 2) * f.px + X] = s2c;
+      if (own && y2 >= Y0 && y2 < Yend && in2) xout[y2 * f.px + X] = s2c;
       xa = xb; xb = xcor;
       b2 = b1; b1 = b0;
       s1a = s1b; s1b = s1c;
     }
+    cur = nxt;
   }
 }
 
@@ -202,7 +256,8 @@ __global__ void __launch_bounds__(64 * kStreamWaves)
   if (!stream_block(gx * nchunk, gx, sx, cy)) return;
   const int strip = sx * kStreamWaves + (threadIdx.x >> 6);
   if (strip >= nstrip) return;
-  post2s_wave<T>(cg, f, x, xc, b, xout, wd1, wd2, scale, strip, cy * R, R);
+  if (!(cy & 1)) post2s_wave<T, true>(cg, f, x, xc, b, xout, wd1, wd2, scale, strip, cy * R, R);
+  else post2s_wave<T, false>(cg, f, x, xc, b, xout, wd1, wd2, scale, strip, cy * R, R);
 }
 
 // Rows per wavefront: an explicit choice, or (0) about 128 row chunks per

@@ -125,3 +125,26 @@ def test_coarse_solve(dim, nH, L, prec):
     got = H.level_op(B.FMG_OP_COARSE, 1, to_dev(b), precision=prec).cpu().numpy()
     err = np.max(np.abs(got - expect)) / np.max(np.abs(expect))
     assert err < 10 * TOL[prec], err
+
+
+def test_level_kernel_timer():
+    """fmg_time_level_kernel: positive durations, the stated byte model, and
+    a clear error for a kernel variant the options do not select."""
+    H = B.Hierarchy(2, 4, 6, B.default_options(2, precision=B.FMG_MIXED), device=DEV)
+    N, Nc = (H.n - 1) ** 2, (H.n // 2 - 1) ** 2
+    for name, s in (("pre_sweeps_restrict_2d_stream_f64", 8), ("prolong_post_sweeps_2d_stream_f32", 4)):
+        ms, nb = B.time_level_kernel(H, name, H.levels, 5)
+        assert ms > 0 and nb == s * (3 * N + Nc)
+    ms, nb = B.time_level_kernel(H, "smooth_f64", 3, 3)      # level 3: n = 16
+    assert ms > 0 and nb == 8 * 3 * 15 ** 2
+    with pytest.raises(B.FMGError):
+        B.time_level_kernel(H, "pre_sweeps_restrict_2d_f64", H.levels, 1)   # LDS variant not selected
+    with pytest.raises(B.FMGError):
+        B.time_level_kernel(H, "smooth_f64", 1, 1)                          # level 1 has no sweep
+    H.close()
+    H3 = B.Hierarchy(3, 4, 3, device=DEV)
+    ms, nb = B.time_level_kernel(H3, "smooth_f64", H3.levels, 3)
+    assert ms > 0 and nb == 8 * 3 * (H3.n - 1) ** 3
+    with pytest.raises(B.FMGError):
+        B.time_level_kernel(H3, "smooth_f32", H3.levels, 1)                  # no float32 buffers
+    H3.close()
