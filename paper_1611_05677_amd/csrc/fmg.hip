@@ -378,8 +378,15 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
     double bytes = 0.0;
     for (int j = 1; j <= k; ++j)
       bytes += s * interior(p.lev[j].g, DIM) * (3.0 * (h->ro.o.nu_pre + h->ro.o.nu_post) + 4.0);
-    FMG_LAUNCH(h, st, KC_VCYCLE_TAIL64 + (Sel<T>::kc ? 1 : 0), k, N, bytes,
-               k_vcycle_tail<DIM, T><<<1, kTailThreads, 0, st>>>(a));
+    int ns[kTailLevels + 1];
+    for (int j = 1; j <= k; ++j) ns[j] = p.lev[j].g.n;
+    const size_t lds = sizeof(T) * tail_lds_elements<DIM>(ns, k, a.lds_off);
+    if (lds <= kTailLdsMax)
+      FMG_LAUNCH(h, st, KC_VCYCLE_TAIL64 + (Sel<T>::kc ? 1 : 0), k, N, bytes,
+                 k_vcycle_tail_lds<DIM, T><<<1, kTailThreads, lds, st>>>(a));
+    else
+      FMG_LAUNCH(h, st, KC_VCYCLE_TAIL64 + (Sel<T>::kc ? 1 : 0), k, N, bytes,
+                 k_vcycle_tail<DIM, T><<<1, kTailThreads, 0, st>>>(a));
     // mirror the kernel's role swaps
     if ((h->ro.o.nu_pre + h->ro.o.nu_post) & 1)
       for (int j = 2; j <= k; ++j) std::swap(Sel<T>::x(R, j), Sel<T>::t(R, j));

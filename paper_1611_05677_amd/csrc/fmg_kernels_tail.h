@@ -13,6 +13,7 @@ namespace fmg {
 constexpr int kTailThreads = 1024;
 constexpr int kTailLevels = 8;   // deepest level a tail launch may start from
 constexpr int kTailSweeps = 8;   // max sweeps per level in a tail launch
+constexpr size_t kTailLdsMax = 64 * 1024;   // LDS-resident tail up to this many bytes
 
 template <typename T>
 struct TailArgs {
@@ -25,6 +26,7 @@ struct TailArgs {
   T wdpost[kTailLevels + 1][kTailSweeps];
   const T* ainv;                // A_1^{-1}, dense N1 x N1
   int N1, top, npre, npost, zero_top;
+  int lds_off[kTailLevels + 1]; // LDS variant: offset (elements) of level k's x, t, b
 };
 
 template <int DIM>
@@ -139,6 +141,174 @@ __global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailArgs<T> a) {
   T* t[kTailLevels + 1];
   for (int k = 1; k <= a.top; ++k) { x[k] = a.x[k]; t[k] = a.t[k]; }
   vcycle_tail_dev<DIM, T>(a, x, t, a.top, a.zero_top != 0);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-resident variant.  Every level 1..top lives in LDS as three packed
+// (n_k+1)^d arrays (x, t, b; Dirichlet ring zero); only b[top] (and x[top]
+// unless the cycle starts from zero) is read from global memory and only the
+// final x[top] is written back (into the array that holds x[top] after the
+// cycle's role swaps).  Nodes are enumerated by row / plane loops over a fixed
+// thread shape (64 x 16 in 2D, 32 x 8 x 4 in 3D), so no division per node.
+// Same per-node expressions as the grid kernels.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ Grid packed_grid(int n) {
+  Grid g;
+  g.n = n;
+  g.px = n + 1;
+  g.pz = DIM == 3 ? (n + 1) * (n + 1) : 0;
+  return g;
+}
+
+template <int DIM>
+__device__ __forceinline__ int packed_count(int n) {
+  return DIM == 2 ? (n + 1) * (n + 1) : (n + 1) * (n + 1) * (n + 1);
+}
+
+// fn(i, j, l) over the interior nodes 1..n-1 of a level
+template <int DIM, typename F>
+__device__ __forceinline__ void for_interior(int n, F&& fn) {
+  const int tid = threadIdx.x;
+  if (DIM == 2) {
+    const int tx = tid & 63, ty = tid >> 6;
+    for (int j = 1 + ty; j < n; j += kTailThreads / 64)
+      for (int i = 1 + tx; i < n; i += 64) fn(i, j, 0);
+  } else {
+    const int tx = tid & 31, ty = (tid >> 5) & 7, tz = tid >> 8;
+    for (int l = 1 + tz; l < n; l += kTailThreads / 256)
+      for (int j = 1 + ty; j < n; j += 8)
+        for (int i = 1 + tx; i < n; i += 32) fn(i, j, l);
+  }
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kTailThreads) k_vcycle_tail_lds(TailArgs<T> a) {
+  extern __shared__ unsigned char tail_smem[];
+  T* lds = reinterpret_cast<T*>(tail_smem);
+  const int top = a.top;
+  // zero every level (rings stay zero), then bring in b[top] and x[top]
+  {
+    const int total = a.lds_off[top] + 3 * packed_count<DIM>(a.g[top].n);
+    for (int e = threadIdx.x; e < total; e += kTailThreads) lds[e] = T(0);
+  }
+  __syncthreads();
+  {
+    const Grid G = a.g[top];
+    const Grid P = packed_grid<DIM>(G.n);
+    T* X = lds + a.lds_off[top];
+    T* B = X + 2 * packed_count<DIM>(G.n);
+    const bool load_x = !a.zero_top;
+    for_interior<DIM>(G.n, [&](int i, int j, int l) {
+      const int q = gidx<DIM>(P, i, j, l), c = gidx<DIM>(G, i, j, l);
+      B[q] = a.b[top][c];
+      if (load_x) X[q] = a.x[top][c];
+    });
+  }
+  __syncthreads();
+  const int par_pre = a.npre & 1;
+  // down: pre-smoothing, residual, restriction
+  for (int k = top; k >= 2; --k) {
+    const int n = a.g[k].n;
+    const Grid P = packed_grid<DIM>(n);
+    const int cnt = packed_count<DIM>(n);
+    T* xk = lds + a.lds_off[k];
+    T* tk = xk + cnt;
+    T* bk = tk + cnt;
+    const bool zero = k < top || a.zero_top;
+    const T scale = a.scale[k];
+    for (int s = 0; s < a.npre; ++s) {
+      const T wd = a.wdpre[k][s];
+      const bool z = zero && s == 0;
+      for_interior<DIM>(n, [&](int i, int j, int l) {
+        const int c = gidx<DIM>(P, i, j, l);
+        tk[c] = z ? wd * bk[c] : xk[c] + wd * (bk[c] - apply_A_at<DIM>(xk, c, P, scale));
+      });
+      __syncthreads();
+      T* sw = xk; xk = tk; tk = sw;
+    }
+    const Grid C = packed_grid<DIM>(a.g[k - 1].n);
+    T* bc = lds + a.lds_off[k - 1] + 2 * packed_count<DIM>(C.n);
+    for_interior<DIM>(C.n, [&](int i, int j, int l) {
+      const int q = gidx<DIM>(P, 2 * i, 2 * j, 2 * l);
+      auto r = [&](int p) { return bk[p] - apply_A_at<DIM>(xk, p, P, scale); };
+      const int dx = 1, dy = P.px;
+      T h = (r(q + dx) + r(q - dx)) + (r(q + dy) + r(q - dy)) + (r(q + dx + dy) + r(q - dx - dy));
+      if (DIM == 3) {
+        const int dz = P.pz;
+        h += (r(q + dz) + r(q - dz)) + (r(q + dx + dz) + r(q - dx - dz)) +
+             (r(q + dy + dz) + r(q - dy - dz)) + (r(q + dx + dy + dz) + r(q - dx - dy - dz));
+      }
+      bc[gidx<DIM>(C, i, j, l)] = r(q) + T(0.5) * h;
+    });
+    __syncthreads();
+  }
+  // level 1: exact solve with the dense inverse
+  {
+    const Grid P1 = packed_grid<DIM>(a.g[1].n);
+    T* x1 = lds + a.lds_off[1];
+    const T* b1 = x1 + 2 * packed_count<DIM>(P1.n);
+    for (int r = threadIdx.x; r < a.N1; r += kTailThreads) {
+      T s = 0;
+      for (int c = 0; c < a.N1; ++c) s += a.ainv[r * a.N1 + c] * b1[level1_node<DIM>(P1, c)];
+      x1[level1_node<DIM>(P1, r)] = s;
+    }
+    __syncthreads();
+  }
+  // up: prolongation + correction, post-smoothing
+  T* xfinal = nullptr;
+  for (int k = 2; k <= top; ++k) {
+    const int n = a.g[k].n;
+    const Grid P = packed_grid<DIM>(n);
+    const int cnt = packed_count<DIM>(n);
+    T* xk = lds + a.lds_off[k];
+    T* tk = xk + cnt;
+    T* bk = tk + cnt;
+    if (par_pre) { T* sw = xk; xk = tk; tk = sw; }
+    const Grid C = packed_grid<DIM>(a.g[k - 1].n);
+    const T* xc = lds + a.lds_off[k - 1];
+    if (k - 1 >= 2 && par_pre ^ (a.npost & 1)) xc += packed_count<DIM>(C.n);   // level k-1's final x
+    for_interior<DIM>(n, [&](int i, int j, int l) {
+      const int si = i & 1, sj = j & 1, sl = DIM == 3 ? (l & 1) : 0;
+      const int pi = i >> 1, pj = j >> 1, pl = l >> 1;
+      T v = xc[gidx<DIM>(C, pi, pj, pl)];
+      if (si | sj | sl) v = T(0.5) * (v + xc[gidx<DIM>(C, pi + si, pj + sj, pl + sl)]);
+      const int q = gidx<DIM>(P, i, j, l);
+      xk[q] = xk[q] + v;
+    });
+    __syncthreads();
+    const T scale = a.scale[k];
+    for (int s = 0; s < a.npost; ++s) {
+      const T wd = a.wdpost[k][s];
+      for_interior<DIM>(n, [&](int i, int j, int l) {
+        const int c = gidx<DIM>(P, i, j, l);
+        tk[c] = xk[c] + wd * (bk[c] - apply_A_at<DIM>(xk, c, P, scale));
+      });
+      __syncthreads();
+      T* sw = xk; xk = tk; tk = sw;
+    }
+    xfinal = xk;
+  }
+  // write x[top] back where the host expects it after the cycle's role swaps
+  {
+    const Grid G = a.g[top];
+    const Grid P = packed_grid<DIM>(G.n);
+    T* dst = ((a.npre + a.npost) & 1) ? a.t[top] : a.x[top];
+    for_interior<DIM>(G.n, [&](int i, int j, int l) {
+      dst[gidx<DIM>(G, i, j, l)] = xfinal[gidx<DIM>(P, i, j, l)];
+    });
+  }
+}
+
+template <int DIM>
+inline size_t tail_lds_elements(const int* n, int top, int* off) {
+  size_t e = 0;
+  for (int k = 1; k <= top; ++k) {
+    off[k] = (int)e;
+    const size_t c = DIM == 2 ? (size_t)(n[k] + 1) * (n[k] + 1) : (size_t)(n[k] + 1) * (n[k] + 1) * (n[k] + 1);
+    e += 3 * c;
+  }
+  return e;
 }
 
 }  // namespace fmg
