@@ -92,8 +92,9 @@ typedef struct {
     int newton_max;     /* cap on Newton iterations per small solve (30)     */
     double newton_tol;  /* stop when |d|_inf <= tol max(1,|y|_inf) (1e-14)  */
     int newton_passes;  /* fine quadrature passes per correction step kept in
-                           the launch sequence (a single-workgroup finisher
-                           completes any Newton solve that needs more)       */
+                           the launch sequence, the setup pass included (4);
+                           the last one completes, in one workgroup, any
+                           Newton solve that needs more                      */
     int mode;           /* FMG_PAPER: Algorithm 3.2 as stated; FMG_CONVERGED:
                            then repeat correction steps on the finest level
                            until ||du||_2 <= converged_tol ||u||_2 (synchronous) */

@@ -434,14 +434,7 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
   }
 }
 
-constexpr int kNewtonThreads = 1024;
 
-inline size_t newton_lds_bytes(const Plan& p, bool finisher) {
-  const int ncell = p.dim == 2 ? p.nH * p.nH : p.nH * p.nH * p.nH;
-  const int NQ = p.dim == 2 ? Acc<2>::NQ : Acc<3>::NQ;
-  (void)finisher;
-  return sizeof(double) * (size_t)newton_kernel_lds_doubles(ncell, NQ, p.N1, kNewtonThreads);
-}
 
 inline size_t aug_pass_lds_bytes(const Plan& p) {
   const int ncell = p.dim == 2 ? p.nH * p.nH : p.nH * p.nH * p.nH;
@@ -502,18 +495,16 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
     return;
   }
   const size_t lds = aug_pass_lds_bytes(p);
+  const int npass = o.newton_passes;   // setup pass + npass - 1 quadrature passes; the last one finishes
   FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
              (k_aug_pass<DIM, KIND, true><<<L.aug_blocks, kBlock, lds, st>>>(
                  L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, cellsum,
-                 ticket, k, o.newton_max, o.newton_tol)));
-  for (int pass = 1; pass < o.newton_passes; ++pass)
+                 ticket, k, o.newton_max, o.newton_tol, npass == 1 ? 1 : 0)));
+  for (int pass = 1; pass < npass; ++pass)
     FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
                (k_aug_pass<DIM, KIND, false><<<L.aug_blocks, kBlock, lds, st>>>(
                    L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, cellsum,
-                   ticket, k, o.newton_max, o.newton_tol)));
-  FMG_LAUNCH(h, st, KC_NEWTON_FINISH, k, N, 0.0,
-             k_newton_finish<DIM, KIND><<<1, kNewtonThreads, newton_lds_bytes(p, true), st>>>(
-                 L.g, L.aug, R.x[k], h->slot(), A1, L.m, h->ns(), h->rep(), o.newton_max, o.newton_tol));
+                   ticket, k, o.newton_max, o.newton_tol, pass == npass - 1 ? 1 : 0)));
   if (!defer_update)
     FMG_LAUNCH(h, st, KC_AUG_UPDATE, k, N, 16.0 * N,
                k_aug_update<DIM><<<grid, kBlock, 0, st>>>(L.g, L.aug, h->ns(), R.x[k]));
@@ -787,7 +778,7 @@ void fmg_default_options(int dim, fmg_options* o) {
   o->cheb_hi = 2.0;
   o->newton_max = 30;
   o->newton_tol = 1e-14;
-  o->newton_passes = 5;
+  o->newton_passes = 4;
   o->mode = FMG_PAPER;
   o->converged_max_steps = 40;
   o->converged_tol = 1e-13;

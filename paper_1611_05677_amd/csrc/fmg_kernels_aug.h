@@ -544,6 +544,10 @@ __device__ __forceinline__ void newton_step_dev(const AugShape& s, const double*
                                                 double m, NewtonState* ns, fmg_report* rep, int newton_max,
                                                 double tol, double* sm);
 
+template <int DIM, int KIND>
+__device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                           const double* ytry, double param, double* cs);
+
 // One pass of the augmented Newton iteration in one launch.  Every block
 // accumulates its share of the fine quadrature sums at ns->ytry (SETUP: the
 // setup sums plus the sums at y0 = (0,..,0,1), i.e. z = u~) and writes them
@@ -559,7 +563,7 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
                                                      NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
                                                      double* __restrict__ pq, double* __restrict__ ps,
                                                      double* __restrict__ cellsum, unsigned* __restrict__ tickets,
-                                                     int level, int newton_max, double tol) {
+                                                     int level, int newton_max, double tol, int finish) {
   using AC = Acc<DIM>;
   constexpr int W = AC::NQ + (SETUP ? AC::NS : 0);
   extern __shared__ double smem[];
@@ -651,6 +655,16 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
     cs[idx] = cellsum[(size_t)(idx / AC::NQ) * (AC::NQ + AC::NS) + idx % AC::NQ];
   __syncthreads();
   newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
+  if (finish) {
+    // last pass of the launch sequence: this block completes the Newton solve
+    // if it needs more passes, evaluating the fine quadrature by itself
+    while (true) {
+      __syncthreads();
+      if (ns->done) break;
+      quad_cells_by_waves<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cs);
+      newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
+    }
+  }
   if (threadIdx.x == 0) __hip_atomic_store(&tickets[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -697,27 +711,6 @@ __device__ __forceinline__ void setup_cells_by_waves(const Grid& g, const AugSha
     }
   }
   __syncthreads();
-}
-
-// Completes a Newton solve that the fixed number of passes did not finish:
-// one block evaluates the fine quadrature itself.
-template <int DIM, int KIND>
-__global__ void __launch_bounds__(1024) k_newton_finish(Grid g, AugShape s, const double* __restrict__ ut,
-                                                        const ProblemSlot* __restrict__ slot,
-                                                        const double* __restrict__ A1, double m,
-                                                        NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
-                                                        int newton_max, double tol) {
-  using AC = Acc<DIM>;
-  extern __shared__ double smem[];
-  const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
-  double* cs = smem;
-  double* sm = smem + ncell * AC::NQ;
-  while (true) {
-    __syncthreads();
-    if (ns->done) return;
-    quad_cells_by_waves<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cs);
-    newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
-  }
 }
 
 // z = Q w + alpha u~ at node (i, j, l) of the level (0 on the boundary, where

@@ -118,8 +118,16 @@ __global__ void __launch_bounds__(kTailThreads) k_aug_solve_small(Grid g, AugSha
                                                                   fmg_report* rep, int level, int newton_max,
                                                                   double tol, int do_update) {
   extern __shared__ double smem[];
-  aug_solve_dev<DIM, KIND>(g, s, ut, slot, nf1, fs, scale, m, A1, ns, rep, level, newton_max, tol, smem,
+  // the Newton state lives in LDS for the whole solve (its many small,
+  // dependent reads and writes then cost LDS latency, not L2 latency) and is
+  // copied out once at the end for the kernels that consume it
+  __shared__ NewtonState nsl;
+  aug_solve_dev<DIM, KIND>(g, s, ut, slot, nf1, fs, scale, m, A1, &nsl, rep, level, newton_max, tol, smem,
                            do_update != 0);
+  const double* src = reinterpret_cast<const double*>(&nsl);
+  double* dst = reinterpret_cast<double*>(ns);
+  static_assert(sizeof(NewtonState) % sizeof(double) == 0, "NewtonState copied as doubles");
+  for (int i = threadIdx.x; i < (int)(sizeof(NewtonState) / sizeof(double)); i += blockDim.x) dst[i] = src[i];
 }
 
 template <int DIM, int KIND, bool MIXED>
