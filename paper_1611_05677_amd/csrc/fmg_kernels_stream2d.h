@@ -20,7 +20,8 @@
 namespace fmg {
 
 constexpr int kStreamWaves = 4;    // independent wavefronts per block
-constexpr int kStreamQueue = 4;    // rows loaded ahead of use
+constexpr int kPreQueue = 4;       // rows per load group (pre-smoothing kernel)
+constexpr int kPostQueue = 4;      // rows per load group (post-smoothing kernel)
 constexpr int kPreHalo = 4;        // sweep, sweep, residual, restriction
 constexpr int kPostHalo = 2;       // sweep, sweep
 constexpr int kPreStrip = 64 - 2 * kPreHalo;
@@ -105,24 +106,24 @@ __device__ __forceinline__ void pre2s_wave(const Grid& f, const Grid& cg, const 
   // residual rows y-5D, y-4D (+ their lane shifts)
   T xa = 0, xb = 0, b1 = 0, b2 = 0, b3 = 0, s1a = 0, s1b = 0, s2a = 0, s2b = 0;
   T ra = 0, rb = 0, raL = 0, raR = 0, rbL = 0, rbR = 0;
-  // rows are processed in groups of kStreamQueue; the loads of the next group
+  // rows are processed in groups of kPreQueue; the loads of the next group
   // are issued when a group starts, so they have a whole group of work to land
-  T qx[kStreamQueue], qb[kStreamQueue];
+  T qx[kPreQueue], qb[kPreQueue];
 #pragma unroll
-  for (int q = 0; q < kStreamQueue; ++q) {
+  for (int q = 0; q < kPreQueue; ++q) {
     qx[q] = ZERO ? T(0) : stream_raw(x0, f, Xc, ystart + D * q);
     qb[q] = stream_raw(b, f, Xc, ystart + D * q);
   }
-  for (int i0 = 0; i0 < steps; i0 += kStreamQueue) {
-    T nx[kStreamQueue], nb[kStreamQueue];
+  for (int i0 = 0; i0 < steps; i0 += kPreQueue) {
+    T nx[kPreQueue], nb[kPreQueue];
 #pragma unroll
-    for (int q = 0; q < kStreamQueue; ++q) {     // past the end: clamped, unused rows
-      const int yn = ystart + D * (i0 + kStreamQueue + q);
+    for (int q = 0; q < kPreQueue; ++q) {     // past the end: clamped, unused rows
+      const int yn = ystart + D * (i0 + kPreQueue + q);
       nx[q] = ZERO ? T(0) : stream_raw(x0, f, Xc, yn);
       nb[q] = stream_raw(b, f, Xc, yn);
     }
 #pragma unroll
-    for (int q = 0; q < kStreamQueue; ++q) {
+    for (int q = 0; q < kPreQueue; ++q) {
       const int i = i0 + q;
       const int y = ystart + D * i;
       const T xc = ZERO ? T(0) : stream_mask(qx[q], col_ok, y, n);
@@ -157,7 +158,7 @@ __device__ __forceinline__ void pre2s_wave(const Grid& f, const Grid& cg, const 
       rb = rc; rbL = rcL; rbR = rcR;
     }
 #pragma unroll
-    for (int q = 0; q < kStreamQueue; ++q) { qx[q] = nx[q]; qb[q] = nb[q]; }
+    for (int q = 0; q < kPreQueue; ++q) { qx[q] = nx[q]; qb[q] = nb[q]; }
   }
 }
 
@@ -203,7 +204,7 @@ __device__ __forceinline__ void post2s_wave(const Grid& cg, const Grid& f, const
   const int steps = yhi - ylo + 1;
   // queue entries: x, b and the two coarse values of row y; groups of rows as
   // in the pre-smoothing kernel (next group's loads issued at group start)
-  struct Q4 { T x[kStreamQueue], b[kStreamQueue], c0[kStreamQueue], c1[kStreamQueue]; };
+  struct Q4 { T x[kPostQueue], b[kPostQueue], c0[kPostQueue], c1[kPostQueue]; };
   // (coarse reads clamped into the coarse grid: ci + si <= n/2 for every column)
   auto fetch = [&](Q4& qq, int q, int y) {
     const int yc = clamp_row(y, n);
@@ -215,15 +216,15 @@ __device__ __forceinline__ void post2s_wave(const Grid& cg, const Grid& f, const
   };
   Q4 cur;
 #pragma unroll
-  for (int q = 0; q < kStreamQueue; ++q) fetch(cur, q, ystart + D * q);
+  for (int q = 0; q < kPostQueue; ++q) fetch(cur, q, ystart + D * q);
   // windows: corrected x rows y-2D, y-D; b rows y-D, y-2D; sweep-1 rows y-3D, y-2D
   T xa = 0, xb = 0, b1 = 0, b2 = 0, s1a = 0, s1b = 0;
-  for (int i0 = 0; i0 < steps; i0 += kStreamQueue) {
+  for (int i0 = 0; i0 < steps; i0 += kPostQueue) {
     Q4 nxt;
 #pragma unroll
-    for (int q = 0; q < kStreamQueue; ++q) fetch(nxt, q, ystart + D * (i0 + kStreamQueue + q));
+    for (int q = 0; q < kPostQueue; ++q) fetch(nxt, q, ystart + D * (i0 + kPostQueue + q));
 #pragma unroll
-    for (int q = 0; q < kStreamQueue; ++q) {
+    for (int q = 0; q < kPostQueue; ++q) {
       const int i = i0 + q;
       const int y = ystart + D * i;
       const bool in0 = col_in && y >= 1 && y <= n - 1;
