@@ -149,8 +149,7 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p) {
   p.off_pq = take(sizeof(double) * max_blocks * Acc<3>::NQ);
   p.off_ps = take(sizeof(double) * max_blocks * Acc<3>::NS);
   const LevelInfo& F = p.lev[p.nlev];
-  const size_t rows = (size_t)(F.g.n - 1) * (d == 3 ? (F.g.n - 1) : 1);
-  p.norm_blocks = rows * (size_t)((F.g.n - 1 + kBlock - 1) / kBlock);
+  p.norm_blocks = d == 2 ? grid_blocks<2>(F.g.n) : grid_blocks<3>(F.g.n);
   p.off_norm_part = ro.o.mode == FMG_CONVERGED ? take(sizeof(double) * 2 * p.norm_blocks) : 0;
   for (int k = 1; k <= p.nlev; ++k) {
     const size_t c = p.lev[k].count;
@@ -193,7 +192,7 @@ struct fmg_hierarchy {
 namespace {
 
 inline dim3 grid_of(const Grid& g, int dim) {
-  return dim3((g.n - 1 + kBlock - 1) / kBlock, g.n - 1, dim == 3 ? g.n - 1 : 1);
+  return dim3(dim == 2 ? grid_blocks<2>(g.n) : grid_blocks<3>(g.n));
 }
 
 // Kernel classes reported by fmg_profile_solve.
@@ -495,16 +494,34 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
     return;
   }
   const size_t lds = aug_pass_lds_bytes(p);
-  const int npass = o.newton_passes;   // setup pass + npass - 1 quadrature passes; the last one finishes
-  FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
-             (k_aug_pass<DIM, KIND, true><<<L.aug_blocks, kBlock, lds, st>>>(
-                 L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, cellsum,
-                 ticket, k, o.newton_max, o.newton_tol, npass == 1 ? 1 : 0)));
-  for (int pass = 1; pass < npass; ++pass)
-    FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
-               (k_aug_pass<DIM, KIND, false><<<L.aug_blocks, kBlock, lds, st>>>(
+  const int npass = o.newton_passes;   // setup pass + npass - 1 quadrature passes
+  constexpr bool kFinishInPass = DIM == 2;
+  if (npass == 1 && kFinishInPass)
+    FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
+               (k_aug_pass<DIM, KIND, true, true><<<L.aug_blocks, kBlock, lds, st>>>(
                    L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, cellsum,
-                   ticket, k, o.newton_max, o.newton_tol, pass == npass - 1 ? 1 : 0)));
+                   ticket, k, o.newton_max, o.newton_tol)));
+  else
+    FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
+               (k_aug_pass<DIM, KIND, true, false><<<L.aug_blocks, kBlock, lds, st>>>(
+                   L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, cellsum,
+                   ticket, k, o.newton_max, o.newton_tol)));
+  for (int pass = 1; pass < npass; ++pass) {
+    if (pass == npass - 1 && kFinishInPass)
+      FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
+                 (k_aug_pass<DIM, KIND, false, true><<<L.aug_blocks, kBlock, lds, st>>>(
+                     L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps,
+                     cellsum, ticket, k, o.newton_max, o.newton_tol)));
+    else
+      FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
+                 (k_aug_pass<DIM, KIND, false, false><<<L.aug_blocks, kBlock, lds, st>>>(
+                     L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps,
+                     cellsum, ticket, k, o.newton_max, o.newton_tol)));
+  }
+  if (!kFinishInPass)
+    FMG_LAUNCH(h, st, KC_NEWTON_FINISH, k, N, 0.0,
+               k_newton_finish<DIM, KIND><<<1, kBlock, lds, st>>>(L.g, L.aug, R.x[k], h->slot(), A1, L.m, h->ns(),
+                                                                   h->rep(), o.newton_max, o.newton_tol));
   if (!defer_update)
     FMG_LAUNCH(h, st, KC_AUG_UPDATE, k, N, 16.0 * N,
                k_aug_update<DIM><<<grid, kBlock, 0, st>>>(L.g, L.aug, h->ns(), R.x[k]));

@@ -556,14 +556,14 @@ __device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShap
 // order into the cell sums; the last cell to finish performs the Newton step.
 // tickets: [0] global, [1 + cell] per cell; all zero between launches.
 // LDS: newton_kernel_lds_doubles(ncell, NQ, N1, blockDim).
-template <int DIM, int KIND, bool SETUP>
+template <int DIM, int KIND, bool SETUP, bool FINISH>
 __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
                                                      const ProblemSlot* __restrict__ slot, int nf1, int fs,
                                                      double scale, double m, const double* __restrict__ A1,
                                                      NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
                                                      double* __restrict__ pq, double* __restrict__ ps,
                                                      double* __restrict__ cellsum, unsigned* __restrict__ tickets,
-                                                     int level, int newton_max, double tol, int finish) {
+                                                     int level, int newton_max, double tol) {
   using AC = Acc<DIM>;
   constexpr int W = AC::NQ + (SETUP ? AC::NS : 0);
   extern __shared__ double smem[];
@@ -655,7 +655,7 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
     cs[idx] = cellsum[(size_t)(idx / AC::NQ) * (AC::NQ + AC::NS) + idx % AC::NQ];
   __syncthreads();
   newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
-  if (finish) {
+  if (FINISH) {
     // last pass of the launch sequence: this block completes the Newton solve
     // if it needs more passes, evaluating the fine quadrature by itself
     while (true) {
@@ -711,6 +711,27 @@ __device__ __forceinline__ void setup_cells_by_waves(const Grid& g, const AugSha
     }
   }
   __syncthreads();
+}
+
+// Completes a Newton solve that the passes of the launch sequence did not
+// finish: one block evaluates the fine quadrature itself (3D).
+template <int DIM, int KIND>
+__global__ void __launch_bounds__(kBlock) k_newton_finish(Grid g, AugShape s, const double* __restrict__ ut,
+                                                          const ProblemSlot* __restrict__ slot,
+                                                          const double* __restrict__ A1, double m,
+                                                          NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
+                                                          int newton_max, double tol) {
+  using AC = Acc<DIM>;
+  extern __shared__ double smem[];
+  const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
+  double* cs = smem;
+  double* sm = smem + ncell * AC::NQ;
+  while (true) {
+    __syncthreads();
+    if (ns->done) return;
+    quad_cells_by_waves<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cs);
+    newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
+  }
 }
 
 // z = Q w + alpha u~ at node (i, j, l) of the level (0 on the boundary, where
@@ -954,8 +975,7 @@ __global__ void __launch_bounds__(kBlock) k_diff_norm_partials(Grid g, const dou
     acc[1] = x[c] * x[c];
   }
   const double t = block_sum_many<2>(acc, lds);
-  const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  if (threadIdx.x < 2) partials[b * 2 + threadIdx.x] = t;
+  if (threadIdx.x < 2) partials[(size_t)blockIdx.x * 2 + threadIdx.x] = t;
 }
 
 __global__ void k_sum_pairs(const double* __restrict__ partials, size_t count, double* __restrict__ out) {

@@ -15,13 +15,33 @@
 
 namespace fmg {
 
+// Grid kernels: logical block (bx, by, bz) covers kBlock nodes of row
+// (j, l) = (1 + by, 1 + bz).  The launch is one-dimensional with
+// grid_blocks() blocks; hardware block ids go to the 8 XCDs in turn, and the
+// remap below hands each XCD a contiguous range of logical blocks (whole rows,
+// hence neighbouring rows and planes), so stencil neighbours read by one block
+// were usually brought into that XCD's L2 by the block before it.
+template <int DIM>
+__host__ __device__ inline int logical_blocks(int n) {
+  const int gx = (n - 1 + kBlock - 1) / kBlock;
+  return gx * (n - 1) * (DIM == 3 ? n - 1 : 1);
+}
+template <int DIM>
+__host__ __device__ inline int grid_blocks(int n) { return ((logical_blocks<DIM>(n) + 7) / 8) * 8; }
+
 // Thread -> interior node (i, j, l) of a grid kernel launched with
-// dim3((n-1+255)/256, n-1, DIM==3 ? n-1 : 1) blocks of 256 threads.
+// grid_blocks<DIM>(n) blocks of kBlock threads.
 template <int DIM>
 __device__ __forceinline__ bool node_of_thread(const Grid& g, int& i, int& j, int& l) {
-  i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
-  j = 1 + blockIdx.y;
-  l = DIM == 3 ? 1 + blockIdx.z : 0;
+  const int nb = logical_blocks<DIM>(g.n);
+  const int per = (nb + 7) >> 3;
+  const int L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (L >= nb) return false;
+  const int gx = (g.n - 1 + kBlock - 1) / kBlock, gy = g.n - 1;
+  const int bx = L % gx, r = L / gx;
+  i = 1 + bx * kBlock + threadIdx.x;
+  j = 1 + r % gy;
+  l = DIM == 3 ? 1 + r / gy : 0;
   return i < g.n;
 }
 
