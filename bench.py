@@ -159,7 +159,7 @@ def roofline_live(B, H, dim, workload, reps, stream=None):
             "launches_timed": reps, "avg_launch_us": ms * 1e3, "bytes_per_launch": nbytes,
             "bytes_model": "each nodal array of the launch read or written once: "
                            + ("s(3N + N_c), N, N_c interior nodes of the level and of the next coarser"
-                              if dim == 2 else "3sN, N interior nodes of the level"),
+                              if dim == 2 else "3sN (read x, b; write x'), N interior nodes of the level"),
             "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT) if traffic is not None else None}
 
 

@@ -112,7 +112,9 @@ typedef struct {
                             launch (0: never; default 4096 in 2D, 0 in 3D)   */
     int sweep_rows;     /* 2D V(2,2) levels: rows marched by each wavefront of
                            the register-streaming level kernels (4..4096);
-                           0 = chosen per level; -1 = LDS-tiled kernels     */
+                           0 = chosen per level; -1 = LDS-tiled kernels.
+                           3D: a positive value also selects the
+                           plane-marching sweep (else one node per thread) */
 } fmg_options;
 
 typedef struct {
@@ -203,7 +205,8 @@ int fmg_level_op(fmg_hierarchy *h, int op, int level, int precision,
  * `kernel` is a kernel class as reported by fmg_profile_solve and named by
  * fmg_kernel_name; supported: the fused 2D V(2,2) level kernels
  * ("pre_sweeps_restrict_2d*", "prolong_post_sweeps_2d*", whichever variant
- * the hierarchy's options select) and the separate sweep
+ * the hierarchy's options select), the 3D plane-marching sweep
+ * ("smooth_3d_stream_f64/f32") and the separate sweep
  * ("smooth_f64/f32"), residual-restriction and prolongation-correction
  * kernels, in float64 or (mixed-mode hierarchies) float32.  The kernel is
  * launched with the solve's launch shape on level `level` (2..levels) of the

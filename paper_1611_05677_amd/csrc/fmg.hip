@@ -19,6 +19,7 @@
 #include "fmg_kernels_fmgtail.h"
 #include "fmg_kernels_fused2d.h"
 #include "fmg_kernels_stream2d.h"
+#include "fmg_kernels_stream3d.h"
 #include "fmg_newton_reg.h"
 
 using namespace fmg;
@@ -202,7 +203,7 @@ enum KernelClass {
   KC_TRANSITION, KC_RHS, KC_RESID_F32, KC_ADD_F32, KC_AUG_PASS0, KC_AUG_PASS, KC_OUTPUT_UPDATE,
   KC_NEWTON_FINISH, KC_AUG_UPDATE, KC_LEVEL1, KC_BEGIN, KC_OUTPUT, KC_END, KC_FILL,
   KC_VCYCLE_TAIL64, KC_VCYCLE_TAIL32, KC_FMG_TAIL, KC_AUG_SMALL, KC_PRE2D64, KC_POST2D64, KC_PRE2D32, KC_POST2D32,
-  KC_PRE2S64, KC_POST2S64, KC_PRE2S32, KC_POST2S32, KC_COUNT
+  KC_PRE2S64, KC_POST2S64, KC_PRE2S32, KC_POST2S32, KC_SMOOTH3S64, KC_SMOOTH3S32, KC_COUNT
 };
 const char* const kKernelNames[KC_COUNT] = {
   "smooth_f64", "smooth_f64_from_zero", "resid_restrict_f64", "prolong_add_f64", "coarse_solve_f64",
@@ -212,7 +213,8 @@ const char* const kKernelNames[KC_COUNT] = {
   "vcycle_tail_f64", "vcycle_tail_f32", "fmg_tail", "aug_solve_small", "pre_sweeps_restrict_2d_f64", "prolong_post_sweeps_2d_f64",
   "pre_sweeps_restrict_2d_f32", "prolong_post_sweeps_2d_f32",
   "pre_sweeps_restrict_2d_stream_f64", "prolong_post_sweeps_2d_stream_f64",
-  "pre_sweeps_restrict_2d_stream_f32", "prolong_post_sweeps_2d_stream_f32"};
+  "pre_sweeps_restrict_2d_stream_f32", "prolong_post_sweeps_2d_stream_f32",
+  "smooth_3d_stream_f64", "smooth_3d_stream_f32"};
 
 // Event pairs around launches (fmg_profile_solve only).
 struct Prof {
@@ -355,6 +357,27 @@ double launch_post2(const fmg_hierarchy* h, int k, const T* x, const T* xc, cons
   return bytes;
 }
 
+// One weighted-Jacobi sweep t = x + wd (b - A x) on level k: the grid kernel,
+// or in 3D on request (positive sweep_rows) the plane-marching kernel.
+template <int DIM, typename T>
+double launch_sweep(const fmg_hierarchy* h, int k, const T* x, const T* b, T* t, T wd, hipStream_t st) {
+  const LevelInfo& L = h->plan.lev[k];
+  const long long N = interior(L.g, DIM);
+  const double bytes = 3.0 * sizeof(T) * N;
+  const int kc = Sel<T>::kc ? 1 : 0;
+  const T scale = (T)L.scale;
+  if (DIM == 3 && h->ro.o.sweep_rows > 0 && L.g.n >= 16) {
+    int zc = 0, nzc = 0;
+    const int blocks = smooth3s_blocks(L.g.n, zc, nzc);
+    FMG_LAUNCH(h, st, KC_SMOOTH3S64 + kc, k, N, bytes,
+               k_smooth3s<T><<<blocks, 64 * kS3Waves, 0, st>>>(L.g, x, b, t, wd, scale, zc, nzc));
+  } else {
+    FMG_LAUNCH(h, st, KC_SMOOTH64 + (Sel<T>::kc ? KC_SMOOTH32 - KC_SMOOTH64 : 0), k, N, bytes,
+               k_smooth<DIM, T, false><<<grid_of(L.g, DIM), kBlock, 0, st>>>(L.g, x, b, t, wd, scale));
+  }
+  return bytes;
+}
+
 template <int DIM, typename T>
 void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t st) {
   const Plan& p = h->plan;
@@ -413,8 +436,7 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
       FMG_LAUNCH(h, st, KC_SMOOTH64_ZERO + kc, k, N, 2 * s * N,
                  k_smooth<DIM, T, true><<<grid, kBlock, 0, st>>>(L.g, x, b, t, wd, scale));
     else
-      FMG_LAUNCH(h, st, KC_SMOOTH64 + kc, k, N, 3 * s * N,
-                 k_smooth<DIM, T, false><<<grid, kBlock, 0, st>>>(L.g, x, b, t, wd, scale));
+      launch_sweep<DIM, T>(h, k, x, b, t, wd, st);
     std::swap(x, t);
   }
   const LevelInfo& C = p.lev[k - 1];
@@ -427,8 +449,7 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
              k_prolong<DIM, T, true><<<grid, kBlock, 0, st>>>(C.g, L.g, Sel<T>::x(R, k - 1), x));
   for (int i = 0; i < npost; ++i) {
     const T wd = (T)(h->ro.post[i] / D);
-    FMG_LAUNCH(h, st, KC_SMOOTH64 + kc, k, N, 3 * s * N,
-               k_smooth<DIM, T, false><<<grid, kBlock, 0, st>>>(L.g, x, b, t, wd, scale));
+    launch_sweep<DIM, T>(h, k, x, b, t, wd, st);
     std::swap(x, t);
   }
 }
@@ -1221,6 +1242,11 @@ int time_launch(fmg_hierarchy* h, int base, int k, hipStream_t st, double& bytes
       bytes = 3 * s * N;
       k_smooth<DIM, T, false><<<grid_of(L.g, DIM), kBlock, 0, st>>>(L.g, x, b, t, (T)(h->ro.pre[0] / D), scale);
       return FMG_OK;
+    case KC_SMOOTH3S64: {
+      if (DIM != 3 || h->ro.o.sweep_rows <= 0 || L.g.n < 16) return FMG_E_UNSUPPORTED;
+      bytes = launch_sweep<DIM, T>(h, k, x, b, t, (T)(h->ro.pre[0] / D), st);
+      return FMG_OK;
+    }
     case KC_RESTRICT64:
       bytes = s * (2 * N + Nc);
       k_resid_restrict<DIM, T><<<grid_of(C.g, DIM), kBlock, 0, st>>>(L.g, C.g, x, b, Sel<T>::b(h, k - 1), scale);
@@ -1240,8 +1266,11 @@ int time_launch_any(fmg_hierarchy* h, int kernel, int k, hipStream_t st, double&
   const int d_mg = KC_SMOOTH32 - KC_SMOOTH64, d_2d = KC_PRE2D32 - KC_PRE2D64;
   switch (kernel) {
     case KC_SMOOTH64: case KC_RESTRICT64: case KC_PROLONG64_ADD:
-    case KC_PRE2D64: case KC_POST2D64: case KC_PRE2S64: case KC_POST2S64:
+    case KC_PRE2D64: case KC_POST2D64: case KC_PRE2S64: case KC_POST2S64: case KC_SMOOTH3S64:
       return time_launch<DIM, double>(h, kernel, k, st, bytes);
+    case KC_SMOOTH3S32:
+      if (!h->plan.off_xs[k]) return FMG_E_UNSUPPORTED;
+      return time_launch<DIM, float>(h, KC_SMOOTH3S64, k, st, bytes);
     case KC_SMOOTH32: case KC_RESTRICT32: case KC_PROLONG32_ADD:
       if (!h->plan.off_xs[k]) return FMG_E_UNSUPPORTED;
       return time_launch<DIM, float>(h, kernel - d_mg, k, st, bytes);

@@ -249,3 +249,18 @@ def test_streaming_kernels_on_wide_level_match_replica():
     assert rep["status"] == 0
     expect = o2_fmg(o2_hier(P), P.g_nodes, Nonlinearity(P.f_kind)).full()
     assert rel(u, expect) <= PARITY
+
+
+@pytest.mark.parametrize("precision", [B.FMG_FP64, B.FMG_MIXED], ids=["fp64", "mixed"])
+def test_plane_marching_3d_sweep_matches_grid_sweep(precision):
+    """3D V-cycles with the plane-marching sweep (levels with n >= 16, several
+    z chunks, strips and row groups with ragged ends) against the
+    one-node-per-thread sweep."""
+    P = W.cube_u_plus_sin(4)
+    u_s, r1 = gpu_solve(P, precision=precision, tail_max_nodes=0, sweep_rows=8)
+    u_g, r2 = gpu_solve(P, precision=precision, tail_max_nodes=0, sweep_rows=-1)
+    assert r1["status"] == 0 and r2["status"] == 0
+    assert rel(u_s, u_g) <= (1e-13 if precision == B.FMG_FP64 else 1e-9)
+    if precision == B.FMG_FP64:
+        expect = o2_fmg(o2_hier(P), P.g_nodes, Nonlinearity(P.f_kind, P.f_param)).full()
+        assert rel(u_s, expect) <= PARITY

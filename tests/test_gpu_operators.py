@@ -146,5 +146,11 @@ def test_level_kernel_timer():
     ms, nb = B.time_level_kernel(H3, "smooth_f64", H3.levels, 3)
     assert ms > 0 and nb == 8 * 3 * (H3.n - 1) ** 3
     with pytest.raises(B.FMGError):
+        B.time_level_kernel(H3, "smooth_3d_stream_f64", H3.levels, 1)        # not selected by default
+    H3s = B.Hierarchy(3, 4, 3, B.default_options(3, sweep_rows=8), device=DEV)
+    ms, nb = B.time_level_kernel(H3s, "smooth_3d_stream_f64", H3s.levels, 3)
+    assert ms > 0 and nb == 8 * 3 * (H3s.n - 1) ** 3
+    H3s.close()
+    with pytest.raises(B.FMGError):
         B.time_level_kernel(H3, "smooth_f32", H3.levels, 1)                  # no float32 buffers
     H3.close()
