@@ -50,6 +50,8 @@ struct LevelInfo {
 struct Plan {
   int dim, nH, nlev, N1;
   int tail_top;            // deepest level handled by the single-workgroup tail (0: none)
+  int tail_dense;          // 1: levels <= tail_top apply the V-cycle as a dense operator
+  size_t off_tailB[FMG_MAX_LEVELS + 1];   // B_k (N_k x N_k float64, row-major), k = 2..tail_top
   LevelInfo lev[FMG_MAX_LEVELS + 1];   // 1-based
   size_t off_state, off_report, off_slot, off_flag, off_norm_out, off_norm_part;
   size_t off_A1, off_A1inv, off_A1inv_f, off_pq, off_ps;
@@ -146,6 +148,17 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p) {
     for (int k = 2; k <= std::min(p.nlev, kTailLevels); ++k) {
       const long long m = p.lev[k].g.n - 1;
       if ((d == 2 ? m * m : m * m * m) <= ro.o.tail_max_nodes) p.tail_top = k;
+    }
+  p.tail_dense = 0;
+  if (p.tail_top >= 2) {
+    const long long m = p.lev[p.tail_top].g.n - 1;
+    p.tail_dense = (d == 2 ? m * m : m * m * m) <= kDenseTailMax ? 1 : 0;
+  }
+  for (int k = 0; k <= FMG_MAX_LEVELS; ++k) p.off_tailB[k] = 0;
+  if (p.tail_dense)
+    for (int k = 2; k <= p.tail_top; ++k) {
+      const size_t m = p.lev[k].g.n - 1, N = d == 2 ? m * m : m * m * m;
+      p.off_tailB[k] = take(sizeof(double) * N * N);
     }
   p.off_pq = take(sizeof(double) * max_blocks * Acc<3>::NQ);
   p.off_ps = take(sizeof(double) * max_blocks * Acc<3>::NS);
@@ -391,6 +404,17 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
   if (k == 1) {
     FMG_LAUNCH(h, st, KC_COARSE64 + kc, 1, N, 2 * s * N,
                k_coarse_solve<DIM, T><<<1, 64, 0, st>>>(L.g, p.N1, Sel<T>::ainv(h), b, x));
+    return;
+  }
+  if (k <= p.tail_top && p.tail_dense) {
+    // x_k = x0 + B_k (b_k - A_k x0) (zero start: B_k b_k), written to the
+    // spare array so no block reads what another writes; roles of level k swap
+    const long long Nk = interior(L.g, DIM);
+    const int blocks = (int)((Nk + 3) / 4);
+    FMG_LAUNCH(h, st, KC_VCYCLE_TAIL64 + (Sel<T>::kc ? 1 : 0), k, N, 8.0 * Nk * Nk + 3.0 * s * N,
+               k_tail_dense<DIM, T><<<blocks, 256, sizeof(double) * Nk, st>>>(
+                   L.g, h->at<double>(p.off_tailB[k]), (int)Nk, x, b, t, (T)L.scale, zero_init ? 1 : 0));
+    std::swap(x, t);
     return;
   }
   if (k <= p.tail_top) {
@@ -693,6 +717,119 @@ void build_level1(const Plan& p, std::vector<double>& A, std::vector<double>& Ai
   }
 }
 
+// The V-cycle of levels k..1 from a zero start is a linear map b_k -> x_k
+// (pre-smoothing, residual, P^T, exact level-1 solve, P-correction,
+// post-smoothing; the same steps and weights as the device cycle).  Its
+// matrix B_k is built here by running that cycle on the host for every unit
+// vector; a cycle from x0 is then x0 + B_k (b - A_k x0).
+struct HostLevel {
+  int n;
+  double scale;
+  std::vector<double> x, t, b;
+};
+
+void build_tail_operators(const Plan& p, const Resolved& ro, const std::vector<double>& A1inv,
+                          std::vector<std::vector<double>>& Bs) {
+  const int d = p.dim;
+  Bs.assign(p.tail_top + 1, {});
+  auto idx = [&](int n, int i, int j, int l) { return i + (n + 1) * (j + (n + 1) * l); };
+  auto count = [&](int n) { return (size_t)(d == 2 ? (n + 1) * (n + 1) : (n + 1) * (n + 1) * (n + 1)); };
+  auto interior = [&](int n, auto&& fn) {
+    for (int l = (d == 3 ? 1 : 0); l <= (d == 3 ? n - 1 : 0); ++l)
+      for (int j = 1; j <= n - 1; ++j)
+        for (int i = 1; i <= n - 1; ++i) fn(i, j, l);
+  };
+  auto applyA = [&](const HostLevel& L, const std::vector<double>& x, int i, int j, int l) {
+    const int n = L.n, c = idx(n, i, j, l), px = n + 1, pz = (n + 1) * (n + 1);
+    double sm = (x[c - 1] + x[c + 1]) + (x[c - px] + x[c + px]);
+    if (d == 3) sm += x[c - pz] + x[c + pz];
+    return L.scale * (2.0 * d * x[c] - sm);
+  };
+  for (int top = 2; top <= p.tail_top; ++top) {
+    std::vector<HostLevel> lv(top + 1);
+    for (int k = 1; k <= top; ++k) {
+      lv[k].n = p.lev[k].g.n;
+      lv[k].scale = p.lev[k].scale;
+      lv[k].x.assign(count(lv[k].n), 0.0);
+      lv[k].t.assign(count(lv[k].n), 0.0);
+      lv[k].b.assign(count(lv[k].n), 0.0);
+    }
+    const int nt = lv[top].n, mt = nt - 1;
+    const size_t N = d == 2 ? (size_t)mt * mt : (size_t)mt * mt * mt;
+    std::vector<double>& B = Bs[top];
+    B.assign(N * N, 0.0);
+    for (size_t q = 0; q < N; ++q) {
+      for (int k = 1; k <= top; ++k) {
+        std::fill(lv[k].x.begin(), lv[k].x.end(), 0.0);
+        std::fill(lv[k].b.begin(), lv[k].b.end(), 0.0);
+      }
+      {
+        const int i = 1 + (int)(q % mt), j = 1 + (int)((q / mt) % mt), l = d == 3 ? 1 + (int)(q / ((size_t)mt * mt)) : 0;
+        lv[top].b[idx(nt, i, j, l)] = 1.0;
+      }
+      for (int k = top; k >= 2; --k) {
+        HostLevel& L = lv[k];
+        const double D = 2.0 * d * L.scale;
+        for (int s = 0; s < ro.o.nu_pre; ++s) {
+          const double wd = ro.pre[s] / D;
+          interior(L.n, [&](int i, int j, int l) {
+            const int c = idx(L.n, i, j, l);
+            L.t[c] = L.x[c] + wd * (L.b[c] - applyA(L, L.x, i, j, l));
+          });
+          std::swap(L.x, L.t);
+        }
+        HostLevel& C = lv[k - 1];
+        interior(C.n, [&](int i, int j, int l) {
+          const int q0 = idx(L.n, 2 * i, 2 * j, 2 * l), n = L.n, px = n + 1, pz = (n + 1) * (n + 1);
+          auto r = [&](int c) {
+            const int li = c % px, lj = (c / px) % px, ll = d == 3 ? c / pz : 0;
+            return L.b[c] - applyA(L, L.x, li, lj, ll);
+          };
+          double h = (r(q0 + 1) + r(q0 - 1)) + (r(q0 + px) + r(q0 - px)) + (r(q0 + 1 + px) + r(q0 - 1 - px));
+          if (d == 3)
+            h += (r(q0 + pz) + r(q0 - pz)) + (r(q0 + 1 + pz) + r(q0 - 1 - pz)) + (r(q0 + px + pz) + r(q0 - px - pz)) +
+                 (r(q0 + 1 + px + pz) + r(q0 - 1 - px - pz));
+          C.b[idx(C.n, i, j, l)] = r(q0) + 0.5 * h;
+        });
+      }
+      {
+        HostLevel& L1 = lv[1];
+        const int m1 = L1.n - 1;
+        for (int rr = 0; rr < p.N1; ++rr) {
+          double sm = 0.0;
+          for (int c = 0; c < p.N1; ++c) {
+            const int i = 1 + c % m1, j = 1 + (c / m1) % m1, l = d == 3 ? 1 + c / (m1 * m1) : 0;
+            sm += A1inv[(size_t)rr * p.N1 + c] * L1.b[idx(L1.n, i, j, l)];
+          }
+          const int i = 1 + rr % m1, j = 1 + (rr / m1) % m1, l = d == 3 ? 1 + rr / (m1 * m1) : 0;
+          L1.x[idx(L1.n, i, j, l)] = sm;
+        }
+      }
+      for (int k = 2; k <= top; ++k) {
+        HostLevel& L = lv[k];
+        const HostLevel& C = lv[k - 1];
+        interior(L.n, [&](int i, int j, int l) {
+          const int si = i & 1, sj = j & 1, sl = d == 3 ? (l & 1) : 0;
+          double v = C.x[idx(C.n, i >> 1, j >> 1, l >> 1)];
+          if (si | sj | sl) v = 0.5 * (v + C.x[idx(C.n, (i >> 1) + si, (j >> 1) + sj, (l >> 1) + sl)]);
+          L.x[idx(L.n, i, j, l)] += v;
+        });
+        const double D = 2.0 * d * L.scale;
+        for (int s = 0; s < ro.o.nu_post; ++s) {
+          const double wd = ro.post[s] / D;
+          interior(L.n, [&](int i, int j, int l) {
+            const int c = idx(L.n, i, j, l);
+            L.t[c] = L.x[c] + wd * (L.b[c] - applyA(L, L.x, i, j, l));
+          });
+          std::swap(L.x, L.t);
+        }
+      }
+      size_t row = 0;
+      interior(nt, [&](int i, int j, int l) { B[row++ * N + q] = lv[top].x[idx(nt, i, j, l)]; });
+    }
+  }
+}
+
 }  // namespace
 
 namespace {
@@ -858,6 +995,23 @@ int fmg_create_hierarchy(const fmg_mesh_desc* mesh, const fmg_options* opts, voi
   for (auto& g : h->graph) g = nullptr;
   h->prof = nullptr;
   if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete h; return FMG_E_HIP; }
+  // the LDS-resident V-cycle tail may use up to the whole 160 KB of a workgroup
+  {
+    const int lim = (int)kTailLdsMax;
+    const hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vcycle_tail_lds<2, double>),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    const hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vcycle_tail_lds<2, float>),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    const hipError_t e3 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vcycle_tail_lds<3, double>),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    const hipError_t e4 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vcycle_tail_lds<3, float>),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+      (void)hipStreamDestroy(h->cap_stream);
+      delete h;
+      return FMG_E_HIP;
+    }
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   // zero every level array once: the Dirichlet rings stay zero for good
   for (int k = 1; k <= p.nlev; ++k) {
@@ -901,6 +1055,17 @@ int fmg_create_hierarchy(const fmg_mesh_desc* mesh, const fmg_options* opts, voi
   }
   std::vector<double> A, Ainv;
   build_level1(p, A, Ainv);
+  if (p.tail_dense) {
+    std::vector<std::vector<double>> Bs;
+    build_tail_operators(p, ro, Ainv, Bs);
+    for (int k = 2; k <= p.tail_top; ++k)
+      if (hipMemcpy(h->at<double>(p.off_tailB[k]), Bs[k].data(), Bs[k].size() * sizeof(double),
+                    hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipStreamDestroy(h->cap_stream);
+        delete h;
+        return FMG_E_HIP;
+      }
+  }
   std::vector<float> Ainv_f(Ainv.begin(), Ainv.end());
   if (hipMemcpyAsync(h->at<double>(p.off_A1), A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice, s) !=
           hipSuccess ||

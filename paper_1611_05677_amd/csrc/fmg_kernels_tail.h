@@ -13,7 +13,8 @@ namespace fmg {
 constexpr int kTailThreads = 1024;
 constexpr int kTailLevels = 8;   // deepest level a tail launch may start from
 constexpr int kTailSweeps = 8;   // max sweeps per level in a tail launch
-constexpr size_t kTailLdsMax = 64 * 1024;   // LDS-resident tail up to this many bytes
+constexpr size_t kTailLdsMax = 160 * 1024;  // LDS-resident tail up to this many bytes (gfx950 workgroup limit)
+constexpr long long kDenseTailMax = 1024;    // dense-operator tail up to this many top-level unknowns
 
 template <typename T>
 struct TailArgs {
@@ -309,6 +310,39 @@ inline size_t tail_lds_elements(const int* n, int top, int* off) {
     e += 3 * c;
   }
   return e;
+}
+
+// ---------------------------------------------------------------------------
+// Dense-operator variant: the cycle from x0 equals x0 + B (b - A x0) with B the
+// cycle's matrix (built on the host from the same steps).  Every block forms
+// the residual r = b - A x0 of the N top-level unknowns in LDS (float64),
+// then each wavefront produces one output row as a 64-lane dot product.
+// out must not alias x0.
+// ---------------------------------------------------------------------------
+template <int DIM, typename T>
+__global__ void __launch_bounds__(256) k_tail_dense(Grid g, const double* __restrict__ B, int N,
+                                                    const T* __restrict__ x0, const T* __restrict__ b,
+                                                    T* __restrict__ out, T scale, int zero) {
+  extern __shared__ double r[];
+  const int m = g.n - 1;
+  for (int q = threadIdx.x; q < N; q += blockDim.x) {
+    const int i = 1 + q % m, j = 1 + (q / m) % m, l = DIM == 3 ? 1 + q / (m * m) : 0;
+    const int c = gidx<DIM>(g, i, j, l);
+    r[q] = zero ? (double)b[c] : (double)(b[c] - apply_A_at<DIM>(x0, c, g, scale));
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= N) return;                      // whole wavefront leaves together
+  const double* __restrict__ Br = B + (size_t)row * N;
+  double acc = 0.0;
+  for (int q = lane; q < N; q += 64) acc += Br[q] * r[q];
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const int i = 1 + row % m, j = 1 + (row / m) % m, l = DIM == 3 ? 1 + row / (m * m) : 0;
+    const int c = gidx<DIM>(g, i, j, l);
+    out[c] = zero ? (T)acc : (T)((double)x0[c] + acc);
+  }
 }
 
 }  // namespace fmg
