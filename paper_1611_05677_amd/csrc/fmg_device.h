@@ -167,6 +167,32 @@ __device__ __forceinline__ double wave_sum(double v) {
   return lane_value(v, 63);
 }
 
+// Sum over aligned segments of LPC lanes (LPC = 4, 8, 16, 32 or 64); the
+// last lane of each segment receives its segment's total (LPC <= 16: every
+// lane of the segment does).
+template <int LPC>
+__device__ __forceinline__ double seg_sum(double v) {
+  static_assert(LPC == 4 || LPC == 8 || LPC == 16 || LPC == 32 || LPC == 64, "segment size");
+  v += dpp_move<0xb1>(v);                        // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);                        // quad_perm [2,3,0,1]: quad sums
+  if (LPC >= 8) v += dpp_move<0x141>(v);         // row_half_mirror: the other quad of the half-row
+  if (LPC >= 16) v += dpp_move<0x140>(v);        // row_mirror: the other half of the row
+  if (LPC >= 32) v += dpp_move<0x142, 0xa>(v);   // row_bcast 15 into rows 1 and 3
+  if (LPC >= 64) v += dpp_move<0x143, 0xc>(v);   // row_bcast 31 into rows 2 and 3
+  return v;
+}
+
+// 1 / sqrt(d) for d > 0: the hardware estimate refined by two Newton steps
+// (quadratic convergence from ~2^-29 relative error to full double accuracy),
+// a short dependent chain in place of the correctly rounded sqrt and divide.
+__device__ __forceinline__ double fast_rsqrt(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double hd = 0.5 * d;
+  y = y * (1.5 - hd * y * y);
+  y = y * (1.5 - hd * y * y);
+  return y;
+}
+
 // Maximum over the 64 lanes (inputs >= 0), returned to every lane.
 __device__ __forceinline__ double wave_max_nonneg(double v) {
   v = fmax(v, dpp_move<0xb1>(v));

@@ -668,24 +668,65 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
   if (threadIdx.x == 0) __hip_atomic_store(&tickets[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Per-cell quadrature sums of all cells by one block: wavefront w reduces
-// cells w, w + nwaves, ... (no block barrier inside).
-template <int DIM, int KIND>
-__device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShape& s, const double* __restrict__ ut,
-                                           const double* ytry, double param, double* cs) {
+// Per-cell sums of all cells by one block.  A cell's r^d fine nodes are
+// spread over a segment of LPC = min(64, r^d) lanes, so a wavefront holds
+// 64 / LPC cells and reduces each accumulator over its segment only; the last
+// lane of a segment writes the cell's sums.  No block barrier inside.
+template <int DIM, int KIND, int LPC>
+__device__ __forceinline__ void quad_cells_seg(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                               const double* ytry, double param, double* cs) {
   using AC = Acc<DIM>;
+  constexpr int CPW = 64 / LPC;
   const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int sub = lane % LPC;
   const int nodes = 1 << (DIM * s.log2r);
-  for (int cell = wave; cell < ncell; cell += nw) {
+  for (int c0 = wave * CPW; c0 < ncell; c0 += nw * CPW) {
+    const int cell = c0 + lane / LPC;
     double acc[AC::NQ];
 #pragma unroll
     for (int q = 0; q < AC::NQ; ++q) acc[q] = 0.0;
-    quad_accumulate<DIM, KIND>(g, s, ut, ytry, param, cell, 0, nodes, lane, 64, acc);
+    if (cell < ncell) quad_accumulate<DIM, KIND>(g, s, ut, ytry, param, cell, 0, nodes, sub, LPC, acc);
 #pragma unroll
     for (int q = 0; q < AC::NQ; ++q) {
-      const double v = wave_sum(acc[q]);
-      if (lane == 0) cs[cell * AC::NQ + q] = v;
+      const double v = seg_sum<LPC>(acc[q]);
+      if (sub == LPC - 1 && cell < ncell) cs[cell * AC::NQ + q] = v;
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIM, int KIND>
+__device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                           const double* ytry, double param, double* cs) {
+  const int nodes_log = DIM * s.log2r;
+  if (nodes_log <= 2) quad_cells_seg<DIM, KIND, 4>(g, s, ut, ytry, param, cs);
+  else if (nodes_log == 3) quad_cells_seg<DIM, KIND, 8>(g, s, ut, ytry, param, cs);
+  else if (nodes_log == 4) quad_cells_seg<DIM, KIND, 16>(g, s, ut, ytry, param, cs);
+  else if (nodes_log == 5) quad_cells_seg<DIM, KIND, 32>(g, s, ut, ytry, param, cs);
+  else quad_cells_seg<DIM, KIND, 64>(g, s, ut, ytry, param, cs);
+}
+
+template <int DIM, int LPC>
+__device__ __forceinline__ void setup_cells_seg(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                                const double* __restrict__ gl, int nf1, int fs, double scale,
+                                                double* cs) {
+  using AC = Acc<DIM>;
+  constexpr int CPW = 64 / LPC;
+  const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int sub = lane % LPC;
+  const int nodes = 1 << (DIM * s.log2r);
+  for (int c0 = wave * CPW; c0 < ncell; c0 += nw * CPW) {
+    const int cell = c0 + lane / LPC;
+    double acc[AC::NS];
+#pragma unroll
+    for (int q = 0; q < AC::NS; ++q) acc[q] = 0.0;
+    if (cell < ncell) setup_accumulate<DIM>(g, s, ut, gl, nf1, fs, scale, cell, 0, nodes, sub, LPC, acc);
+#pragma unroll
+    for (int q = 0; q < AC::NS; ++q) {
+      const double v = seg_sum<LPC>(acc[q]);
+      if (sub == LPC - 1 && cell < ncell) cs[cell * AC::NS + q] = v;
     }
   }
   __syncthreads();
@@ -695,22 +736,12 @@ template <int DIM>
 __device__ __forceinline__ void setup_cells_by_waves(const Grid& g, const AugShape& s, const double* __restrict__ ut,
                                             const double* __restrict__ gl, int nf1, int fs, double scale,
                                             double* cs) {
-  using AC = Acc<DIM>;
-  const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int nodes = 1 << (DIM * s.log2r);
-  for (int cell = wave; cell < ncell; cell += nw) {
-    double acc[AC::NS];
-#pragma unroll
-    for (int q = 0; q < AC::NS; ++q) acc[q] = 0.0;
-    setup_accumulate<DIM>(g, s, ut, gl, nf1, fs, scale, cell, 0, nodes, lane, 64, acc);
-#pragma unroll
-    for (int q = 0; q < AC::NS; ++q) {
-      const double v = wave_sum(acc[q]);
-      if (lane == 0) cs[cell * AC::NS + q] = v;
-    }
-  }
-  __syncthreads();
+  const int nodes_log = DIM * s.log2r;
+  if (nodes_log <= 2) setup_cells_seg<DIM, 4>(g, s, ut, gl, nf1, fs, scale, cs);
+  else if (nodes_log == 3) setup_cells_seg<DIM, 8>(g, s, ut, gl, nf1, fs, scale, cs);
+  else if (nodes_log == 4) setup_cells_seg<DIM, 16>(g, s, ut, gl, nf1, fs, scale, cs);
+  else if (nodes_log == 5) setup_cells_seg<DIM, 32>(g, s, ut, gl, nf1, fs, scale, cs);
+  else setup_cells_seg<DIM, 64>(g, s, ut, gl, nf1, fs, scale, cs);
 }
 
 // Completes a Newton solve that the passes of the launch sequence did not

@@ -36,8 +36,8 @@ __device__ __forceinline__ void chol_reg(double (&jr)[NY], double& myrd) {
 #pragma unroll
   for (int k = 0; k < NY - 1; ++k) {
     const double dkk = lane_value(jr[k], k);
-    const double sk = sqrt(dkk);
-    const double rk = 1.0 / sk;
+    const double rk = fast_rsqrt(dkk);
+    const double sk = dkk * rk;
     const double lik = lane > k ? jr[k] * rk : 0.0;
     if (lane == k) { jr[k] = sk; myrd = rk; }
     if (lane > k) jr[k] = lik;
@@ -227,7 +227,7 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
     chol_reg<NY>(jr, myrd);
     const double schur = lane_value(jr[N1], N1);
     const bool drop = !(schur > kSchurDrop * Juu);
-    if (!drop && lane == N1) { jr[N1] = sqrt(schur); myrd = 1.0 / jr[N1]; }
+    if (!drop && lane == N1) { myrd = fast_rsqrt(schur); jr[N1] = schur * myrd; }
     const double dv = chol_solve_reg<NY>(jr, myrd, drop ? N1 : NY, act ? -Rl : 0.0, J);
     dnew = dv;
     slope = wave_allsum(Rl * dv);
@@ -304,7 +304,7 @@ __device__ __forceinline__ void level1_newton_reg(const Grid& g1, double m1, con
     }
     double myrd = 0.0;
     chol_reg<N1>(jr, myrd);
-    if (lane == N1 - 1) { jr[N1 - 1] = sqrt(jr[N1 - 1]); myrd = 1.0 / jr[N1 - 1]; }
+    if (lane == N1 - 1) { myrd = fast_rsqrt(jr[N1 - 1]); jr[N1 - 1] = jr[N1 - 1] * myrd; }
     const double D = chol_solve_reg<N1>(jr, myrd, N1, node ? -R : 0.0, sm);
     const double slope = wave_allsum(R * D);
     double t = 1.0, Et = 0.0, St = 0.0, T = U;
