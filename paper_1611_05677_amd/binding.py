@@ -12,6 +12,12 @@ import os
 from dataclasses import dataclass
 
 import numpy as np
+# torch is imported before the library is loaded: torch ships its own HIP
+# runtime, and the library must bind to that same runtime (already mapped
+# under the same soname).  Loaded the other way round, the process would hold
+# two HIP runtimes and torch's device pointers and streams would be foreign
+# to the library's.
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FMG_LIBRARY", os.path.join(HERE, "libfmg.so"))

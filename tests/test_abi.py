@@ -78,7 +78,10 @@ def test_workspace_bytes_plan():
     for L in (5, 9):
         nodes = sum((4 * 2 ** (k - 1) + 1) * (((4 * 2 ** (k - 1) + 1) + 15) // 16 * 16)
                     for k in range(1, L + 2))
-        assert 24 * nodes <= B.workspace_bytes(2, 4, L) <= 24 * nodes + 4 * 2 ** 20
+        # plus the dense coarse-cycle operators of the levels with <= 1024 unknowns
+        tail = 8 * sum(((4 * 2 ** (k - 1) - 1) ** 2) ** 2 for k in range(2, L + 2)
+                       if (4 * 2 ** (k - 1) - 1) ** 2 <= 1024)
+        assert 24 * nodes + tail <= B.workspace_bytes(2, 4, L) <= 24 * nodes + tail + 4 * 2 ** 20
     mixed = B.default_options(2, precision=B.FMG_MIXED)
     assert B.workspace_bytes(2, 4, 9, mixed) > B.workspace_bytes(2, 4, 9)
     assert B.workspace_bytes(3, 4, 6) > 0
@@ -139,3 +142,12 @@ def test_status_strings():
     for code in range(7):
         assert B.status_str(code)
     assert B.status_str(99) == "unknown status"
+
+
+def test_library_binds_to_torchs_hip_runtime():
+    """Importing the binding maps exactly one HIP runtime (torch's): a second
+    runtime would make torch's device pointers and streams foreign to the
+    library."""
+    maps = open("/proc/self/maps").read()
+    runtimes = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(runtimes) == 1, runtimes
