@@ -325,6 +325,66 @@ def roofline_leg(args, B, torch, factory, depth):
     print(json.dumps({"roofline": roof, "copy_bytes_each_way": 8 * n, "copies": 3}), flush=True)
 
 
+EXAMPLES_DESC = ("the paper's Examples 1-3 on (0,1)^3 (Kuhn tetrahedra, coarse 4^3, m = 2, p = 1): "
+                 "Ex. 1 f = u^3, u = sin sin sin; Ex. 2 -Lap u - exp(-u) = 1 (no closed form); "
+                 "Ex. 3 f = sign(u)|u|^{3/2}, u = sin 2pi x sin 2pi y sin 2pi z; float64, depths 1-6")
+
+
+def examples_mode(args, B, W, torch):
+    """Errors and time per level for the paper's 3D examples: nodal L2 error
+    against the exact solution (Ex. 1, 3) or against the next finer level's
+    solution injected (Ex. 2), with observed rates, and fine DOF/s per level."""
+    depths = list(range(1, args.max_depth + 1))
+    out = {}
+    for ex, factory in ((1, W.cube_example1), (2, W.cube_example2), (3, W.cube_example3)):
+        rows, prev = [], None
+        for L in depths:
+            P = factory(L)
+            g = torch.from_numpy(P.g_nodes).to("cuda:0")
+            H = B.Hierarchy(3, 4, L, B.default_options(3), device="cuda:0")
+            u = torch.empty(H.nodes(), dtype=torch.float64, device="cuda:0")
+            for _ in range(2):
+                H.solve_async(g, P.f_kind, P.f_param, u)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                H.solve_async(g, P.f_kind, P.f_param, u)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            rep = H.report()
+            H.close()
+            n = P.n
+            un = u.cpu().numpy().reshape((n + 1,) * 3)
+            row = {"depth": L, "n": n, "dofs": P.interior_dofs, "ms_per_solve": ms,
+                   "dof_per_s": P.interior_dofs / (ms * 1e-3), "status": rep["status"]}
+            if P.u_exact_nodes is not None:
+                ue = P.u_exact_nodes.reshape((n + 1,) * 3)
+                row["err_nodal_l2"] = float(np.sqrt(np.sum((un - ue) ** 2) / n ** 3))
+            if ex == 2 and prev is not None:
+                # previous (coarser) level's solution against this one at the shared nodes
+                pn = prev.shape[0] - 1
+                diff = prev - un[::2, ::2, ::2]
+                rows[-1]["err_nodal_l2_vs_finer"] = float(np.sqrt(np.sum(diff ** 2) / pn ** 3))
+            prev = un
+            rows.append(row)
+            log(f"example {ex} depth {L}: {ms:.3f} ms, {row['dof_per_s'] / 1e9:.3f} GDOF/s, "
+                f"err {row.get('err_nodal_l2', float('nan')):.3e}")
+        key = "err_nodal_l2" if ex != 2 else "err_nodal_l2_vs_finer"
+        for a, b in zip(rows, rows[1:]):
+            if a.get(key) and b.get(key):
+                b["rate"] = float(np.log2(a[key] / b[key]))
+        out[f"example{ex}"] = rows
+    top = out["example1"][-1]
+    return {
+        "metric": METRIC, "value": top["dof_per_s"], "unit": "DOF/s", "n_gpus": 1, "steps": 5, "warmup": 2,
+        "ms_per_step": top["ms_per_solve"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": EXAMPLES_DESC, "value_is": "Example 1 at the deepest level"},
+        "examples": out,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,7 +392,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", default="square2048", choices=sorted(WORKLOADS) + ["batch64", "serve"])
+    ap.add_argument("--workload", default="square2048",
+                    choices=sorted(WORKLOADS) + ["batch64", "serve", "examples"])
+    ap.add_argument("--max-depth", type=int, default=6, help="examples: deepest refinement")
     ap.add_argument("--requests", type=int, default=1200, help="serve: requests in the trace")
     ap.add_argument("--inflight", type=int, default=8, help="serve: concurrent solves")
     ap.add_argument("--roof-reps", type=int, default=200, help="launches timed for the roofline kernel")
@@ -352,8 +414,9 @@ def main():
     from paper_1611_05677_amd import binding as B
     from paper_1611_05677_amd import workloads as W
 
-    if args.workload in ("batch64", "serve"):
-        line = (batch_mode if args.workload == "batch64" else serve_mode)(args, B, W, torch)
+    if args.workload in ("batch64", "serve", "examples"):
+        mode = {"batch64": batch_mode, "serve": serve_mode, "examples": examples_mode}[args.workload]
+        line = mode(args, B, W, torch)
         print(json.dumps(line), flush=True)
         return
     desc, factory, depth, gkey, disc_scale = WORKLOADS[args.workload]

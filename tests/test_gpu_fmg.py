@@ -264,3 +264,30 @@ def test_plane_marching_3d_sweep_matches_grid_sweep(precision):
     if precision == B.FMG_FP64:
         expect = o2_fmg(o2_hier(P), P.g_nodes, Nonlinearity(P.f_kind, P.f_param)).full()
         assert rel(u_s, expect) <= PARITY
+
+
+def test_paper_examples_converge_at_the_optimal_rate():
+    """The paper's 3D Examples 1-3 through the same path: nodal L2 errors
+    against the exact solution fall by about 4 per refinement (O(h^2)) for
+    Examples 1 and 3; for Example 2 (no closed form) the difference between
+    consecutive levels does."""
+    def nodal_err(P, u):
+        n = P.n
+        return np.sqrt(np.sum((u - P.u_exact_nodes) ** 2) / n ** 3)
+    for factory in (W.cube_example1, W.cube_example3):
+        errs = []
+        for L in (2, 3, 4):
+            P = factory(L)
+            u, rep = gpu_solve(P)
+            assert rep["status"] == 0
+            errs.append(nodal_err(P, u))
+        rates = [np.log2(a / b) for a, b in zip(errs, errs[1:])]
+        assert min(rates) >= 1.8, (factory.__name__, errs, rates)
+    sols = []
+    for L in (2, 3, 4):
+        P = W.cube_example2(L)
+        u, rep = gpu_solve(P)
+        assert rep["status"] == 0
+        sols.append(u.reshape((P.n + 1,) * 3))
+    d = [np.sqrt(np.sum((a - b[::2, ::2, ::2]) ** 2) / (a.shape[0] - 1) ** 3) for a, b in zip(sols, sols[1:])]
+    assert np.log2(d[0] / d[1]) >= 1.8, d
