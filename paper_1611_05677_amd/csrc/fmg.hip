@@ -360,8 +360,8 @@ double launch_post2(const fmg_hierarchy* h, int k, const T* x, const T* xc, cons
     int nch = 0;
     const int blocks = stream_blocks(L.g.n, kPostStrip, rows, nch);
     FMG_LAUNCH(h, st, KC_POST2S64 + kc2, k, N, bytes,
-               k_post2s<T><<<blocks, 64 * kStreamWaves, 0, st>>>(C.g, L.g, x, xc, b, t, wd1, wd2, scale, rows,
-                                                                nch));
+               k_post2s<T, false><<<blocks, 64 * kStreamWaves, 0, st>>>(C.g, L.g, x, xc, b, t, nullptr, wd1, wd2,
+                                                                       scale, rows, nch));
   } else {
     const dim3 tiles((L.g.n + kFTX - 1) / kFTX, (L.g.n + kFTY - 1) / kFTY);
     FMG_LAUNCH(h, st, KC_POST2D64 + kc2, k, N, bytes,
@@ -494,6 +494,42 @@ inline size_t fmg_tail_lds_bytes(const Plan& p) {
   return std::max(aug, lev1) * sizeof(double);
 }
 
+// Mixed mode, one float32 V(2,2) cycle on the correction equation at a 2D
+// level that uses the streaming kernels: the float64 residual is formed inside
+// the pre-smoothing kernel and the correction is added to the float64 iterate
+// inside the post-smoothing kernel (same operations as the separate residual
+// and add kernels, two launches and two passes over the level fewer).
+// Returns false where this does not apply.
+template <int DIM>
+bool mixed_cycle_fused(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st) {
+  const Plan& p = h->plan;
+  const fmg_options& o = h->ro.o;
+  if (DIM != 2 || o.nu_pre != 2 || o.nu_post != 2 || k <= p.tail_top || k < 2) return false;
+  const LevelInfo& L = p.lev[k];
+  const LevelInfo& C = p.lev[k - 1];
+  const int rows = stream_rows(o.sweep_rows, L.g.n);
+  if (rows <= 0) return false;
+  const long long N = interior(L.g, 2), Nc = interior(C.g, 2);
+  const double D = 4.0 * L.scale;
+  double* u = R.x[k];
+  const double* b64 = h->at<double>(p.off_b[k]);
+  float* r32 = h->at<float>(p.off_bs[k]);
+  int nch = 0;
+  const int gpre = stream_blocks(L.g.n, kResStrip, rows, nch);
+  FMG_LAUNCH(h, st, KC_PRE2S32, k, N, 16.0 * N + 8.0 * N + 4.0 * Nc,
+             k_pre2s_resid<<<gpre, 64 * kStreamWaves, 0, st>>>(
+                 L.g, C.g, u, b64, r32, R.ts[k], h->at<float>(p.off_bs[k - 1]), (float)(h->ro.pre[0] / D),
+                 (float)(h->ro.pre[1] / D), (float)L.scale, L.scale, rows, nch));
+  std::swap(R.xs[k], R.ts[k]);
+  vcycle<DIM, float>(h, R, k - 1, true, st);
+  const int gpost = stream_blocks(L.g.n, kPostStrip, rows, nch);
+  FMG_LAUNCH(h, st, KC_POST2S32, k, N, 8.0 * N + 16.0 * N + 4.0 * Nc,
+             k_post2s<float, true><<<gpost, 64 * kStreamWaves, 0, st>>>(
+                 C.g, L.g, R.xs[k], R.xs[k - 1], r32, nullptr, u, (float)(h->ro.post[0] / D),
+                 (float)(h->ro.post[1] / D), (float)L.scale, rows, nch));
+  return true;
+}
+
 // One correction step (Algorithm 3.1) on level k; the current iterate is R.x[k].
 // rhs_ready: b_k was already formed (by the level transition).  defer_update:
 // leave u = Q w + alpha u~ to the consumer (next transition or the output).
@@ -514,7 +550,7 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   for (int c = 0; c < o.m_vcycles; ++c) {
     if (o.precision == FMG_FP64) {
       vcycle<DIM, double>(h, R, k, false, st);
-    } else {
+    } else if (!mixed_cycle_fused<DIM>(h, R, k, st)) {
       // float32 cycle on the correction equation, float64 residual and update
       FMG_LAUNCH(h, st, KC_RESID_F32, k, N, 20.0 * N,
                  k_resid_to_f32<DIM><<<grid, kBlock, 0, st>>>(L.g, R.x[k], b, h->at<float>(p.off_bs[k]),

@@ -184,11 +184,14 @@ __global__ void __launch_bounds__(64 * kStreamWaves)
 
 // x + P xc on level f (coarse cg), then two sweeps; R rows per wave, marched
 // upwards or downwards (alternating by chunk, as in the pre-smoothing kernel).
-template <typename T, bool UP>
+// ADDU (mixed mode, top level of a float32 cycle): the result is the
+// correction e, and instead of storing it the kernel adds it to the float64
+// iterate in place, u += (double) e (the separate add kernel's operation).
+template <typename T, bool UP, bool ADDU>
 __device__ __forceinline__ void post2s_wave(const Grid& cg, const Grid& f, const T* __restrict__ x,
                                             const T* __restrict__ xc, const T* __restrict__ b,
-                                            T* __restrict__ xout, T wd1, T wd2, T scale, int strip, int Y0,
-                                            int R) {
+                                            T* __restrict__ xout, double* __restrict__ u64, T wd1, T wd2,
+                                            T scale, int strip, int Y0, int R) {
   constexpr int D = UP ? 1 : -1;
   const int lane = threadIdx.x & 63;
   const int n = f.n;
@@ -204,7 +207,7 @@ __device__ __forceinline__ void post2s_wave(const Grid& cg, const Grid& f, const
   const int steps = yhi - ylo + 1;
   // queue entries: x, b and the two coarse values of row y; groups of rows as
   // in the pre-smoothing kernel (next group's loads issued at group start)
-  struct Q4 { T x[kPostQueue], b[kPostQueue], c0[kPostQueue], c1[kPostQueue]; };
+  struct Q4 { T x[kPostQueue], b[kPostQueue], c0[kPostQueue], c1[kPostQueue]; double u[kPostQueue]; };
   // (coarse reads clamped into the coarse grid: ci + si <= n/2 for every column)
   auto fetch = [&](Q4& qq, int q, int y) {
     const int yc = clamp_row(y, n);
@@ -213,12 +216,14 @@ __device__ __forceinline__ void post2s_wave(const Grid& cg, const Grid& f, const
     const int cj = yc >> 1, sj = yc & 1;
     qq.c0[q] = xc[cj * cg.px + ci];
     qq.c1[q] = xc[min(cj + sj, cg.n) * cg.px + min(ci + si, cg.n)];
+    if (ADDU) qq.u[q] = u64[yc * f.px + Xc];
   };
   Q4 cur;
 #pragma unroll
   for (int q = 0; q < kPostQueue; ++q) fetch(cur, q, ystart + D * q);
   // windows: corrected x rows y-2D, y-D; b rows y-D, y-2D; sweep-1 rows y-3D, y-2D
   T xa = 0, xb = 0, b1 = 0, b2 = 0, s1a = 0, s1b = 0;
+  double ua = 0.0, ub = 0.0;      // ADDU: u rows y-2D, y-D
   for (int i0 = 0; i0 < steps; i0 += kPostQueue) {
     Q4 nxt;
 #pragma unroll
@@ -238,7 +243,11 @@ __device__ __forceinline__ void post2s_wave(const Grid& cg, const Grid& f, const
       const T s1c = stream_sweep(xa, xb, xcor, b1, wd1, scale, in1);
       const bool in2 = col_in && y2 >= 1 && y2 <= n - 1;
       const T s2c = stream_sweep(s1a, s1b, s1c, b2, wd2, scale, in2);
-      if (own && y2 >= Y0 && y2 < Yend && in2) xout[y2 * f.px + X] = s2c;
+      if (own && y2 >= Y0 && y2 < Yend && in2) {
+        if (ADDU) u64[y2 * f.px + X] = ua + (double)s2c;
+        else xout[y2 * f.px + X] = s2c;
+      }
+      if (ADDU) { ua = ub; ub = cur.u[q]; }
       xa = xb; xb = xcor;
       b2 = b1; b1 = b0;
       s1a = s1b; s1b = s1c;
@@ -247,18 +256,122 @@ __device__ __forceinline__ void post2s_wave(const Grid& cg, const Grid& f, const
   }
 }
 
-template <typename T>
+template <typename T, bool ADDU>
 __global__ void __launch_bounds__(64 * kStreamWaves)
     k_post2s(Grid cg, Grid f, const T* __restrict__ x, const T* __restrict__ xc, const T* __restrict__ b,
-             T* __restrict__ xout, T wd1, T wd2, T scale, int R, int nchunk) {
+             T* __restrict__ xout, double* __restrict__ u64, T wd1, T wd2, T scale, int R, int nchunk) {
   const int nstrip = (f.n + 1 + kPostStrip - 1) / kPostStrip;
   const int gx = (nstrip + kStreamWaves - 1) / kStreamWaves;
   int sx, cy;
   if (!stream_block(gx * nchunk, gx, sx, cy)) return;
   const int strip = sx * kStreamWaves + (threadIdx.x >> 6);
   if (strip >= nstrip) return;
-  if (!(cy & 1)) post2s_wave<T, true>(cg, f, x, xc, b, xout, wd1, wd2, scale, strip, cy * R, R);
-  else post2s_wave<T, false>(cg, f, x, xc, b, xout, wd1, wd2, scale, strip, cy * R, R);
+  if (!(cy & 1)) post2s_wave<T, true, ADDU>(cg, f, x, xc, b, xout, u64, wd1, wd2, scale, strip, cy * R, R);
+  else post2s_wave<T, false, ADDU>(cg, f, x, xc, b, xout, u64, wd1, wd2, scale, strip, cy * R, R);
+}
+
+// Mixed mode, top level of a float32 cycle: the cycle's right-hand side is
+// r = (float)(b - A u) of the float64 iterate u (the separate residual
+// kernel's operation, same expression), formed here row by row one row ahead
+// of the float32 pipeline and also stored (the post-smoothing kernel reads
+// it); then, from zero, the two sweeps, residual and restriction of
+// pre2s_wave.  One more halo lane and row for the residual's stencil.
+constexpr int kResHalo = kPreHalo + 1;
+constexpr int kResStrip = 64 - 2 * kResHalo;
+
+template <bool UP>
+__device__ __forceinline__ void pre2s_resid_wave(const Grid& f, const Grid& cg, const double* __restrict__ u,
+                                                 const double* __restrict__ b64, float* __restrict__ r32,
+                                                 float* __restrict__ xout, float* __restrict__ bc, float wd1,
+                                                 float wd2, float scale, double scale64, int strip, int Y0,
+                                                 int R) {
+  using T = float;
+  constexpr int D = UP ? 1 : -1;
+  const int lane = threadIdx.x & 63;
+  const int n = f.n;
+  const int X = strip * kResStrip - kResHalo + lane;
+  const bool col_ok = X >= 0 && X <= n;
+  const bool col_in = X >= 1 && X <= n - 1;
+  const bool own = lane >= kResHalo && lane < 64 - kResHalo && col_in;
+  const bool own_c = own && !(X & 1) && X >= 2 && X <= n - 2;
+  const int Xc = X < 0 ? 0 : (X > n ? n : X);
+  const int Yend = min(Y0 + R, n);
+  const int ylo = Y0 - kResHalo, yhi = Yend + kResHalo - 1;
+  const int ystart = UP ? ylo : yhi;
+  const int steps = yhi - ylo + 1;
+  // float64 windows: u rows y-2D, y-D; b64 row y-D.  float32 windows as in
+  // pre2s_wave (from zero), one row behind: the float pipeline's newest row
+  // is yp = y - D, whose right-hand side rf is formed in this step.
+  double ua = 0.0, ub = 0.0, bq = 0.0;
+  T b1 = 0, b2 = 0, b3 = 0, s1a = 0, s1b = 0, s2a = 0, s2b = 0;
+  T ra = 0, rb = 0, raL = 0, raR = 0, rbL = 0, rbR = 0;
+  double qu[kPreQueue], qb[kPreQueue];
+#pragma unroll
+  for (int q = 0; q < kPreQueue; ++q) {
+    qu[q] = stream_raw(u, f, Xc, ystart + D * q);
+    qb[q] = stream_raw(b64, f, Xc, ystart + D * q);
+  }
+  for (int i0 = 0; i0 < steps; i0 += kPreQueue) {
+    double nu[kPreQueue], nb[kPreQueue];
+#pragma unroll
+    for (int q = 0; q < kPreQueue; ++q) {     // past the end: clamped, unused rows
+      const int yn = ystart + D * (i0 + kPreQueue + q);
+      nu[q] = stream_raw(u, f, Xc, yn);
+      nb[q] = stream_raw(b64, f, Xc, yn);
+    }
+#pragma unroll
+    for (int q = 0; q < kPreQueue; ++q) {
+      const int i = i0 + q;
+      const int y = ystart + D * i;
+      const double uc = stream_mask(qu[q], col_ok, y, n);
+      const double bc64 = stream_mask(qb[q], col_ok, y, n);
+      // residual of the float64 iterate at row yp (stencil rows yp - 1, yp + 1)
+      const int yp = y - D;
+      const bool inp = col_in && yp >= 1 && yp <= n - 1;
+      const double sres = (from_left(ub) + from_right(ub)) + (ua + uc);
+      const T b0 = inp ? (T)(bq - scale64 * (4.0 * ub - sres)) : T(0);
+      if (own && yp >= Y0 && yp < Yend && inp) r32[yp * f.px + X] = b0;
+      // float32 pipeline, from zero: sweep 1 at yp-D, sweep 2 at yp-2D,
+      // residual at yp-3D, restriction at yp-4D
+      const int y1 = yp - D, y2 = yp - 2 * D, y3 = yp - 3 * D, yr = yp - 4 * D;
+      const bool in1 = col_in && y1 >= 1 && y1 <= n - 1;
+      const T s1c = in1 ? wd1 * b1 : T(0);
+      const bool in2 = col_in && y2 >= 1 && y2 <= n - 1;
+      const T s2c = stream_sweep(s1a, s1b, s1c, b2, wd2, scale, in2);
+      if (own && y2 >= Y0 && y2 < Yend && in2) xout[y2 * f.px + X] = s2c;
+      const bool in3 = col_in && y3 >= 1 && y3 <= n - 1;
+      const T ssum = (from_left(s2b) + from_right(s2b)) + (s2a + s2c);
+      const T rc = in3 ? b3 - scale * (T(4) * s2b - ssum) : T(0);
+      const T rcL = from_left(rc), rcR = from_right(rc);
+      const T diag = UP ? (rcR + raL) : (raR + rcL);
+      const T h = ((rbR + rbL) + (rc + ra)) + diag;
+      if (own_c && !(yr & 1) && yr >= Y0 && yr < Yend && yr >= 2 && yr <= n - 2)
+        bc[(yr >> 1) * cg.px + (X >> 1)] = rb + T(0.5) * h;
+      // advance the windows
+      ua = ub; ub = uc; bq = bc64;
+      b3 = b2; b2 = b1; b1 = b0;
+      s1a = s1b; s1b = s1c;
+      s2a = s2b; s2b = s2c;
+      ra = rb; raL = rbL; raR = rbR;
+      rb = rc; rbL = rcL; rbR = rcR;
+    }
+#pragma unroll
+    for (int q = 0; q < kPreQueue; ++q) { qu[q] = nu[q]; qb[q] = nb[q]; }
+  }
+}
+
+__global__ void __launch_bounds__(64 * kStreamWaves)
+    k_pre2s_resid(Grid f, Grid cg, const double* __restrict__ u, const double* __restrict__ b64,
+                  float* __restrict__ r32, float* __restrict__ xout, float* __restrict__ bc, float wd1, float wd2,
+                  float scale, double scale64, int R, int nchunk) {
+  const int nstrip = (f.n + 1 + kResStrip - 1) / kResStrip;
+  const int gx = (nstrip + kStreamWaves - 1) / kStreamWaves;
+  int sx, cy;
+  if (!stream_block(gx * nchunk, gx, sx, cy)) return;
+  const int strip = sx * kStreamWaves + (threadIdx.x >> 6);
+  if (strip >= nstrip) return;            // whole wavefront leaves together
+  if (!(cy & 1)) pre2s_resid_wave<true>(f, cg, u, b64, r32, xout, bc, wd1, wd2, scale, scale64, strip, cy * R, R);
+  else pre2s_resid_wave<false>(f, cg, u, b64, r32, xout, bc, wd1, wd2, scale, scale64, strip, cy * R, R);
 }
 
 // Rows per wavefront: an explicit choice, or (0) about 128 row chunks per
