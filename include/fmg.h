@@ -102,7 +102,11 @@ typedef struct {
     double converged_tol;
     int use_graph;      /* 1: capture the solve once into a hipGraph and replay */
     int tail_max_nodes; /* V-cycle levels with at most this many interior nodes
-                           run together in one single-workgroup launch (0: off) */
+                           run together in one launch (0: off): if the top such
+                           level has at most 1024, the cycle from it is applied
+                           as a dense float64 matrix built at creation (one
+                           wavefront per row); otherwise as one single-workgroup
+                           recursive cycle with the levels in LDS              */
     int fuse_small_levels; /* 1: run Algorithm 3.2 on those small levels (all
                               steps, incl. the Newton solves) in one launch */
     int aug_max_blocks; /* workgroups per fine quadrature pass of the augmented
