@@ -90,9 +90,11 @@ typedef struct {
     double omega;       /* Jacobi weight; 0 = 4/5 (2D) or 6/7 (3D)           */
     double cheb_lo, cheb_hi;   /* default 1/3 and 2                          */
     int newton_max;     /* cap on Newton iterations per small solve (30)     */
-    double newton_tol;  /* stop when |d|_inf <= tol max(1,|y|_inf) (1e-14)  */
+    double newton_tol;  /* stop when a Newton direction (applied in full) or
+                           an accepted damped step d has
+                           |d|_inf <= tol max(1,|y|_inf) (1e-14)            */
     int newton_passes;  /* fine quadrature passes per correction step kept in
-                           the launch sequence, the setup pass included (4);
+                           the launch sequence, the setup pass included (3);
                            the last one completes, in one workgroup, any
                            Newton solve that needs more                      */
     int mode;           /* FMG_PAPER: Algorithm 3.2 as stated; FMG_CONVERGED:

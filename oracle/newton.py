@@ -3,13 +3,16 @@
 Every nonlinear problem in the method is the Euler-Lagrange equation of a
 strictly convex energy (monotone f, coercive a; Section 2, Assumption A):
     E(y) = 1/2 y^T K y + sum_j m_j F(z_j(y)) - sum_j m_j g_j z_j(y),
-with z(y) = B y linear.  The paper only says "fixed-point iteration or Newton
-type iteration" (Section 3.3).  The reading used here: Newton steps
+with z(y) = B y linear.  The paper leaves the nonlinear solver open (a
+fixed-point or a Newton-type iteration, Section 3).  The reading used here: Newton steps
 d = -J^{-1} R with backtracking (halving) until the Armijo decrease
 E(y + t d) <= E(y) + 1e-4 t R.d holds; the test allows for rounding in E by
 adding 1e-12 times the sum of the magnitudes of E's three terms.  The
-iteration stops when the accepted update is small (a rule supplied by the
-caller) or when the update stops decreasing (stagnation at rounding level).
+iteration stops as soon as a computed Newton direction is small (a rule
+supplied by the caller; the direction is then applied in full, without
+evaluating the energy there, since such a step changes E only at rounding
+level), when an accepted damped update is small, or when the update stops
+decreasing (stagnation at rounding level).
 """
 from __future__ import annotations
 
@@ -34,6 +37,8 @@ def newton_minimize(y0, grad_hess, energy, solve, converged, max_iter=50,
     for it in range(1, max_iter + 1):
         R, J = grad_hess(y)
         d = -solve(J, R)
+        if np.all(np.isfinite(d)) and converged(d, y):
+            return y + d, it, True
         slope = float(R @ d)
         t = 1.0
         for _ in range(MAX_HALVINGS):

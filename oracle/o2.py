@@ -20,7 +20,8 @@ Readings of what the paper leaves open (shared with the GPU library):
   * The augmented problem is solved by damped Newton in the coordinates
     (w, alpha) of z = Q_k w + alpha u~ (Q_k = P_k ... P_2), started at
     (0, 1), i.e. z = u~ (the good initial guess of the Remark after
-    Theorem 3.3), and stopped when |d|_inf <= tol max(1, |w|_inf, |alpha|).
+    Theorem 3.3), and stopped as soon as a Newton direction (applied in full)
+    or an accepted damped update d satisfies |d|_inf <= tol max(1, |w|_inf, |alpha|).
   * If u~ adds (numerically) nothing to V_H -- the Schur complement of the
     alpha row of the Newton matrix is <= 1e-12 of its diagonal entry -- the
     alpha component of the step is set to zero and the w block solved alone.

@@ -989,7 +989,7 @@ void fmg_default_options(int dim, fmg_options* o) {
   o->cheb_hi = 2.0;
   o->newton_max = 30;
   o->newton_tol = 1e-14;
-  o->newton_passes = 4;
+  o->newton_passes = 3;
   o->mode = FMG_PAPER;
   o->converged_max_steps = 40;
   o->converged_tol = 1e-13;

@@ -287,7 +287,9 @@ __device__ __forceinline__ void coarse_coords(int nH, int A, int& x, int& y, int
 // state machine, one evaluation per call: accept or halve the trial step,
 // test convergence (|t d|_inf <= tol max(1, |y|_inf)), otherwise compute the
 // next direction d = -J^{-1} R (dropping the u~ direction when its Schur
-// complement is <= 1e-12 of J_uu) and the next trial point.  Every entry of
+// complement is <= 1e-12 of J_uu) and the next trial point; a direction with
+// |d|_inf <= tol max(1, |y|_inf) is applied in full and ends the iteration
+// without another evaluation (it changes E only at rounding level).  Every entry of
 // J and R gathers the contributions of the (at most 2^d) coarse cells that
 // touch it, cells in ascending order.
 // LDS scratch `sm` (newton_scratch_doubles): state | A_1 | J | R | A_1 w | col | rdiag | 8.
@@ -417,18 +419,6 @@ __device__ __forceinline__ void newton_core(const AugShape& s, const double* cs,
   }
   done = __builtin_amdgcn_readlane(done, 0);
   ok = __builtin_amdgcn_readlane(ok, 0);
-  if (lane == 0) {
-    ns->done = done;
-    ns->ok = ok;
-    if (done) {
-      const int k = ns->level - 1;
-      rep->newton_iters[k] = iter;
-      rep->newton_total[k] += iter;
-      rep->alpha[k] = ns->y[N1];
-      if (!finite) report_status(rep, FMG_E_NONFINITE);
-      else if (!ok) report_status(rep, FMG_E_NOT_CONVERGED);
-    }
-  }
   if (newdir) {
     // ---- new direction: J d = -R at the accepted point (y == ytry here) ----
     for (int A = lane; A < ny; A += 64) dsave[A] = -R[A];
@@ -448,6 +438,36 @@ __device__ __forceinline__ void newton_core(const AugShape& s, const double* cs,
     }
     sl = wave_allsum(sl);
     if (lane == 0) { ns->slope = sl; ns->t = 1.0; ns->iter = iter + 1; }
+    // a small direction is applied in full without evaluating the energy there
+    double dmax = 0.0, ymax = 0.0;
+    bool dfin = true;
+    for (int A = lane; A < ny; A += 64) {
+      dmax = fmax(dmax, fabs(dsave[A]));
+      ymax = fmax(ymax, fabs(ns->y[A]));
+      dfin = dfin && isfinite(dsave[A]);
+    }
+    dmax = wave_allmax(dmax);
+    ymax = wave_allmax(ymax);
+    dfin = __all(dfin);
+    if (dfin && dmax <= tol * fmax(1.0, ymax)) {
+      done = 1;
+      ok = 1;
+      for (int A = lane; A < ny; A += 64) ns->y[A] = ns->ytry[A];
+    }
+  }
+  wave_sync();
+  if (lane == 0) {
+    const int iter_new = iter + (newdir ? 1 : 0);
+    ns->done = done;
+    ns->ok = ok;
+    if (done) {
+      const int k = ns->level - 1;
+      rep->newton_iters[k] = iter_new;
+      rep->newton_total[k] += iter_new;
+      rep->alpha[k] = ns->y[N1];
+      if (!finite) report_status(rep, FMG_E_NONFINITE);
+      else if (!ok) report_status(rep, FMG_E_NOT_CONVERGED);
+    }
   }
   wave_sync();
   wave_copy(nsg, ns);
@@ -895,24 +915,38 @@ __device__ __forceinline__ void level1_newton_dev(const Grid& g1, int N1, const 
     chol_solve_wave(J, rdiag, N1, N1, D);
     __syncthreads();
     if (threadIdx.x == 0) {
+      // a small direction is applied in full without evaluating the energy there
+      double dmax = 0.0, umax0 = 0.0;
+      bool dfin = true;
+      for (int a = 0; a < N1; ++a) {
+        dmax = fmax(dmax, fabs(D[a]));
+        umax0 = fmax(umax0, fabs(U[a]));
+        dfin = dfin && isfinite(D[a]);
+      }
+      const bool small = dfin && dmax <= tol * fmax(1.0, umax0);
       double slope = 0.0;
       for (int a = 0; a < N1; ++a) slope += R[a] * D[a];
       double t = 1.0, E = sc[0], S = sc[1], Et = 0.0, St = 0.0;
-      for (int h = 0; h < kMaxHalvings; ++h) {
-        for (int a = 0; a < N1; ++a) T[a] = U[a] + t * D[a];
-        energy(T, Et, St);
-        if (Et <= E + kArmijo * t * slope + kEnergyRounding * fmax(S, St)) break;
-        t *= 0.5;
+      if (small) {
+        for (int a = 0; a < N1; ++a) U[a] += D[a];
+        sc[2] = 1.0;
+      } else {
+        for (int h = 0; h < kMaxHalvings; ++h) {
+          for (int a = 0; a < N1; ++a) T[a] = U[a] + t * D[a];
+          energy(T, Et, St);
+          if (Et <= E + kArmijo * t * slope + kEnergyRounding * fmax(S, St)) break;
+          t *= 0.5;
+        }
+        double stepmax = 0.0, umax = 0.0;
+        for (int a = 0; a < N1; ++a) {
+          stepmax = fmax(stepmax, fabs(T[a] - U[a]));
+          U[a] = T[a];
+          umax = fmax(umax, fabs(U[a]));
+        }
+        sc[0] = Et; sc[1] = St;
+        sc[2] = (stepmax <= tol * fmax(1.0, umax)) ? 1.0 : 0.0;
+        if (!isfinite(Et)) sc[2] = 2.0;
       }
-      double stepmax = 0.0, umax = 0.0;
-      for (int a = 0; a < N1; ++a) {
-        stepmax = fmax(stepmax, fabs(T[a] - U[a]));
-        U[a] = T[a];
-        umax = fmax(umax, fabs(U[a]));
-      }
-      sc[0] = Et; sc[1] = St;
-      sc[2] = (stepmax <= tol * fmax(1.0, umax)) ? 1.0 : 0.0;
-      if (!isfinite(Et)) sc[2] = 2.0;
     }
     __syncthreads();
     if (sc[2] != 0.0) { ok = sc[2] == 1.0; break; }

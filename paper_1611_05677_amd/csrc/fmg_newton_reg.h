@@ -233,7 +233,17 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
     slope = wave_allsum(Rl * dv);
     tnew = 1.0;
     ytry_new = ynew + dv;
+    // a small direction is applied in full without evaluating the energy there
+    const bool dfin = __all(isfinite(dv));
+    const double dmax = wave_allmax(act ? fabs(dv) : 0.0);
+    const double ymax = wave_allmax(act ? fabs(ynew) : 0.0);
+    if (dfin && dmax <= tol * fmax(1.0, ymax)) {
+      ynew = ytry_new;
+      done = 1;
+      ok = 1;
+    }
   }
+  const int iter_new = iter + (newdir ? 1 : 0);
   // ---- write back ----
   if (act) {
     nsg->y[lane] = ynew;
@@ -247,13 +257,13 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
     nsg->slope = slope;
     nsg->halvings = halvings;
     nsg->passes = passes + 1;
-    nsg->iter = iter + (newdir ? 1 : 0);
+    nsg->iter = iter_new;
     nsg->done = done;
     nsg->ok = ok;
     if (done) {
       const int k = nsg->level - 1;
-      rep->newton_iters[k] = iter;
-      rep->newton_total[k] += iter;
+      rep->newton_iters[k] = iter_new;
+      rep->newton_total[k] += iter_new;
       rep->alpha[k] = alpha_new;
       if (!finite) report_status(rep, FMG_E_NONFINITE);
       else if (!ok) report_status(rep, FMG_E_NOT_CONVERGED);
@@ -306,6 +316,16 @@ __device__ __forceinline__ void level1_newton_reg(const Grid& g1, double m1, con
     chol_reg<N1>(jr, myrd);
     if (lane == N1 - 1) { myrd = fast_rsqrt(jr[N1 - 1]); jr[N1 - 1] = jr[N1 - 1] * myrd; }
     const double D = chol_solve_reg<N1>(jr, myrd, N1, node ? -R : 0.0, sm);
+    {   // a small direction is applied in full without evaluating the energy there
+      const bool dfin = __all(isfinite(D));
+      const double dmax = wave_allmax(node ? fabs(D) : 0.0);
+      const double umax0 = wave_allmax(node ? fabs(U) : 0.0);
+      if (dfin && dmax <= tol * fmax(1.0, umax0)) {
+        U = U + D;
+        status = 1;
+        break;
+      }
+    }
     const double slope = wave_allsum(R * D);
     double t = 1.0, Et = 0.0, St = 0.0, T = U;
     for (int h = 0; h < kMaxHalvings; ++h) {
