@@ -60,7 +60,6 @@ struct Plan {
   size_t off_uprev;
   size_t off_fmgtail;
   size_t off_ticket;
-  size_t off_cellsum;
   size_t norm_blocks;
   size_t total;
 };
@@ -178,8 +177,7 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p) {
   }
   p.off_uprev = ro.o.mode == FMG_CONVERGED ? take(sizeof(double) * F.count) : 0;
   p.off_fmgtail = take(sizeof(FmgTailParams));
-  p.off_ticket = take(sizeof(unsigned) * (1 + ncell));
-  p.off_cellsum = take(sizeof(double) * ncell * (Acc<3>::NQ + Acc<3>::NS));
+  p.off_ticket = take(sizeof(unsigned));
   p.total = off;
   return FMG_OK;
 }
@@ -564,7 +562,6 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   double* pq = h->at<double>(p.off_pq);
   double* ps = h->at<double>(p.off_ps);
   unsigned* ticket = h->at<unsigned>(p.off_ticket);
-  double* cellsum = h->at<double>(p.off_cellsum);
   const double* A1 = h->at<double>(p.off_A1);
   if (N <= o.aug_small_nodes) {
     // the whole augmented solve (and the update unless deferred) by one workgroup
@@ -580,24 +577,24 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   if (npass == 1 && kFinishInPass)
     FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
                (k_aug_pass<DIM, KIND, true, true><<<L.aug_blocks, kBlock, lds, st>>>(
-                   L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, cellsum,
-                   ticket, k, o.newton_max, o.newton_tol)));
+                   L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, ticket, k,
+                   o.newton_max, o.newton_tol)));
   else
     FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
                (k_aug_pass<DIM, KIND, true, false><<<L.aug_blocks, kBlock, lds, st>>>(
-                   L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, cellsum,
-                   ticket, k, o.newton_max, o.newton_tol)));
+                   L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, ticket, k,
+                   o.newton_max, o.newton_tol)));
   for (int pass = 1; pass < npass; ++pass) {
     if (pass == npass - 1 && kFinishInPass)
       FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
                  (k_aug_pass<DIM, KIND, false, true><<<L.aug_blocks, kBlock, lds, st>>>(
                      L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps,
-                     cellsum, ticket, k, o.newton_max, o.newton_tol)));
+                     ticket, k, o.newton_max, o.newton_tol)));
     else
       FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
                  (k_aug_pass<DIM, KIND, false, false><<<L.aug_blocks, kBlock, lds, st>>>(
                      L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps,
-                     cellsum, ticket, k, o.newton_max, o.newton_tol)));
+                     ticket, k, o.newton_max, o.newton_tol)));
   }
   if (!kFinishInPass)
     FMG_LAUNCH(h, st, KC_NEWTON_FINISH, k, N, 0.0,
@@ -1060,7 +1057,7 @@ int fmg_create_hierarchy(const fmg_mesh_desc* mesh, const fmg_options* opts, voi
     }
   }
   if (p.off_uprev) k_fill<double><<<1024, 256, 0, s>>>(h->at<double>(p.off_uprev), p.lev[p.nlev].count, 0.0);
-  k_fill<unsigned><<<1, 64, 0, s>>>(h->at<unsigned>(p.off_ticket), 1 + (p.dim == 2 ? p.nH * p.nH : p.nH * p.nH * p.nH), 0u);
+  k_fill<unsigned><<<1, 64, 0, s>>>(h->at<unsigned>(p.off_ticket), 1, 0u);
   if (p.tail_top >= 2 && ro.o.fuse_small_levels) {
     // parameters of the single-workgroup FMG launch over levels 1..T (canonical roles)
     FmgTailParams P;

@@ -571,10 +571,10 @@ __device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShap
 // One pass of the augmented Newton iteration in one launch.  Every block
 // accumulates its share of the fine quadrature sums at ns->ytry (SETUP: the
 // setup sums plus the sums at y0 = (0,..,0,1), i.e. z = u~) and writes them
-// as per-block partials.  The last block of each coarse cell (atomic ticket,
-// release/acquire at device scope) reduces that cell's partials in a fixed
-// order into the cell sums; the last cell to finish performs the Newton step.
-// tickets: [0] global, [1 + cell] per cell; all zero between launches.
+// as per-block partials.  The last block to finish (atomic ticket,
+// release/acquire at device scope) reduces all partials, cell by cell in a
+// fixed block order, into the cell sums and performs the Newton step.
+// tickets[0]: zero between launches.
 // LDS: newton_kernel_lds_doubles(ncell, NQ, N1, blockDim).
 template <int DIM, int KIND, bool SETUP, bool FINISH>
 __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
@@ -582,14 +582,16 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
                                                      double scale, double m, const double* __restrict__ A1,
                                                      NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
                                                      double* __restrict__ pq, double* __restrict__ ps,
-                                                     double* __restrict__ cellsum, unsigned* __restrict__ tickets,
-                                                     int level, int newton_max, double tol) {
+                                                     unsigned* __restrict__ tickets, int level, int newton_max,
+                                                     double tol) {
   using AC = Acc<DIM>;
-  constexpr int W = AC::NQ + (SETUP ? AC::NS : 0);
   extern __shared__ double smem[];
   __shared__ int is_last;
   __shared__ double y0[kMaxY];
-  if (!SETUP && ns->done) return;
+  // the state loads are issued together; a solve already done skips the pass
+  const int done_in = SETUP ? 0 : ns->done;
+  const double param = slot->param;
+  if (!SETUP && done_in) return;
   const int bpc = 1 << s.bpc_log;
   const int cell = blockIdx.x >> s.bpc_log, chunk = blockIdx.x & (bpc - 1);
   const int t0 = chunk << s.npb_log, t1 = t0 + (1 << s.npb_log);
@@ -609,71 +611,27 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
     double acc[AC::NQ];
 #pragma unroll
     for (int q = 0; q < AC::NQ; ++q) acc[q] = 0.0;
-    quad_accumulate<DIM, KIND>(g, s, ut, ytry, slot->param, cell, t0, t1, threadIdx.x, blockDim.x, acc);
+    quad_accumulate<DIM, KIND>(g, s, ut, ytry, param, cell, t0, t1, threadIdx.x, blockDim.x, acc);
     const double tot = block_sum_many<AC::NQ>(acc, smem);
     if (threadIdx.x < AC::NQ) pq[(size_t)blockIdx.x * AC::NQ + threadIdx.x] = tot;
   }
-  // ---- level 1: the last block of this cell reduces the cell's partials ----
+  // ---- the last block reduces every cell's partials and takes the Newton step ----
   __syncthreads();
-  if (bpc > 1) {
-    if (threadIdx.x == 0)
-      is_last = __hip_atomic_fetch_add(&tickets[1 + cell], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
-                (unsigned)(bpc - 1);
-    __syncthreads();
-    if (!is_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  {
-    const int S = max(1, min(bpc, (int)blockDim.x / W));
-    const int seg = (bpc + S - 1) / S;
-    double* tmp = smem;   // W * S <= blockDim doubles
-    for (int idx = threadIdx.x; idx < W * S; idx += blockDim.x) {
-      const int item = idx % W, sg = idx / W;
-      const bool quad = item < AC::NQ;
-      const int q = quad ? item : item - AC::NQ, n = quad ? AC::NQ : AC::NS;
-      const double* p = (quad ? pq : ps) + ((size_t)cell * bpc) * n + q;
-      const int b0 = sg * seg, b1 = min(bpc, b0 + seg);
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int b = b0;
-      for (; b + 3 < b1; b += 4) {
-        a0 += p[(size_t)b * n];
-        a1 += p[(size_t)(b + 1) * n];
-        a2 += p[(size_t)(b + 2) * n];
-        a3 += p[(size_t)(b + 3) * n];
-      }
-      for (; b < b1; ++b) a0 += p[(size_t)b * n];
-      tmp[sg * W + item] = (a0 + a1) + (a2 + a3);
-    }
-    __syncthreads();
-    for (int item = threadIdx.x; item < W; item += blockDim.x) {
-      double t = 0.0;
-      for (int sg = 0; sg < S; ++sg) t += tmp[sg * W + item];
-      cellsum[(size_t)cell * (AC::NQ + AC::NS) + item] = t;
-    }
-  }
-  // ---- level 2: the last cell performs the Newton step ----
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (bpc > 1) __hip_atomic_store(&tickets[1 + cell], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0)
     is_last = __hip_atomic_fetch_add(&tickets[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
-              (unsigned)(DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH) - 1u;
-  }
+              gridDim.x - 1u;
   __syncthreads();
   if (!is_last) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
   double* cs = smem;
   double* sm = cs + ncell * AC::NQ;
+  double* tmp = sm + newton_scratch_doubles(s.N1);
   if (SETUP) {
-    for (int idx = threadIdx.x; idx < ncell * AC::NS; idx += blockDim.x)
-      cs[idx] = cellsum[(size_t)(idx / AC::NS) * (AC::NQ + AC::NS) + AC::NQ + idx % AC::NS];
     if (threadIdx.x == 0) newton_state_reset(ns, s.N1, level);
-    __syncthreads();
-    setup_scatter<DIM>(s, cs, m, ns);
+    setup_reduce<DIM>(s, ps, m, ns, cs, tmp);
   }
-  for (int idx = threadIdx.x; idx < ncell * AC::NQ; idx += blockDim.x)
-    cs[idx] = cellsum[(size_t)(idx / AC::NQ) * (AC::NQ + AC::NS) + idx % AC::NQ];
-  __syncthreads();
+  cell_sums_from_partials<AC::NQ>(pq, ncell, bpc, cs, tmp);
   newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   if (FINISH) {
     // last pass of the launch sequence: this block completes the Newton solve
@@ -681,7 +639,7 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
     while (true) {
       __syncthreads();
       if (ns->done) break;
-      quad_cells_by_waves<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cs);
+      quad_cells_by_waves<DIM, KIND>(g, s, ut, ns->ytry, param, cs);
       newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
     }
   }
