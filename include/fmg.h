@@ -111,8 +111,10 @@ typedef struct {
                            recursive cycle with the levels in LDS              */
     int fuse_small_levels; /* 1: run Algorithm 3.2 on those small levels (all
                               steps, incl. the Newton solves) in one launch */
-    int aug_max_blocks; /* workgroups per fine quadrature pass of the augmented
-                           problem (upper bound; 64..16384)                  */
+    int aug_max_blocks; /* size of a fine quadrature pass of the augmented
+                           problem, in 256-thread workgroups (upper bound;
+                           64..16384; 512); large 2D levels run 1024-thread
+                           workgroups, a quarter as many                    */
     int aug_small_nodes; /* levels with at most this many interior nodes solve
                             the augmented problem in one single-workgroup
                             launch (0: never; default 4096 in 2D, 0 in 3D)   */

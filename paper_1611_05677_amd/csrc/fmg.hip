@@ -45,6 +45,7 @@ struct LevelInfo {
   double m;                // lumped mass h^d
   AugShape aug;            // augmented-pass tiling (levels >= 2)
   int aug_blocks;
+  int aug_threads;          // threads per block of the augmented passes
 };
 
 struct Plan {
@@ -131,8 +132,12 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p) {
     L.m = d == 2 ? h * h : h * h * h;
     if (k >= 2) {
       const int nodes_log = d * (k - 1);
-      const int cap_log = ilog2(std::max(1, ro.o.aug_max_blocks / ncell));
-      const int bpc_log = std::max(0, std::min(nodes_log - 8, cap_log));
+      // large 2D levels: 1024-thread blocks, a quarter as many
+      const bool wide = d == 2 && nodes_log >= kAugWideNodesLog;
+      const int tlog = wide ? 10 : 8;
+      const int cap_log = ilog2(std::max(1, (ro.o.aug_max_blocks >> (tlog - 8)) / ncell));
+      const int bpc_log = std::max(0, std::min(nodes_log - tlog, cap_log));
+      L.aug_threads = 1 << tlog;
       L.aug.nH = p.nH;
       L.aug.log2r = k - 1;
       L.aug.bpc_log = bpc_log;
@@ -481,7 +486,7 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
 inline size_t aug_pass_lds_bytes(const Plan& p) {
   const int ncell = p.dim == 2 ? p.nH * p.nH : p.nH * p.nH * p.nH;
   const int NQ = p.dim == 2 ? Acc<2>::NQ : Acc<3>::NQ;
-  return sizeof(double) * (size_t)newton_kernel_lds_doubles(ncell, NQ, p.N1, kBlock);
+  return sizeof(double) * (size_t)newton_kernel_lds_doubles(ncell, NQ, p.N1, kAugMaxThreads);
 }
 
 inline size_t fmg_tail_lds_bytes(const Plan& p) {
@@ -576,23 +581,23 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   constexpr bool kFinishInPass = DIM == 2;
   if (npass == 1 && kFinishInPass)
     FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
-               (k_aug_pass<DIM, KIND, true, true><<<L.aug_blocks, kBlock, lds, st>>>(
+               (k_aug_pass<DIM, KIND, true, true><<<L.aug_blocks, L.aug_threads, lds, st>>>(
                    L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, ticket, k,
                    o.newton_max, o.newton_tol)));
   else
     FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
-               (k_aug_pass<DIM, KIND, true, false><<<L.aug_blocks, kBlock, lds, st>>>(
+               (k_aug_pass<DIM, KIND, true, false><<<L.aug_blocks, L.aug_threads, lds, st>>>(
                    L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, ticket, k,
                    o.newton_max, o.newton_tol)));
   for (int pass = 1; pass < npass; ++pass) {
     if (pass == npass - 1 && kFinishInPass)
       FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
-                 (k_aug_pass<DIM, KIND, false, true><<<L.aug_blocks, kBlock, lds, st>>>(
+                 (k_aug_pass<DIM, KIND, false, true><<<L.aug_blocks, L.aug_threads, lds, st>>>(
                      L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps,
                      ticket, k, o.newton_max, o.newton_tol)));
     else
       FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
-                 (k_aug_pass<DIM, KIND, false, false><<<L.aug_blocks, kBlock, lds, st>>>(
+                 (k_aug_pass<DIM, KIND, false, false><<<L.aug_blocks, L.aug_threads, lds, st>>>(
                      L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps,
                      ticket, k, o.newton_max, o.newton_tol)));
   }

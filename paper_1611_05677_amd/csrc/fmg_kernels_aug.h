@@ -74,18 +74,47 @@ __device__ __forceinline__ void cell_of(int cell, int nH, int& cx, int& cy, int&
 }
 
 // Visit the fine nodes of one block's share of a coarse cell:
-// fn(grid index c, local coordinates t[DIM], i, j, l).
+// fn(grid index c, local coordinates t[DIM], i, j, l, u[c]).  The values
+// u[c] are loaded kNodePrefetch visits ahead (from clamped, in-bounds
+// addresses), so each wave keeps several loads in flight instead of waiting
+// for one per node.  All threads of a block make the same number of visits
+// unless the block's share is smaller than its thread count.
+constexpr int kNodePrefetch = 4;
+
 template <int DIM, typename Fn>
 __device__ __forceinline__ void for_cell_nodes(const Grid& g, const AugShape& s, int cx, int cy, int cz,
-                                               int t0, int t1, int tid, int nthreads, Fn&& fn) {
+                                               int t0, int t1, int tid, int nthreads,
+                                               const double* __restrict__ u, Fn&& fn) {
   const int r = 1 << s.log2r, mask = r - 1;
   const double inv_r = 1.0 / r;
-  for (int t = t0 + tid; t < t1; t += nthreads) {
+  auto index_of = [&](int t, int& i, int& j, int& l) {
     const int lx = t & mask, ly = (t >> s.log2r) & mask, lz = DIM == 3 ? t >> (2 * s.log2r) : 0;
-    const int i = cx * r + lx, j = cy * r + ly, l = cz * r + lz;
-    if (i == 0 || j == 0 || (DIM == 3 && l == 0)) continue;   // Dirichlet nodes
-    double tl[3] = {lx * inv_r, ly * inv_r, lz * inv_r};
-    fn(gidx<DIM>(g, i, j, l), tl, i, j, l);
+    i = cx * r + lx; j = cy * r + ly; l = cz * r + lz;
+    return gidx<DIM>(g, i, j, l);
+  };
+  auto load = [&](int t) {
+    int i, j, l;
+    return u[index_of(t < t1 ? t : t1 - 1, i, j, l)];
+  };
+  double q[kNodePrefetch];
+#pragma unroll
+  for (int p = 0; p < kNodePrefetch; ++p) q[p] = load(t0 + tid + p * nthreads);
+  for (int tb = t0 + tid; tb < t1; tb += kNodePrefetch * nthreads) {
+#pragma unroll
+    for (int p = 0; p < kNodePrefetch; ++p) {
+      const int t = tb + p * nthreads;
+      const double uc = q[p];
+      q[p] = load(t + kNodePrefetch * nthreads);
+      if (t < t1) {
+        int i, j, l;
+        const int c = index_of(t, i, j, l);
+        if (i != 0 && j != 0 && (DIM == 2 || l != 0)) {   // skip the Dirichlet nodes
+          const int lx = i - cx * r, ly = j - cy * r, lz = DIM == 3 ? l - cz * r : 0;
+          double tl[3] = {lx * inv_r, ly * inv_r, lz * inv_r};
+          fn(c, tl, i, j, l, uc);
+        }
+      }
+    }
   }
 }
 
@@ -108,26 +137,71 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Grid g, const ProblemSlot* __res
 
 // Per-cell setup sums for one block's node range:
 //   sum phi_a (A u~)_j, sum u~_j (A u~)_j, sum phi_a g_j, sum u~_j g_j.
+// Setup sums of one fine node (Alg. 3.1 step 2: the linear terms of the
+// augmented problem): (A u~) phi_a, (A u~) u~, g phi_a, g u~.
+template <int DIM>
+__device__ __forceinline__ void setup_node(const double* phi, double u, double au, double gv, double* acc) {
+  using AC = Acc<DIM>;
+#pragma unroll
+  for (int a = 0; a < AC::NV; ++a) {
+    acc[AC::S_BH + a] += phi[a] * au;
+    acc[AC::S_GH + a] += phi[a] * gv;
+  }
+  acc[AC::S_C] += u * au;
+  acc[AC::S_GU] += u * gv;
+}
+
+// Quadrature sums of one fine node at z (the nonlinear terms and their
+// derivatives): f phi_a, f' phi_a u~, f' phi_a phi_b, f u~, f' u~^2, F.
+template <int DIM, int KIND>
+__device__ __forceinline__ void quad_node(const double* phi, double z, double u, double param, double* acc) {
+  using AC = Acc<DIM>;
+  using PR = Pairs<DIM>;
+  double f, df, F;
+  NL<KIND>::all(z, param, f, df, F);
+  double dphi[AC::NV];
+#pragma unroll
+  for (int a = 0; a < AC::NV; ++a) {
+    acc[AC::Q_NH + a] += f * phi[a];
+    dphi[a] = df * phi[a];
+    acc[AC::Q_KHU + a] += dphi[a] * u;
+  }
+#pragma unroll
+  for (int p = 0; p < PR::N; ++p) acc[AC::Q_K + p] += dphi[PR::a(p)] * phi[PR::b(p)];
+  acc[AC::Q_NU] += f * u;
+  acc[AC::Q_KUU] += df * u * u;
+  acc[AC::Q_E] += F;
+}
+
 template <int DIM>
 __device__ __forceinline__ void setup_accumulate(const Grid& g, const AugShape& s, const double* __restrict__ ut,
                                                  const double* __restrict__ gl, int nf1, int fs, double scale,
                                                  int cell, int t0, int t1, int tid, int nthreads, double* acc) {
-  using AC = Acc<DIM>;
   int cx, cy, cz;
   cell_of<DIM>(cell, s.nH, cx, cy, cz);
-  for_cell_nodes<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, [&](int c, const double* tl, int i, int j, int l) {
-    double phi[AC::NV];
+  for_cell_nodes<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, ut,
+                      [&](int c, const double* tl, int i, int j, int l, double u) {
+    double phi[Acc<DIM>::NV];
     kuhn_phi<DIM>(tl, phi);
-    const double u = ut[c];
-    const double au = apply_A_at<DIM>(ut, c, g, scale);
-    const double gv = gl[fine_load_index(nf1, fs, i, j, l)];
-#pragma unroll
-    for (int a = 0; a < AC::NV; ++a) {
-      acc[AC::S_BH + a] += phi[a] * au;
-      acc[AC::S_GH + a] += phi[a] * gv;
-    }
-    acc[AC::S_C] += u * au;
-    acc[AC::S_GU] += u * gv;
+    setup_node<DIM>(phi, u, apply_A_at<DIM>(ut, c, g, scale), gl[fine_load_index(nf1, fs, i, j, l)], acc);
+  });
+}
+
+// Setup sums and the quadrature sums at the Newton start y0 = (0, .., 0, 1)
+// (z = u~) in one visit of the nodes.
+template <int DIM, int KIND>
+__device__ __forceinline__ void setup_quad_accumulate(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                                      const double* __restrict__ gl, int nf1, int fs, double scale,
+                                                      double param, int cell, int t0, int t1, int tid,
+                                                      int nthreads, double* acc_s, double* acc_q) {
+  int cx, cy, cz;
+  cell_of<DIM>(cell, s.nH, cx, cy, cz);
+  for_cell_nodes<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, ut,
+                      [&](int c, const double* tl, int i, int j, int l, double u) {
+    double phi[Acc<DIM>::NV];
+    kuhn_phi<DIM>(tl, phi);
+    setup_node<DIM>(phi, u, apply_A_at<DIM>(ut, c, g, scale), gl[fine_load_index(nf1, fs, i, j, l)], acc_s);
+    quad_node<DIM, KIND>(phi, u, u, param, acc_q);
   });
 }
 
@@ -147,7 +221,6 @@ __device__ __forceinline__ void quad_accumulate(const Grid& g, const AugShape& s
                                                 const double* ytry, double param, int cell, int t0, int t1,
                                                 int tid, int nthreads, double* acc) {
   using AC = Acc<DIM>;
-  using PR = Pairs<DIM>;
   int cx, cy, cz;
   cell_of<DIM>(cell, s.nH, cx, cy, cz);
   double wv[AC::NV];
@@ -157,27 +230,14 @@ __device__ __forceinline__ void quad_accumulate(const Grid& g, const AugShape& s
     wv[a] = gi >= 0 ? ytry[gi] : 0.0;
   }
   const double alpha = ytry[s.N1];
-  for_cell_nodes<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, [&](int c, const double* tl, int, int, int) {
+  for_cell_nodes<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, ut,
+                      [&](int, const double* tl, int, int, int, double u) {
     double phi[AC::NV];
     kuhn_phi<DIM>(tl, phi);
-    const double u = ut[c];
     double z = alpha * u;
 #pragma unroll
     for (int a = 0; a < AC::NV; ++a) z += wv[a] * phi[a];
-    double f, df, F;
-    NL<KIND>::all(z, param, f, df, F);
-    double dphi[AC::NV];
-#pragma unroll
-    for (int a = 0; a < AC::NV; ++a) {
-      acc[AC::Q_NH + a] += f * phi[a];
-      dphi[a] = df * phi[a];
-      acc[AC::Q_KHU + a] += dphi[a] * u;
-    }
-#pragma unroll
-    for (int p = 0; p < PR::N; ++p) acc[AC::Q_K + p] += dphi[PR::a(p)] * phi[PR::b(p)];
-    acc[AC::Q_NU] += f * u;
-    acc[AC::Q_KUU] += df * u * u;
-    acc[AC::Q_E] += F;
+    quad_node<DIM, KIND>(phi, z, u, param, acc);
   });
 }
 
@@ -554,6 +614,16 @@ __device__ __forceinline__ void setup_reduce(const AugShape& s, const double* __
   setup_scatter<DIM>(s, cs, m, ns);
 }
 
+// Threads per block of the fine quadrature passes: 256, or 1024 on the 2D
+// levels with at least 2^kAugWideNodesLog fine nodes per coarse cell (a
+// quarter as many blocks, so a quarter as many release/ticket operations and
+// partials for the last block to reduce).  The kernel is compiled for the
+// larger size; the 3D quadrature needs more registers and keeps 256.
+constexpr int kAugMaxThreads = 1024;
+constexpr int kAugWideNodesLog = 14;
+template <int DIM>
+__host__ __device__ constexpr int aug_threads() { return DIM == 2 ? kAugMaxThreads : 256; }
+
 // LDS doubles of k_newton_step / k_newton_finish for a block of `threads`.
 __host__ __device__ constexpr int newton_kernel_lds_doubles(int ncell, int NQ, int N1, int threads) {
   return ncell * NQ + newton_scratch_doubles(N1) + threads;
@@ -577,7 +647,7 @@ __device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShap
 // tickets[0]: zero between launches.
 // LDS: newton_kernel_lds_doubles(ncell, NQ, N1, blockDim).
 template <int DIM, int KIND, bool SETUP, bool FINISH>
-__global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
+__global__ void __launch_bounds__(aug_threads<DIM>()) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
                                                      const ProblemSlot* __restrict__ slot, int nf1, int fs,
                                                      double scale, double m, const double* __restrict__ A1,
                                                      NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
@@ -587,7 +657,6 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
   using AC = Acc<DIM>;
   extern __shared__ double smem[];
   __shared__ int is_last;
-  __shared__ double y0[kMaxY];
   // the state loads are issued together; a solve already done skips the pass
   const int done_in = SETUP ? 0 : ns->done;
   const double param = slot->param;
@@ -595,23 +664,21 @@ __global__ void __launch_bounds__(kBlock) k_aug_pass(Grid g, AugShape s, const d
   const int bpc = 1 << s.bpc_log;
   const int cell = blockIdx.x >> s.bpc_log, chunk = blockIdx.x & (bpc - 1);
   const int t0 = chunk << s.npb_log, t1 = t0 + (1 << s.npb_log);
-  const double* ytry = ns->ytry;
   if (SETUP) {
-    for (int a = threadIdx.x; a <= s.N1; a += blockDim.x) y0[a] = a == s.N1 ? 1.0 : 0.0;
-    __syncthreads();
-    ytry = y0;
-    double acc[AC::NS];
+    // setup sums and the sums at y0 = (0, .., 0, 1) in one visit of the nodes
+    double acc[AC::NS + AC::NQ];
 #pragma unroll
-    for (int q = 0; q < AC::NS; ++q) acc[q] = 0.0;
-    setup_accumulate<DIM>(g, s, ut, slot->g, nf1, fs, scale, cell, t0, t1, threadIdx.x, blockDim.x, acc);
-    const double tot = block_sum_many<AC::NS>(acc, smem);
+    for (int q = 0; q < AC::NS + AC::NQ; ++q) acc[q] = 0.0;
+    setup_quad_accumulate<DIM, KIND>(g, s, ut, slot->g, nf1, fs, scale, param, cell, t0, t1, threadIdx.x,
+                                     blockDim.x, acc, acc + AC::NS);
+    const double tot = block_sum_many<AC::NS + AC::NQ>(acc, smem);
     if (threadIdx.x < AC::NS) ps[(size_t)blockIdx.x * AC::NS + threadIdx.x] = tot;
-  }
-  {
+    else if (threadIdx.x < AC::NS + AC::NQ) pq[(size_t)blockIdx.x * AC::NQ + threadIdx.x - AC::NS] = tot;
+  } else {
     double acc[AC::NQ];
 #pragma unroll
     for (int q = 0; q < AC::NQ; ++q) acc[q] = 0.0;
-    quad_accumulate<DIM, KIND>(g, s, ut, ytry, param, cell, t0, t1, threadIdx.x, blockDim.x, acc);
+    quad_accumulate<DIM, KIND>(g, s, ut, ns->ytry, param, cell, t0, t1, threadIdx.x, blockDim.x, acc);
     const double tot = block_sum_many<AC::NQ>(acc, smem);
     if (threadIdx.x < AC::NQ) pq[(size_t)blockIdx.x * AC::NQ + threadIdx.x] = tot;
   }
