@@ -167,6 +167,27 @@ __device__ __forceinline__ double wave_sum(double v) {
   return lane_value(v, 63);
 }
 
+// N independent sums over the 64 lanes, each returned to every lane; every
+// stage of the DPP tree is applied to all N values before the next, so the
+// N reductions overlap (same additions, in the same order, as wave_sum).
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0xb1>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x4e>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x124>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x128>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x142, 0xa>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x143, 0xc>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = lane_value(v[i], 63);
+}
+
 // Sum over aligned segments of LPC lanes (LPC = 4, 8, 16, 32 or 64); the
 // last lane of each segment receives its segment's total (LPC <= 16: every
 // lane of the segment does).
@@ -202,6 +223,25 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
   v = fmax(v, dpp_move<0x142, 0xa>(v));
   v = fmax(v, dpp_move<0x143, 0xc>(v));
   return lane_value(v, 63);
+}
+
+// N independent maxima over the 64 lanes (inputs >= 0), as wave_sum_n.
+template <int N>
+__device__ __forceinline__ void wave_max_n(double (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = fmax(v[i], dpp_move<0xb1>(v[i]));
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = fmax(v[i], dpp_move<0x4e>(v[i]));
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = fmax(v[i], dpp_move<0x124>(v[i]));
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = fmax(v[i], dpp_move<0x128>(v[i]));
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = fmax(v[i], dpp_move<0x142, 0xa>(v[i]));
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = fmax(v[i], dpp_move<0x143, 0xc>(v[i]));
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = lane_value(v[i], 63);
 }
 
 // Sum NACC per-thread accumulators over the block; thread t < NACC receives

@@ -27,33 +27,36 @@ __device__ __forceinline__ double stencil_shfl(double v, int A, int ax, int ay, 
 }
 
 // Cholesky of the NY x NY matrix whose row `lane` is jr[] (lower part used),
-// steps k = 0..NY-2; returns through jr the factor rows and through myrd the
-// reciprocal of the lane's pivot.  The Schur complement of the last row is
-// left in lane NY-1's jr[NY-1] (not square-rooted).
+// steps k = 0..NY-2, with the forward substitution L y = b carried along: v
+// holds b_lane on entry; on exit lanes 0..NY-2 hold y_lane and lane NY-1 holds
+// b minus the contributions of y_0..y_{NY-2} (not yet divided by its pivot).
+// jr returns the factor rows and myrd the reciprocal of the lane's pivot; the
+// Schur complement of the last row is left in lane NY-1's jr[NY-1] (not
+// square-rooted).  Entries above the diagonal are updated too (it keeps the
+// updates free of lane masks) and are never read.
 template <int NY>
-__device__ __forceinline__ void chol_reg(double (&jr)[NY], double& myrd) {
+__device__ __forceinline__ void chol_fwd_reg(double (&jr)[NY], double& myrd, double& v) {
   const int lane = threadIdx.x;
 #pragma unroll
   for (int k = 0; k < NY - 1; ++k) {
     const double dkk = lane_value(jr[k], k);
     const double rk = fast_rsqrt(dkk);
-    const double sk = dkk * rk;
     const double lik = lane > k ? jr[k] * rk : 0.0;
-    if (lane == k) { jr[k] = sk; myrd = rk; }
-    if (lane > k) jr[k] = lik;
+    const double yk = lane_value(v, k) * rk;
+    if (lane == k) { jr[k] = dkk * rk; myrd = rk; }
+    else if (lane > k) jr[k] = lik;
+    v = lane == k ? yk : v - lik * yk;
 #pragma unroll
-    for (int j = k + 1; j < NY; ++j) {
-      const double ljk = lane_value(lik, j);
-      if (lane >= j) jr[j] -= lik * ljk;
-    }
+    for (int j = k + 1; j < NY; ++j) jr[j] -= lik * lane_value(lik, j);
   }
 }
 
-// Solve L L^T x = b for the leading nn unknowns (v holds b_lane on entry and
-// x_lane on exit).  Lt: LDS scratch of NY*NY doubles for the transpose.
+// Backward substitution L^T x = y for the leading nn unknowns (v holds y_lane
+// on entry and x_lane on exit; 0 for lanes >= nn).  Lt: LDS scratch of NY*NY
+// doubles for the transpose.
 template <int NY>
-__device__ __forceinline__ double chol_solve_reg(const double (&jr)[NY], double myrd, int nn, double v,
-                                                 double* __restrict__ Lt) {
+__device__ __forceinline__ double chol_bwd_reg(const double (&jr)[NY], double myrd, int nn, double v,
+                                               double* __restrict__ Lt) {
   const int lane = threadIdx.x;
 #pragma unroll
   for (int j = 0; j < NY; ++j)
@@ -62,14 +65,6 @@ __device__ __forceinline__ double chol_solve_reg(const double (&jr)[NY], double 
   double colr[NY];
 #pragma unroll
   for (int j = 0; j < NY; ++j) colr[j] = (lane < NY && j > lane) ? Lt[j * NY + lane] : 0.0;
-#pragma unroll
-  for (int j = 0; j < NY; ++j) {
-    if (j < nn) {
-      if (lane == j) v *= myrd;
-      const double xj = lane_value(v, j);
-      if (lane > j && lane < nn) v -= jr[j] * xj;
-    }
-  }
 #pragma unroll
   for (int j = NY - 1; j >= 0; --j) {
     if (j < nn) {
@@ -156,8 +151,10 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
     kuu += cs[cidx * AC::NQ + AC::Q_KUU];
     sF += cs[cidx * AC::NQ + AC::Q_E];
   }
-  nu = wave_allsum(nu); kuu = wave_allsum(kuu); sF = wave_allsum(sF);
-  const double bw = wave_allsum(bh * w), gw = wave_allsum(gh * w), wAw = wave_allsum(w * Aw);
+  double sums[6] = {nu, kuu, sF, bh * w, gh * w, w * Aw};
+  wave_sum_n<6>(sums);
+  nu = sums[0]; kuu = sums[1]; sF = sums[2];
+  const double bw = sums[3], gw = sums[4], wAw = sums[5];
   const double Juu = c + m * kuu;
   const double Ru = bw + alpha * c + m * nu - Gu;
   const double Rl = lane == N1 ? Ru : R;
@@ -173,9 +170,9 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
   } else if (passes == 0) {
     newdir = 1;
   } else if (Etry <= E + kArmijo * t * slope0 + kEnergyRounding * fmax(Escale, Stry)) {
-    const double stepmax = wave_allmax(act ? fabs(t * dold) : 0.0);
-    const double ymax = wave_allmax(act ? fabs(yt) : 0.0);
-    if (stepmax <= tol * fmax(1.0, ymax)) { done = 1; ok = 1; }
+    double mx[2] = {act ? fabs(t * dold) : 0.0, act ? fabs(yt) : 0.0};
+    wave_max_n<2>(mx);
+    if (mx[0] <= tol * fmax(1.0, mx[1])) { done = 1; ok = 1; }
     else newdir = 1;
   } else {
     halve = 1;
@@ -191,11 +188,11 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
     if (++halvings > kMaxHalvings * newton_max) { done = 1; ok = 0; }
   }
   if (newdir) {
-    // rows of J in LDS, then in registers
-    if (node) {
+    // rows of J in LDS, then in registers; the lanes without a row use a
+    // scratch row NY (zeros), so no store or load needs a lane mask
+    const int row = act ? lane : NY;
 #pragma unroll
-      for (int B = 0; B < NY; ++B) J[A * NY + B] = 0.0;
-    }
+    for (int B = 0; B < NY; ++B) J[row * NY + B] = 0.0;
     wave_sync();
     if (node) {
 #pragma unroll
@@ -209,35 +206,29 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
         J[A * NY + B] = a1 + m * st[q];
       }
       J[A * NY + N1] = jAu;
+      J[N1 * NY + A] = jAu;
     }
-    {
-#pragma unroll
-      for (int B = 0; B < N1; ++B) {
-        const double v = lane_value(jAu, B);
-        if (lane == N1) J[N1 * NY + B] = v;
-      }
-      if (lane == N1) J[N1 * NY + N1] = Juu;
-    }
+    if (lane == N1) J[N1 * NY + N1] = Juu;
     wave_sync();
     double jr[NY];
 #pragma unroll
-    for (int B = 0; B < NY; ++B) jr[B] = act ? J[lane * NY + B] : 0.0;
+    for (int B = 0; B < NY; ++B) jr[B] = J[row * NY + B];
     wave_sync();
-    double myrd = 0.0;
-    chol_reg<NY>(jr, myrd);
+    double myrd = 0.0, v = act ? -Rl : 0.0;
+    chol_fwd_reg<NY>(jr, myrd, v);
     const double schur = lane_value(jr[N1], N1);
     const bool drop = !(schur > kSchurDrop * Juu);
-    if (!drop && lane == N1) { myrd = fast_rsqrt(schur); jr[N1] = schur * myrd; }
-    const double dv = chol_solve_reg<NY>(jr, myrd, drop ? N1 : NY, act ? -Rl : 0.0, J);
+    if (!drop && lane == N1) { myrd = fast_rsqrt(schur); jr[N1] = schur * myrd; v *= myrd; }
+    const double dv = chol_bwd_reg<NY>(jr, myrd, drop ? N1 : NY, v, J);
     dnew = dv;
     slope = wave_allsum(Rl * dv);
     tnew = 1.0;
     ytry_new = ynew + dv;
     // a small direction is applied in full without evaluating the energy there
     const bool dfin = __all(isfinite(dv));
-    const double dmax = wave_allmax(act ? fabs(dv) : 0.0);
-    const double ymax = wave_allmax(act ? fabs(ynew) : 0.0);
-    if (dfin && dmax <= tol * fmax(1.0, ymax)) {
+    double mx[2] = {act ? fabs(dv) : 0.0, act ? fabs(ynew) : 0.0};
+    wave_max_n<2>(mx);
+    if (dfin && mx[0] <= tol * fmax(1.0, mx[1])) {
       ynew = ytry_new;
       done = 1;
       ok = 1;
@@ -292,9 +283,11 @@ __device__ __forceinline__ void level1_newton_reg(const Grid& g1, double m1, con
     const double AV = stencil_shfl<DIM>(V, A, ax, ay, az, mm, node, s1);
     double f, df, F;
     NL<KIND>::all(V, q, f, df, F);
-    const double t1 = 0.5 * wave_allsum(node ? V * AV : 0.0);
-    const double t2 = m1 * wave_allsum(node ? F : 0.0);
-    const double t3 = wave_allsum(G * V);
+    double sums[3] = {node ? V * AV : 0.0, node ? F : 0.0, G * V};
+    wave_sum_n<3>(sums);
+    const double t1 = 0.5 * sums[0];
+    const double t2 = m1 * sums[1];
+    const double t3 = sums[2];
     Eo = t1 + t2 - t3;
     So = fabs(t1) + fabs(t2) + fabs(t3);
   };
@@ -312,15 +305,15 @@ __device__ __forceinline__ void level1_newton_reg(const Grid& g1, double m1, con
       const int nz = abs(bx - ax) + abs(by - ay) + abs(bz - az);
       jr[B] = !node ? 0.0 : (nz == 0 ? 2.0 * DIM * s1 + m1 * df : (nz == 1 ? -s1 : 0.0));
     }
-    double myrd = 0.0;
-    chol_reg<N1>(jr, myrd);
-    if (lane == N1 - 1) { myrd = fast_rsqrt(jr[N1 - 1]); jr[N1 - 1] = jr[N1 - 1] * myrd; }
-    const double D = chol_solve_reg<N1>(jr, myrd, N1, node ? -R : 0.0, sm);
+    double myrd = 0.0, v = node ? -R : 0.0;
+    chol_fwd_reg<N1>(jr, myrd, v);
+    if (lane == N1 - 1) { myrd = fast_rsqrt(jr[N1 - 1]); jr[N1 - 1] = jr[N1 - 1] * myrd; v *= myrd; }
+    const double D = chol_bwd_reg<N1>(jr, myrd, N1, v, sm);
     {   // a small direction is applied in full without evaluating the energy there
       const bool dfin = __all(isfinite(D));
-      const double dmax = wave_allmax(node ? fabs(D) : 0.0);
-      const double umax0 = wave_allmax(node ? fabs(U) : 0.0);
-      if (dfin && dmax <= tol * fmax(1.0, umax0)) {
+      double mx[2] = {node ? fabs(D) : 0.0, node ? fabs(U) : 0.0};
+      wave_max_n<2>(mx);
+      if (dfin && mx[0] <= tol * fmax(1.0, mx[1])) {
         U = U + D;
         status = 1;
         break;
@@ -334,9 +327,10 @@ __device__ __forceinline__ void level1_newton_reg(const Grid& g1, double m1, con
       if (Et <= E + kArmijo * t * slope + kEnergyRounding * fmax(S, St)) break;
       t *= 0.5;
     }
-    const double stepmax = wave_allmax(node ? fabs(T - U) : 0.0);
+    double mx[2] = {node ? fabs(T - U) : 0.0, node ? fabs(T) : 0.0};
+    wave_max_n<2>(mx);
+    const double stepmax = mx[0], umax = mx[1];
     U = T;
-    const double umax = wave_allmax(node ? fabs(U) : 0.0);
     E = Et;
     S = St;
     if (!isfinite(Et)) { status = 2; break; }
