@@ -615,9 +615,9 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
   const Plan& p = h->plan;
   const fmg_options& o = h->ro.o;
   const int nf1 = p.lev[p.nlev].g.n + 1;
-  FMG_LAUNCH(h, st, KC_BEGIN, 0, 0, 0.0, k_begin_solve<<<1, 64, 0, st>>>(h->rep(), p.nlev, h->flag()));
   int first = 2;
   if (p.tail_top >= 2 && o.fuse_small_levels) {
+    FMG_LAUNCH(h, st, KC_BEGIN, 0, 0, 0.0, k_begin_solve<<<1, 64, 0, st>>>(h->rep(), p.nlev, h->flag()));
     // Algorithm 3.2 on levels 1..T in one single-workgroup launch
     const int T = std::min(p.tail_top, p.nlev);
     const size_t lds = fmg_tail_lds_bytes(p);
@@ -639,13 +639,14 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
           }
     first = T + 1;
   } else {
-    // Algorithm 3.2, step 1: exact semilinear solve on V_{h_1}
+    // report reset and Algorithm 3.2, step 1: exact semilinear solve on V_{h_1}
     const LevelInfo& L1 = p.lev[1];
     const size_t lds1 = sizeof(double) * (size_t)level1_lds_doubles(p.N1);
     FMG_LAUNCH(h, st, KC_LEVEL1, 1, p.N1, 0.0,
                k_level1_newton<DIM, KIND><<<1, 256, lds1, st>>>(L1.g, p.N1, h->at<double>(p.off_A1), L1.m,
                                                                 h->slot(), nf1, 1 << (p.nlev - 1), R.x[1],
-                                                                h->rep(), o.newton_max, o.newton_tol));
+                                                                h->rep(), o.newton_max, o.newton_tol, p.nlev,
+                                                                h->flag()));
   }
   // step 2: levels k = first..n
   bool pending_aug = false;   // last update of level k-1 left to the transition
@@ -655,7 +656,7 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     const long long N = interior(L.g, DIM);
     FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (3 * N + interior(C.g, DIM)),
                k_transition<DIM, KIND><<<grid_of(L.g, DIM), kBlock, 0, st>>>(
-                   C.g, C.aug, h->ns(), R.x[k - 1], pending_aug ? 1 : 0, L.g, R.x[k], h->at<double>(p.off_b[k]),
+                   C.g, h->ns(), R.x[k - 1], pending_aug ? 1 : 0, L.g, L.aug, R.x[k], h->at<double>(p.off_b[k]),
                    h->slot(), nf1, 1 << (p.nlev - k), L.m));
     for (int l = 0; l < o.p_steps; ++l) {
       const bool defer = l == o.p_steps - 1 && (k < p.nlev || finish);

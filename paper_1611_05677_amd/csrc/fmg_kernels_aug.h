@@ -812,9 +812,12 @@ __global__ void __launch_bounds__(kBlock) k_newton_finish(Grid g, AugShape s, co
 
 // z = Q w + alpha u~ at node (i, j, l) of the level (0 on the boundary, where
 // u~ and every interior coarse hat function vanish).
+// Q w + alpha v at fine interior node (i, j, l) of a level with augmented-pass
+// shape s, given the value v of u~ there: the coarse hats evaluated at the
+// node's local coordinates in its coarse cell.
 template <int DIM>
-__device__ __forceinline__ double aug_value(const Grid& g, const AugShape& s, const double* __restrict__ y,
-                                            const double* __restrict__ ut, int i, int j, int l) {
+__device__ __forceinline__ double aug_combine(const AugShape& s, const double* __restrict__ y, double v, int i,
+                                              int j, int l) {
   using AC = Acc<DIM>;
   const int r = 1 << s.log2r;
   const double inv_r = 1.0 / r;
@@ -823,7 +826,7 @@ __device__ __forceinline__ double aug_value(const Grid& g, const AugShape& s, co
   double tl[3] = {(i - cx * r) * inv_r, (j - cy * r) * inv_r, DIM == 3 ? (l - cz * r) * inv_r : 0.0};
   double phi[AC::NV];
   kuhn_phi<DIM>(tl, phi);
-  double z = y[s.N1] * ut[gidx<DIM>(g, i, j, l)];
+  double z = y[s.N1] * v;
 #pragma unroll
   for (int a = 0; a < AC::NV; ++a) {
     const int gi = coarse_vertex<DIM>(s.nH, cx, cy, cz, a);
@@ -832,24 +835,30 @@ __device__ __forceinline__ double aug_value(const Grid& g, const AugShape& s, co
   return z;
 }
 
+template <int DIM>
+__device__ __forceinline__ double aug_value(const Grid& g, const AugShape& s, const double* __restrict__ y,
+                                            const double* __restrict__ ut, int i, int j, int l) {
+  return aug_combine<DIM>(s, y, ut[gidx<DIM>(g, i, j, l)], i, j, l);
+}
+
 // Level transition of Algorithm 3.2: u_k^(0) = P u_{k-1} (natural inclusion)
 // and b_k = M_k (g - f(u_k^(0))).  With use_aug, u_{k-1} is the result of the
-// last correction step on level k-1, Q w + alpha u~, evaluated where read.
+// last correction step on level k-1, Q w + alpha u~; since Q w lies in V_H,
+// P (Q w + alpha u~) = Q w + alpha P u~, with Q w evaluated at the fine node
+// (sf: the augmented-pass shape of level k).
 template <int DIM, int KIND>
-__global__ void __launch_bounds__(kBlock) k_transition(Grid gc, AugShape sc, const NewtonState* __restrict__ ns,
+__global__ void __launch_bounds__(kBlock) k_transition(Grid gc, const NewtonState* __restrict__ ns,
                                                        const double* __restrict__ uc, int use_aug, Grid gf,
-                                                       double* __restrict__ uf, double* __restrict__ bf,
-                                                       const ProblemSlot* __restrict__ slot, int nf1, int fs,
-                                                       double m) {
+                                                       AugShape sf, double* __restrict__ uf,
+                                                       double* __restrict__ bf, const ProblemSlot* __restrict__ slot,
+                                                       int nf1, int fs, double m) {
   int i, j, l;
   if (!node_of_thread<DIM>(gf, i, j, l)) return;
   const int si = i & 1, sj = j & 1, sl = DIM == 3 ? (l & 1) : 0;
   const int pi = i >> 1, pj = j >> 1, pl = l >> 1;
-  auto coarse = [&](int a, int b, int c) {
-    return use_aug ? aug_value<DIM>(gc, sc, ns->y, uc, a, b, c) : uc[gidx<DIM>(gc, a, b, c)];
-  };
-  double v = coarse(pi, pj, pl);
-  if (si | sj | sl) v = 0.5 * (v + coarse(pi + si, pj + sj, pl + sl));
+  double v = uc[gidx<DIM>(gc, pi, pj, pl)];
+  if (si | sj | sl) v = 0.5 * (v + uc[gidx<DIM>(gc, pi + si, pj + sj, pl + sl)]);
+  if (use_aug) v = aug_combine<DIM>(sf, ns->y, v, i, j, l);
   const int q = gidx<DIM>(gf, i, j, l);
   uf[q] = v;
   bf[q] = m * (slot->g[fine_load_index(nf1, fs, i, j, l)] - NL<KIND>::f(v, slot->param));
@@ -994,7 +1003,7 @@ __global__ void k_set_slot(ProblemSlot* slot, const double* g, double* u_out, fm
   }
 }
 
-__global__ void k_begin_solve(fmg_report* rep, int levels, int* flag) {
+__device__ __forceinline__ void begin_solve_dev(fmg_report* rep, int levels, int* flag) {
   const int t = threadIdx.x;
   if (t == 0) {
     rep->status = 0; rep->levels = levels; rep->level1_iters = 0; rep->extra_steps = 0;
@@ -1003,6 +1012,8 @@ __global__ void k_begin_solve(fmg_report* rep, int levels, int* flag) {
   }
   if (t < FMG_MAX_LEVELS) { rep->newton_iters[t] = 0; rep->newton_total[t] = 0; rep->alpha[t] = 0.0; }
 }
+
+__global__ void k_begin_solve(fmg_report* rep, int levels, int* flag) { begin_solve_dev(rep, levels, flag); }
 
 // Copy the finest solution out (packed layout, zero boundary) and flag NaN/Inf.
 template <int DIM>
