@@ -1015,42 +1015,45 @@ __device__ __forceinline__ void begin_solve_dev(fmg_report* rep, int levels, int
 
 __global__ void k_begin_solve(fmg_report* rep, int levels, int* flag) { begin_solve_dev(rep, levels, flag); }
 
-// Copy the finest solution out (packed layout, zero boundary) and flag NaN/Inf.
-template <int DIM>
-__global__ void k_output(Grid g, const double* __restrict__ x, const ProblemSlot* __restrict__ slot,
-                         int* __restrict__ flag) {
+// Copy the finest solution out (packed layout, zero boundary) and flag
+// NaN/Inf.  Blocks take whole grid rows (one division per row, none per
+// node); with AUG the level's last update was deferred and Q w + alpha u~ is
+// written directly.
+template <int DIM, bool AUG>
+__device__ __forceinline__ void output_rows(const Grid& g, const AugShape& s, const NewtonState* __restrict__ ns,
+                                            const double* __restrict__ x, const ProblemSlot* __restrict__ slot,
+                                            int* __restrict__ flag) {
   const int n1 = g.n + 1;
-  const size_t total = DIM == 2 ? (size_t)n1 * n1 : (size_t)n1 * n1 * n1;
+  const int rows = DIM == 2 ? n1 : n1 * n1;
   double* __restrict__ out = slot->u_out;
   int bad = 0;
-  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(p % n1), j = (int)((p / n1) % n1), l = DIM == 3 ? (int)(p / ((size_t)n1 * n1)) : 0;
-    const bool bnd = i == 0 || j == 0 || i == g.n || j == g.n || (DIM == 3 && (l == 0 || l == g.n));
-    const double v = bnd ? 0.0 : x[gidx<DIM>(g, i, j, l)];
-    bad |= !isfinite(v);
-    out[p] = v;
+  for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int j = r % n1, l = DIM == 3 ? r / n1 : 0;
+    const bool bnd_row = j == 0 || j == g.n || (DIM == 3 && (l == 0 || l == g.n));
+    double* __restrict__ orow = out + (size_t)r * n1;
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+      double v = 0.0;
+      if (!bnd_row && i != 0 && i != g.n)
+        v = AUG ? aug_value<DIM>(g, s, ns->y, x, i, j, l) : x[gidx<DIM>(g, i, j, l)];
+      bad |= !isfinite(v);
+      orow[i] = v;
+    }
   }
   if (bad) atomicOr(flag, 1);
 }
 
-// Output of the final level when its last update was deferred: writes
-// Q w + alpha u~ directly in the packed layout.
+template <int DIM>
+__global__ void k_output(Grid g, const double* __restrict__ x, const ProblemSlot* __restrict__ slot,
+                         int* __restrict__ flag) {
+  output_rows<DIM, false>(g, AugShape{}, nullptr, x, slot, flag);
+}
+
+// Output of the final level when its last update was deferred.
 template <int DIM>
 __global__ void k_output_update(Grid g, AugShape s, const NewtonState* __restrict__ ns,
                                 const double* __restrict__ ut, const ProblemSlot* __restrict__ slot,
                                 int* __restrict__ flag) {
-  const int n1 = g.n + 1;
-  const size_t total = DIM == 2 ? (size_t)n1 * n1 : (size_t)n1 * n1 * n1;
-  double* __restrict__ out = slot->u_out;
-  int bad = 0;
-  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(p % n1), j = (int)((p / n1) % n1), l = DIM == 3 ? (int)(p / ((size_t)n1 * n1)) : 0;
-    const bool bnd = i == 0 || j == 0 || i == g.n || j == g.n || (DIM == 3 && (l == 0 || l == g.n));
-    const double v = bnd ? 0.0 : aug_value<DIM>(g, s, ns->y, ut, i, j, l);
-    bad |= !isfinite(v);
-    out[p] = v;
-  }
-  if (bad) atomicOr(flag, 1);
+  output_rows<DIM, true>(g, s, ns, ut, slot, flag);
 }
 
 __global__ void k_end_solve(fmg_report* rep, const int* flag, const ProblemSlot* slot) {
