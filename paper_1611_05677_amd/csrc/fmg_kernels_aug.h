@@ -813,24 +813,46 @@ __global__ void __launch_bounds__(kBlock) k_newton_finish(Grid g, AugShape s, co
 // z = Q w + alpha u~ at node (i, j, l) of the level (0 on the boundary, where
 // u~ and every interior coarse hat function vanish).
 // Q w + alpha v at fine interior node (i, j, l) of a level with augmented-pass
-// shape s, given the value v of u~ there: the coarse hats evaluated at the
-// node's local coordinates in its coarse cell.
+// shape s, given the value v of u~ there.  The node lies in the Kuhn simplex
+// of its coarse cell that follows the axes in order of decreasing local
+// coordinate; only that simplex's d+1 vertices have nonzero hats there (the
+// same values, added in the same vertex order, as the max/min hat formula).
 template <int DIM>
 __device__ __forceinline__ double aug_combine(const AugShape& s, const double* __restrict__ y, double v, int i,
                                               int j, int l) {
-  using AC = Acc<DIM>;
   const int r = 1 << s.log2r;
   const double inv_r = 1.0 / r;
   const int cx = min(i >> s.log2r, s.nH - 1), cy = min(j >> s.log2r, s.nH - 1),
             cz = DIM == 3 ? min(l >> s.log2r, s.nH - 1) : 0;
-  double tl[3] = {(i - cx * r) * inv_r, (j - cy * r) * inv_r, DIM == 3 ? (l - cz * r) * inv_r : 0.0};
-  double phi[AC::NV];
-  kuhn_phi<DIM>(tl, phi);
+  const double t[3] = {(i - cx * r) * inv_r, (j - cy * r) * inv_r, DIM == 3 ? (l - cz * r) * inv_r : 0.0};
+  // axes by decreasing coordinate (ties keep the lower axis first)
+  int p0 = 0, p1 = 1, p2 = 2;
+  if (t[p1] > t[p0]) { const int q = p0; p0 = p1; p1 = q; }
+  if (DIM == 3) {
+    if (t[p2] > t[p1]) { const int q = p1; p1 = p2; p2 = q; }
+    if (t[p1] > t[p0]) { const int q = p0; p0 = p1; p1 = q; }
+  }
+  constexpr int NC = DIM + 1;
+  int vtx[NC];
+  double lam[NC];
+  vtx[0] = 0;
+  lam[0] = 1.0 - t[p0];
+  vtx[1] = 1 << p0;
+  lam[1] = t[p0] - t[p1];
+  if (DIM == 2) {
+    vtx[2] = 3;
+    lam[2] = t[p1] - 0.0;
+  } else {
+    vtx[2] = vtx[1] | (1 << p1);
+    lam[2] = t[p1] - t[p2];
+    vtx[NC - 1] = 7;
+    lam[NC - 1] = t[p2] - 0.0;
+  }
   double z = y[s.N1] * v;
 #pragma unroll
-  for (int a = 0; a < AC::NV; ++a) {
-    const int gi = coarse_vertex<DIM>(s.nH, cx, cy, cz, a);
-    if (gi >= 0) z += y[gi] * phi[a];
+  for (int c = 0; c < NC; ++c) {
+    const int gi = coarse_vertex<DIM>(s.nH, cx, cy, cz, vtx[c]);
+    if (gi >= 0) z += y[gi] * lam[c];
   }
   return z;
 }
