@@ -92,6 +92,28 @@ def test_newton_minimize_quadratic_is_one_step():
     assert it <= 2
 
 
+def test_newton_minimize_applies_small_direction_without_evaluation():
+    """Reading of the Newton stop: a direction already below the tolerance is
+    applied in full and ends the iteration without another energy evaluation.
+    On a quadratic energy the first step is exact, so the second direction is
+    at rounding level: two directions, two energy evaluations (start and the
+    first trial point)."""
+    K = np.array([[4.0, -1.0, 0.0], [-1.0, 4.0, -1.0], [0.0, -1.0, 4.0]])
+    b = np.array([1.0, -2.0, 0.5])
+    calls = []
+
+    def energy(y):
+        calls.append(1)
+        return 0.5 * y @ K @ y - b @ y, 1.0
+
+    tol = 1e-14
+    y, it, ok = newton_minimize(
+        np.zeros(3), lambda y: (K @ y - b, K), energy, np.linalg.solve,
+        lambda s, y: np.max(np.abs(s)) <= tol * max(1.0, np.max(np.abs(y))), stagnation=False)
+    assert ok and it == 2 and len(calls) == 2
+    np.testing.assert_allclose(y, np.linalg.solve(K, b), rtol=0, atol=1e-15)
+
+
 @pytest.mark.slow
 def test_o1_convergence_rates():
     """Lemma 2.1 / Corollary 3.1: O(h^2) in L2 and O(h) in the energy norm."""
