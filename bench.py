@@ -402,8 +402,9 @@ def main():
                     help="only the roofline leg (dominant kernel + a reference copy), for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver runs on a single "
-              "device and multi-GPU runs are not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver runs on a single "
+              "device, and sharding a solve or a request stream over several GPUs is not implemented",
+              file=sys.stderr)
         sys.exit(2)
 
     from paper_1611_05677_amd import build as build_mod
