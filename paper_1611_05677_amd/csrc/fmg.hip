@@ -536,9 +536,31 @@ bool mixed_cycle_fused(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st) 
 // One correction step (Algorithm 3.1) on level k; the current iterate is R.x[k].
 // rhs_ready: b_k was already formed (by the level transition).  defer_update:
 // leave u = Q w + alpha u~ to the consumer (next transition or the output).
+// Transitions into fine levels with at most this many interior nodes run at
+// the end of the coarser level's single-workgroup kernel (level 1, or the
+// small-level augmented solve) instead of in a launch of their own.
+constexpr long long kFoldTransitionNodes = 1024;
+
+// Arguments of the level transition into level k (from the current u~ of k-1).
+TransitionArgs transition_args(const fmg_hierarchy* h, const Roles& R, int k, bool use_aug) {
+  const Plan& p = h->plan;
+  TransitionArgs a;
+  a.gc = p.lev[k - 1].g;
+  a.gf = p.lev[k].g;
+  a.sf = p.lev[k].aug;
+  a.uc = R.x[k - 1];
+  a.uf = R.x[k];
+  a.bf = h->at<double>(p.off_b[k]);
+  a.use_aug = use_aug ? 1 : 0;
+  a.nf1 = p.lev[p.nlev].g.n + 1;
+  a.fs = 1 << (p.nlev - k);
+  a.m = p.lev[k].m;
+  return a;
+}
+
 template <int DIM, int KIND>
 void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bool rhs_ready,
-                     bool defer_update) {
+                     bool defer_update, bool fold_next) {
   const Plan& p = h->plan;
   const LevelInfo& L = p.lev[k];
   const fmg_options& o = h->ro.o;
@@ -573,7 +595,8 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
     FMG_LAUNCH(h, st, KC_AUG_SMALL, k, N, 0.0,
                (k_aug_solve_small<DIM, KIND><<<1, kTailThreads, fmg_tail_lds_bytes(p), st>>>(
                    L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), k, o.newton_max,
-                   o.newton_tol, defer_update ? 0 : 1)));
+                   o.newton_tol, defer_update ? 0 : 1, fold_next ? 1 : 0,
+                   fold_next ? transition_args(h, R, k + 1, defer_update) : TransitionArgs{})));
     return;
   }
   const size_t lds = aug_pass_lds_bytes(p);
@@ -616,6 +639,7 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
   const fmg_options& o = h->ro.o;
   const int nf1 = p.lev[p.nlev].g.n + 1;
   int first = 2;
+  bool folded = false;   // the transition into the next level is done already
   if (p.tail_top >= 2 && o.fuse_small_levels) {
     FMG_LAUNCH(h, st, KC_BEGIN, 0, 0, 0.0, k_begin_solve<<<1, 64, 0, st>>>(h->rep(), p.nlev, h->flag()));
     // Algorithm 3.2 on levels 1..T in one single-workgroup launch
@@ -642,11 +666,14 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     // report reset and Algorithm 3.2, step 1: exact semilinear solve on V_{h_1}
     const LevelInfo& L1 = p.lev[1];
     const size_t lds1 = sizeof(double) * (size_t)level1_lds_doubles(p.N1);
+    folded = p.nlev >= 2 && interior(p.lev[2].g, DIM) <= kFoldTransitionNodes;
     FMG_LAUNCH(h, st, KC_LEVEL1, 1, p.N1, 0.0,
                k_level1_newton<DIM, KIND><<<1, 256, lds1, st>>>(L1.g, p.N1, h->at<double>(p.off_A1), L1.m,
                                                                 h->slot(), nf1, 1 << (p.nlev - 1), R.x[1],
                                                                 h->rep(), o.newton_max, o.newton_tol, p.nlev,
-                                                                h->flag()));
+                                                                h->flag(), folded ? 1 : 0,
+                                                                folded ? transition_args(h, R, 2, false)
+                                                                       : TransitionArgs{}));
   }
   // step 2: levels k = first..n
   bool pending_aug = false;   // last update of level k-1 left to the transition
@@ -654,14 +681,19 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     const LevelInfo& L = p.lev[k];
     const LevelInfo& C = p.lev[k - 1];
     const long long N = interior(L.g, DIM);
-    FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (3 * N + interior(C.g, DIM)),
-               k_transition<DIM, KIND><<<grid_of(L.g, DIM), kBlock, 0, st>>>(
-                   C.g, h->ns(), R.x[k - 1], pending_aug ? 1 : 0, L.g, L.aug, R.x[k], h->at<double>(p.off_b[k]),
-                   h->slot(), nf1, 1 << (p.nlev - k), L.m));
+    if (!folded)
+      FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (3 * N + interior(C.g, DIM)),
+                 k_transition<DIM, KIND><<<grid_of(L.g, DIM), kBlock, 0, st>>>(
+                     transition_args(h, R, k, pending_aug), h->ns(), h->slot()));
+    folded = false;
     for (int l = 0; l < o.p_steps; ++l) {
       const bool defer = l == o.p_steps - 1 && (k < p.nlev || finish);
-      correction_step<DIM, KIND>(h, R, k, st, l == 0, defer);
+      // the last small-level augmented solve also performs a small next transition
+      const bool fold = defer && k < p.nlev && N <= o.aug_small_nodes &&
+                        interior(p.lev[k + 1].g, DIM) <= kFoldTransitionNodes;
+      correction_step<DIM, KIND>(h, R, k, st, l == 0, defer, fold);
       pending_aug = defer;
+      folded = fold;
     }
   }
   if (finish) {
@@ -678,7 +710,7 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
 }
 
 typedef void (*record_fn)(const fmg_hierarchy*, Roles&, bool, hipStream_t);
-typedef void (*step_fn)(const fmg_hierarchy*, Roles&, int, hipStream_t, bool, bool);
+typedef void (*step_fn)(const fmg_hierarchy*, Roles&, int, hipStream_t, bool, bool, bool);
 
 template <int DIM>
 record_fn pick_record(int kind) {
@@ -1152,7 +1184,7 @@ int fmg_solve(fmg_hierarchy* h, const fmg_problem* prob, double* d_u_out, fmg_re
       const dim3 grid = grid_of(F.g, p.dim);
       if (p.dim == 2) k_copy_interior<2, double><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev);
       else k_copy_interior<3, double><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev);
-      step(h, R, k, s, false, false);
+      step(h, R, k, s, false, false, false);
       if (p.dim == 2) k_diff_norm_partials<2><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev, npart);
       else k_diff_norm_partials<3><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev, npart);
       k_sum_pairs<<<1, kBlock, 0, s>>>(npart, p.norm_blocks, nout);

@@ -868,22 +868,50 @@ __device__ __forceinline__ double aug_value(const Grid& g, const AugShape& s, co
 // last correction step on level k-1, Q w + alpha u~; since Q w lies in V_H,
 // P (Q w + alpha u~) = Q w + alpha P u~, with Q w evaluated at the fine node
 // (sf: the augmented-pass shape of level k).
+// The transition's arguments: fine level (grid gf, augmented-pass shape sf,
+// arrays uf, bf, load stride fs, mass m) from coarse u~ (grid gc, array uc).
+struct TransitionArgs {
+  Grid gc, gf;
+  AugShape sf;
+  const double* uc;
+  double* uf;
+  double* bf;
+  int use_aug, nf1, fs;
+  double m;
+};
+
 template <int DIM, int KIND>
-__global__ void __launch_bounds__(kBlock) k_transition(Grid gc, const NewtonState* __restrict__ ns,
-                                                       const double* __restrict__ uc, int use_aug, Grid gf,
-                                                       AugShape sf, double* __restrict__ uf,
-                                                       double* __restrict__ bf, const ProblemSlot* __restrict__ slot,
-                                                       int nf1, int fs, double m) {
-  int i, j, l;
-  if (!node_of_thread<DIM>(gf, i, j, l)) return;
+__device__ __forceinline__ void transition_node(const TransitionArgs& a, const double* __restrict__ y,
+                                                const ProblemSlot* __restrict__ slot, int i, int j, int l) {
   const int si = i & 1, sj = j & 1, sl = DIM == 3 ? (l & 1) : 0;
   const int pi = i >> 1, pj = j >> 1, pl = l >> 1;
-  double v = uc[gidx<DIM>(gc, pi, pj, pl)];
-  if (si | sj | sl) v = 0.5 * (v + uc[gidx<DIM>(gc, pi + si, pj + sj, pl + sl)]);
-  if (use_aug) v = aug_combine<DIM>(sf, ns->y, v, i, j, l);
-  const int q = gidx<DIM>(gf, i, j, l);
-  uf[q] = v;
-  bf[q] = m * (slot->g[fine_load_index(nf1, fs, i, j, l)] - NL<KIND>::f(v, slot->param));
+  double v = a.uc[gidx<DIM>(a.gc, pi, pj, pl)];
+  if (si | sj | sl) v = 0.5 * (v + a.uc[gidx<DIM>(a.gc, pi + si, pj + sj, pl + sl)]);
+  if (a.use_aug) v = aug_combine<DIM>(a.sf, y, v, i, j, l);
+  const int q = gidx<DIM>(a.gf, i, j, l);
+  a.uf[q] = v;
+  a.bf[q] = a.m * (slot->g[fine_load_index(a.nf1, a.fs, i, j, l)] - NL<KIND>::f(v, slot->param));
+}
+
+template <int DIM, int KIND>
+__global__ void __launch_bounds__(kBlock) k_transition(TransitionArgs a, const NewtonState* __restrict__ ns,
+                                                       const ProblemSlot* __restrict__ slot) {
+  int i, j, l;
+  if (!node_of_thread<DIM>(a.gf, i, j, l)) return;
+  transition_node<DIM, KIND>(a, ns->y, slot, i, j, l);
+}
+
+// The same transition by the threads of one block (small fine levels, at the
+// end of the single-workgroup kernel of the coarser level); y may be in LDS.
+template <int DIM, int KIND>
+__device__ __forceinline__ void transition_block(const TransitionArgs& a, const double* y,
+                                                 const ProblemSlot* __restrict__ slot) {
+  const int mm = a.gf.n - 1;
+  const int total = DIM == 2 ? mm * mm : mm * mm * mm;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int i = 1 + t % mm, j = 1 + (t / mm) % mm, l = DIM == 3 ? 1 + t / (mm * mm) : 0;
+    transition_node<DIM, KIND>(a, y, slot, i, j, l);
+  }
 }
 
 // u = Q w + alpha u~ at fine interior node (i, j, l) (in place on u~).

@@ -110,13 +110,16 @@ __device__ __forceinline__ void aug_solve_dev(const Grid& g, const AugShape& s, 
 // The augmented problem of one correction step on a small level, solved by
 // one workgroup in one launch (setup sums, every Newton iteration, and the
 // update unless the caller defers it).
+// With fold, the block then also performs the transition into the next
+// (small) level, reading (w, alpha) from LDS.
 template <int DIM, int KIND>
 __global__ void __launch_bounds__(kTailThreads) k_aug_solve_small(Grid g, AugShape s, double* __restrict__ ut,
                                                                   const ProblemSlot* __restrict__ slot, int nf1,
                                                                   int fs, double scale, double m,
                                                                   const double* __restrict__ A1, NewtonState* ns,
                                                                   fmg_report* rep, int level, int newton_max,
-                                                                  double tol, int do_update) {
+                                                                  double tol, int do_update, int fold,
+                                                                  TransitionArgs next) {
   extern __shared__ double smem[];
   // the Newton state lives in LDS for the whole solve (its many small,
   // dependent reads and writes then cost LDS latency, not L2 latency) and is
@@ -124,6 +127,7 @@ __global__ void __launch_bounds__(kTailThreads) k_aug_solve_small(Grid g, AugSha
   __shared__ NewtonState nsl;
   aug_solve_dev<DIM, KIND>(g, s, ut, slot, nf1, fs, scale, m, A1, &nsl, rep, level, newton_max, tol, smem,
                            do_update != 0);
+  if (fold) transition_block<DIM, KIND>(next, nsl.y, slot);
   const double* src = reinterpret_cast<const double*>(&nsl);
   double* dst = reinterpret_cast<double*>(ns);
   static_assert(sizeof(NewtonState) % sizeof(double) == 0, "NewtonState copied as doubles");

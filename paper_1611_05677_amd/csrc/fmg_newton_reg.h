@@ -366,16 +366,18 @@ __device__ __forceinline__ void newton_step_dev(const AugShape& s, const double*
 }
 
 // First kernel of a solve: resets the report (as k_begin_solve), then
-// Algorithm 3.2, step 1.
+// Algorithm 3.2, step 1, then (fold) the transition into level 2.
 template <int DIM, int KIND>
 __global__ void __launch_bounds__(256) k_level1_newton(Grid g1, int N1, const double* __restrict__ A1, double m1,
                                                        const ProblemSlot* __restrict__ slot, int nf1, int fs,
                                                        double* __restrict__ x1, fmg_report* __restrict__ rep,
-                                                       int newton_max, double tol, int levels, int* flag) {
+                                                       int newton_max, double tol, int levels, int* flag, int fold,
+                                                       TransitionArgs next) {
   extern __shared__ double smem[];
   begin_solve_dev(rep, levels, flag);
   __syncthreads();
   level1_dispatch<DIM, KIND>(g1, N1, A1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
+  if (fold) transition_block<DIM, KIND>(next, nullptr, slot);
 }
 
 }  // namespace fmg
