@@ -789,6 +789,51 @@ __device__ __forceinline__ void setup_cells_by_waves(const Grid& g, const AugSha
   else setup_cells_seg<DIM, 64>(g, s, ut, gl, nf1, fs, scale, cs);
 }
 
+// Setup sums (to cs_s) and the quadrature sums at the Newton start z = u~ (to
+// cs_q) of all cells in one visit of the nodes, segmented as quad_cells_seg.
+template <int DIM, int KIND, int LPC>
+__device__ __forceinline__ void setup_quad_cells_seg(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                                     const double* __restrict__ gl, int nf1, int fs, double scale,
+                                                     double param, double* cs_s, double* cs_q) {
+  using AC = Acc<DIM>;
+  constexpr int CPW = 64 / LPC;
+  const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int sub = lane % LPC;
+  const int nodes = 1 << (DIM * s.log2r);
+  for (int c0 = wave * CPW; c0 < ncell; c0 += nw * CPW) {
+    const int cell = c0 + lane / LPC;
+    double acc[AC::NS + AC::NQ];
+#pragma unroll
+    for (int q = 0; q < AC::NS + AC::NQ; ++q) acc[q] = 0.0;
+    if (cell < ncell)
+      setup_quad_accumulate<DIM, KIND>(g, s, ut, gl, nf1, fs, scale, param, cell, 0, nodes, sub, LPC, acc,
+                                       acc + AC::NS);
+#pragma unroll
+    for (int q = 0; q < AC::NS + AC::NQ; ++q) {
+      const double v = seg_sum<LPC>(acc[q]);
+      if (sub == LPC - 1 && cell < ncell) {
+        if (q < AC::NS) cs_s[cell * AC::NS + q] = v;
+        else cs_q[cell * AC::NQ + q - AC::NS] = v;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIM, int KIND>
+__device__ __forceinline__ void setup_quad_cells_by_waves(const Grid& g, const AugShape& s,
+                                                          const double* __restrict__ ut, const double* __restrict__ gl,
+                                                          int nf1, int fs, double scale, double param, double* cs_s,
+                                                          double* cs_q) {
+  const int nodes_log = DIM * s.log2r;
+  if (nodes_log <= 2) setup_quad_cells_seg<DIM, KIND, 4>(g, s, ut, gl, nf1, fs, scale, param, cs_s, cs_q);
+  else if (nodes_log == 3) setup_quad_cells_seg<DIM, KIND, 8>(g, s, ut, gl, nf1, fs, scale, param, cs_s, cs_q);
+  else if (nodes_log == 4) setup_quad_cells_seg<DIM, KIND, 16>(g, s, ut, gl, nf1, fs, scale, param, cs_s, cs_q);
+  else if (nodes_log == 5) setup_quad_cells_seg<DIM, KIND, 32>(g, s, ut, gl, nf1, fs, scale, param, cs_s, cs_q);
+  else setup_quad_cells_seg<DIM, KIND, 64>(g, s, ut, gl, nf1, fs, scale, param, cs_s, cs_q);
+}
+
 // Completes a Newton solve that the passes of the launch sequence did not
 // finish: one block evaluates the fine quadrature itself (3D).
 template <int DIM, int KIND>

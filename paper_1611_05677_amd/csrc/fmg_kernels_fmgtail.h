@@ -88,12 +88,22 @@ __device__ __forceinline__ void aug_solve_dev(const Grid& g, const AugShape& s, 
   double* sm = cs + ncell * AC::NQ;
   if (threadIdx.x == 0) newton_state_reset(ns, s.N1, level);
   __syncthreads();
-  setup_cells_by_waves<DIM>(g, s, ut, slot->g, nf1, fs, scale, cs);
-  setup_scatter<DIM>(s, cs, m, ns);
+  // 2D: the setup sums (held in the Newton scratch until scattered) and the
+  // sums at the start y0 = (0, .., 0, 1) in one visit; 3D: two visits (the
+  // fused accumulators would not fit the registers of a 1024-thread block)
+  bool have_sums = DIM == 2;
+  if (DIM == 2) {
+    setup_quad_cells_by_waves<DIM, KIND>(g, s, ut, slot->g, nf1, fs, scale, slot->param, sm, cs);
+    setup_scatter<DIM>(s, sm, m, ns);
+  } else {
+    setup_cells_by_waves<DIM>(g, s, ut, slot->g, nf1, fs, scale, cs);
+    setup_scatter<DIM>(s, cs, m, ns);
+  }
   while (true) {
     __syncthreads();
     if (ns->done) break;
-    quad_cells_by_waves<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cs);
+    if (!have_sums) quad_cells_by_waves<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cs);
+    have_sums = false;
     newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   }
   __syncthreads();
