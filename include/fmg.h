@@ -113,8 +113,8 @@ typedef struct {
                               steps, incl. the Newton solves) in one launch */
     int aug_max_blocks; /* size of a fine quadrature pass of the augmented
                            problem, in 256-thread workgroups (upper bound;
-                           64..16384; 512); large 2D levels run 1024-thread
-                           workgroups, a quarter as many                    */
+                           64..16384; 512); large levels run 1024-thread
+                           (2D) or 512-thread (3D) workgroups, fewer of them */
     int aug_small_nodes; /* levels with at most this many interior nodes solve
                             the augmented problem in one single-workgroup
                             launch (0: never; default 4096 in 2D, 0 in 3D)   */

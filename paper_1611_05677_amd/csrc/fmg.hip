@@ -132,9 +132,9 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p) {
     L.m = d == 2 ? h * h : h * h * h;
     if (k >= 2) {
       const int nodes_log = d * (k - 1);
-      // large 2D levels: 1024-thread blocks, a quarter as many
-      const bool wide = d == 2 && nodes_log >= kAugWideNodesLog;
-      const int tlog = wide ? 10 : 8;
+      // large levels: 1024-thread (2D) or 512-thread (3D) blocks, fewer of them
+      const bool wide = nodes_log >= (d == 2 ? aug_wide_nodes_log<2>() : aug_wide_nodes_log<3>());
+      const int tlog = wide ? ilog2(d == 2 ? aug_threads<2>() : aug_threads<3>()) : 8;
       const int cap_log = ilog2(std::max(1, (ro.o.aug_max_blocks >> (tlog - 8)) / ncell));
       const int bpc_log = std::max(0, std::min(nodes_log - tlog, cap_log));
       L.aug_threads = 1 << tlog;

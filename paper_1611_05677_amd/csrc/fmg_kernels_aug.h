@@ -614,15 +614,16 @@ __device__ __forceinline__ void setup_reduce(const AugShape& s, const double* __
   setup_scatter<DIM>(s, cs, m, ns);
 }
 
-// Threads per block of the fine quadrature passes: 256, or 1024 on the 2D
-// levels with at least 2^kAugWideNodesLog fine nodes per coarse cell (a
-// quarter as many blocks, so a quarter as many release/ticket operations and
-// partials for the last block to reduce).  The kernel is compiled for the
-// larger size; the 3D quadrature needs more registers and keeps 256.
+// Threads per block of the fine quadrature passes: 256, or on levels with at
+// least 2^aug_wide_nodes_log fine nodes per coarse cell 1024 (2D) / 512 (3D),
+// so fewer blocks: fewer release/ticket operations and fewer partials for the
+// last block to reduce.  The 3D quadrature needs more registers per thread and
+// stops at 512.
 constexpr int kAugMaxThreads = 1024;
-constexpr int kAugWideNodesLog = 14;
 template <int DIM>
-__host__ __device__ constexpr int aug_threads() { return DIM == 2 ? kAugMaxThreads : 256; }
+__host__ __device__ constexpr int aug_threads() { return DIM == 2 ? kAugMaxThreads : 512; }
+template <int DIM>
+__host__ __device__ constexpr int aug_wide_nodes_log() { return DIM == 2 ? 12 : 15; }
 
 // LDS doubles of k_newton_step / k_newton_finish for a block of `threads`.
 __host__ __device__ constexpr int newton_kernel_lds_doubles(int ncell, int NQ, int N1, int threads) {
