@@ -701,10 +701,11 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     const double nodes = DIM == 2 ? (double)(F.g.n + 1) * (F.g.n + 1) : (double)(F.g.n + 1) * (F.g.n + 1) * (F.g.n + 1);
     if (pending_aug)
       FMG_LAUNCH(h, st, KC_OUTPUT_UPDATE, p.nlev, interior(F.g, DIM), 16.0 * nodes,
-                 k_output_update<DIM><<<1024, 256, 0, st>>>(F.g, F.aug, h->ns(), R.x[p.nlev], h->slot(), h->flag()));
+                 k_output_update<DIM><<<output_blocks<DIM>(F.g), 256, 0, st>>>(F.g, F.aug, h->ns(), R.x[p.nlev],
+                                                                                h->slot(), h->flag()));
     else
       FMG_LAUNCH(h, st, KC_OUTPUT, p.nlev, interior(F.g, DIM), 16.0 * nodes,
-                 k_output<DIM><<<1024, 256, 0, st>>>(F.g, R.x[p.nlev], h->slot(), h->flag()));
+                 k_output<DIM><<<output_blocks<DIM>(F.g), 256, 0, st>>>(F.g, R.x[p.nlev], h->slot(), h->flag()));
     FMG_LAUNCH(h, st, KC_END, 0, 0, 0.0, k_end_solve<<<1, 64, 0, st>>>(h->rep(), h->flag(), h->slot()));
   }
 }
@@ -1209,8 +1210,8 @@ int fmg_solve(fmg_hierarchy* h, const fmg_problem* prob, double* d_u_out, fmg_re
     info.last_update_rel = rel;
     if (!reached && info.status == FMG_OK) info.status = FMG_E_NOT_CONVERGED;
     if (hipMemcpyAsync(h->rep(), &info, sizeof(info), hipMemcpyHostToDevice, s) != hipSuccess) return FMG_E_HIP;
-    if (p.dim == 2) k_output<2><<<1024, 256, 0, s>>>(F.g, R.x[k], h->slot(), h->flag());
-    else k_output<3><<<1024, 256, 0, s>>>(F.g, R.x[k], h->slot(), h->flag());
+    if (p.dim == 2) k_output<2><<<output_blocks<2>(F.g), 256, 0, s>>>(F.g, R.x[k], h->slot(), h->flag());
+    else k_output<3><<<output_blocks<3>(F.g), 256, 0, s>>>(F.g, R.x[k], h->slot(), h->flag());
     k_end_solve<<<1, 64, 0, s>>>(h->rep(), h->flag(), h->slot());
     if (hipStreamSynchronize(s) != hipSuccess) return FMG_E_HIP;
   }

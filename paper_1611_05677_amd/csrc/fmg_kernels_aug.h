@@ -1138,6 +1138,11 @@ __device__ __forceinline__ void output_rows(const Grid& g, const AugShape& s, co
   if (bad) atomicOr(flag, 1);
 }
 
+// One block per grid row, so that all rows are in flight at once (a block that
+// walked many rows would wait on each row's loads in turn).
+template <int DIM>
+inline int output_blocks(const Grid& g) { return DIM == 2 ? g.n + 1 : (g.n + 1) * (g.n + 1); }
+
 template <int DIM>
 __global__ void k_output(Grid g, const double* __restrict__ x, const ProblemSlot* __restrict__ slot,
                          int* __restrict__ flag) {
