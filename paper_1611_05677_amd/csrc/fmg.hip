@@ -681,10 +681,14 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     const LevelInfo& L = p.lev[k];
     const LevelInfo& C = p.lev[k - 1];
     const long long N = interior(L.g, DIM);
-    if (!folded)
+    if (!folded && pending_aug)
       FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (3 * N + interior(C.g, DIM)),
-                 k_transition<DIM, KIND><<<grid_of(L.g, DIM), kBlock, 0, st>>>(
-                     transition_args(h, R, k, pending_aug), h->ns(), h->slot()));
+                 k_transition<DIM, KIND, true><<<grid_of(L.g, DIM), kBlock, 0, st>>>(
+                     transition_args(h, R, k, true), h->ns(), h->slot()));
+    else if (!folded)
+      FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (3 * N + interior(C.g, DIM)),
+                 k_transition<DIM, KIND, false><<<grid_of(L.g, DIM), kBlock, 0, st>>>(
+                     transition_args(h, R, k, false), h->ns(), h->slot()));
     folded = false;
     for (int l = 0; l < o.p_steps; ++l) {
       const bool defer = l == o.p_steps - 1 && (k < p.nlev || finish);

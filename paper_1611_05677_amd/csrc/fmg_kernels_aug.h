@@ -864,13 +864,16 @@ __global__ void __launch_bounds__(kBlock) k_newton_finish(Grid g, AugShape s, co
 // coordinate; only that simplex's d+1 vertices have nonzero hats there (the
 // same values, added in the same vertex order, as the max/min hat formula).
 template <int DIM>
-__device__ __forceinline__ double aug_combine(const AugShape& s, const double* __restrict__ y, double v, int i,
-                                              int j, int l) {
+__device__ __forceinline__ void kuhn_weights(const AugShape& s, int i, int j, int l, int& cx, int& cy, int& cz,
+                                             int (&vtx)[DIM + 1], double (&lam)[DIM + 1]) {
   const int r = 1 << s.log2r;
-  const double inv_r = 1.0 / r;
-  const int cx = min(i >> s.log2r, s.nH - 1), cy = min(j >> s.log2r, s.nH - 1),
-            cz = DIM == 3 ? min(l >> s.log2r, s.nH - 1) : 0;
-  const double t[3] = {(i - cx * r) * inv_r, (j - cy * r) * inv_r, DIM == 3 ? (l - cz * r) * inv_r : 0.0};
+  cx = min(i >> s.log2r, s.nH - 1);
+  cy = min(j >> s.log2r, s.nH - 1);
+  cz = DIM == 3 ? min(l >> s.log2r, s.nH - 1) : 0;
+  // Local coordinates in units of the fine step; the barycentric weights are
+  // their differences times 1/r = 2^-log2r (exact).
+  const int t[3] = {i - cx * r, j - cy * r, DIM == 3 ? l - cz * r : 0};
+  const double inv_r = __longlong_as_double((long long)(1023 - s.log2r) << 52);
   // axes by decreasing coordinate (ties keep the lower axis first)
   int p0 = 0, p1 = 1, p2 = 2;
   if (t[p1] > t[p0]) { const int q = p0; p0 = p1; p1 = q; }
@@ -878,29 +881,57 @@ __device__ __forceinline__ double aug_combine(const AugShape& s, const double* _
     if (t[p2] > t[p1]) { const int q = p1; p1 = p2; p2 = q; }
     if (t[p1] > t[p0]) { const int q = p0; p0 = p1; p1 = q; }
   }
-  constexpr int NC = DIM + 1;
-  int vtx[NC];
-  double lam[NC];
   vtx[0] = 0;
-  lam[0] = 1.0 - t[p0];
+  lam[0] = (r - t[p0]) * inv_r;
   vtx[1] = 1 << p0;
-  lam[1] = t[p0] - t[p1];
-  if (DIM == 2) {
+  lam[1] = (t[p0] - t[p1]) * inv_r;
+  if constexpr (DIM == 2) {
     vtx[2] = 3;
-    lam[2] = t[p1] - 0.0;
+    lam[2] = t[p1] * inv_r;
   } else {
     vtx[2] = vtx[1] | (1 << p1);
-    lam[2] = t[p1] - t[p2];
-    vtx[NC - 1] = 7;
-    lam[NC - 1] = t[p2] - 0.0;
+    lam[2] = (t[p1] - t[p2]) * inv_r;
+    vtx[3] = 7;
+    lam[3] = t[p2] * inv_r;
   }
-  double z = y[s.N1] * v;
+}
+
+// The coefficients and weights of Q w + alpha v at fine node (i, j, l): all
+// d+1 loads are issued before any is used (boundary vertices read y[0] and get
+// weight 0), so a wave waits for one round trip, not d+1.
+template <int DIM>
+struct AugTerms {
+  double w[DIM + 1], lam[DIM + 1], alpha;
+};
+
+template <int DIM>
+__device__ __forceinline__ AugTerms<DIM> aug_gather(const AugShape& s, const double* __restrict__ y, int i, int j,
+                                                    int l) {
+  AugTerms<DIM> t;
+  int cx, cy, cz, vtx[DIM + 1];
+  kuhn_weights<DIM>(s, i, j, l, cx, cy, cz, vtx, t.lam);
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
+  for (int c = 0; c <= DIM; ++c) {
     const int gi = coarse_vertex<DIM>(s.nH, cx, cy, cz, vtx[c]);
-    if (gi >= 0) z += y[gi] * lam[c];
+    t.w[c] = y[max(gi, 0)];
+    if (gi < 0) t.lam[c] = 0.0;
   }
+  t.alpha = y[s.N1];
+  return t;
+}
+
+template <int DIM>
+__device__ __forceinline__ double aug_apply(const AugTerms<DIM>& t, double v) {
+  double z = t.alpha * v;
+#pragma unroll
+  for (int c = 0; c <= DIM; ++c) z += t.w[c] * t.lam[c];
   return z;
+}
+
+template <int DIM>
+__device__ __forceinline__ double aug_combine(const AugShape& s, const double* __restrict__ y, double v, int i,
+                                              int j, int l) {
+  return aug_apply<DIM>(aug_gather<DIM>(s, y, i, j, l), v);
 }
 
 template <int DIM>
@@ -926,25 +957,33 @@ struct TransitionArgs {
   double m;
 };
 
-template <int DIM, int KIND>
+// AUG: a.use_aug, as a template argument so that the node's code has no
+// branch and every load is issued before the first use.
+template <int DIM, int KIND, bool AUG>
 __device__ __forceinline__ void transition_node(const TransitionArgs& a, const double* __restrict__ y,
                                                 const ProblemSlot* __restrict__ slot, int i, int j, int l) {
   const int si = i & 1, sj = j & 1, sl = DIM == 3 ? (l & 1) : 0;
   const int pi = i >> 1, pj = j >> 1, pl = l >> 1;
-  double v = a.uc[gidx<DIM>(a.gc, pi, pj, pl)];
-  if (si | sj | sl) v = 0.5 * (v + a.uc[gidx<DIM>(a.gc, pi + si, pj + sj, pl + sl)]);
-  if (a.use_aug) v = aug_combine<DIM>(a.sf, y, v, i, j, l);
+  const double gv = slot->g[fine_load_index(a.nf1, a.fs, i, j, l)];
+  AugTerms<DIM> t;
+  if constexpr (AUG) t = aug_gather<DIM>(a.sf, y, i, j, l);
+  // both coarse values are loaded; at a coarse node they are the same value,
+  // and 0.5 (v0 + v0) = v0 exactly
+  const double v0 = a.uc[gidx<DIM>(a.gc, pi, pj, pl)];
+  const double v1 = a.uc[gidx<DIM>(a.gc, pi + si, pj + sj, pl + sl)];
+  double v = 0.5 * (v0 + v1);
+  if constexpr (AUG) v = aug_apply<DIM>(t, v);
   const int q = gidx<DIM>(a.gf, i, j, l);
   a.uf[q] = v;
-  a.bf[q] = a.m * (slot->g[fine_load_index(a.nf1, a.fs, i, j, l)] - NL<KIND>::f(v, slot->param));
+  a.bf[q] = a.m * (gv - NL<KIND>::f(v, slot->param));
 }
 
-template <int DIM, int KIND>
+template <int DIM, int KIND, bool AUG>
 __global__ void __launch_bounds__(kBlock) k_transition(TransitionArgs a, const NewtonState* __restrict__ ns,
                                                        const ProblemSlot* __restrict__ slot) {
   int i, j, l;
   if (!node_of_thread<DIM>(a.gf, i, j, l)) return;
-  transition_node<DIM, KIND>(a, ns->y, slot, i, j, l);
+  transition_node<DIM, KIND, AUG>(a, ns->y, slot, i, j, l);
 }
 
 // The same transition by the threads of one block (small fine levels, at the
@@ -956,7 +995,8 @@ __device__ __forceinline__ void transition_block(const TransitionArgs& a, const 
   const int total = DIM == 2 ? mm * mm : mm * mm * mm;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     const int i = 1 + t % mm, j = 1 + (t / mm) % mm, l = DIM == 3 ? 1 + t / (mm * mm) : 0;
-    transition_node<DIM, KIND>(a, y, slot, i, j, l);
+    if (a.use_aug) transition_node<DIM, KIND, true>(a, y, slot, i, j, l);
+    else transition_node<DIM, KIND, false>(a, y, slot, i, j, l);
   }
 }
 
