@@ -97,10 +97,14 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid cg, Grid f, const T* __
   if (!node_of_thread<DIM>(f, i, j, l)) return;
   const int si = i & 1, sj = j & 1, sl = DIM == 3 ? (l & 1) : 0;
   const int pi = i >> 1, pj = j >> 1, pl = l >> 1;
-  T v = xc[gidx<DIM>(cg, pi, pj, pl)];
-  if (si | sj | sl) v = T(0.5) * (v + xc[gidx<DIM>(cg, pi + si, pj + sj, pl + sl)]);
+  // All loads are issued before the first use; at a coarse node both coarse
+  // loads read the same value, and 0.5 (v0 + v0) = v0 exactly.
   const int q = gidx<DIM>(f, i, j, l);
-  xf[q] = ADD ? xf[q] + v : v;
+  const T old = ADD ? xf[q] : T(0);
+  const T v0 = xc[gidx<DIM>(cg, pi, pj, pl)];
+  const T v1 = xc[gidx<DIM>(cg, pi + si, pj + sj, pl + sl)];
+  const T v = T(0.5) * (v0 + v1);
+  xf[q] = ADD ? old + v : v;
 }
 
 // Dense index r (x fastest over the (n1-1)^d interior nodes of level 1) -> grid index.
