@@ -45,6 +45,32 @@ __device__ __forceinline__ bool node_of_thread(const Grid& g, int& i, int& j, in
   return i < g.n;
 }
 
+// The same blocks as node_of_thread, with the rows of each XCD's chunk taken
+// in bands of kRowBand rows (j) that march through the planes (l).  A kernel
+// whose threads read several planes on either side (the residual restriction:
+// two fine planes each way) then keeps its working set in the XCD's L2; in
+// plane order the rows in flight span about eight fine planes of two arrays.
+constexpr int kRowBand = 16;
+
+template <int DIM>
+__device__ __forceinline__ bool node_of_thread_banded(const Grid& g, int& i, int& j, int& l) {
+  if (DIM == 2) return node_of_thread<DIM>(g, i, j, l);
+  const int nb = logical_blocks<DIM>(g.n);
+  const int per = (nb + 7) >> 3;
+  const int L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (L >= nb) return false;
+  const int gx = (g.n - 1 + kBlock - 1) / kBlock, gy = g.n - 1;
+  const int bx = L % gx, r = L / gx;  // row r of the gy * gy interior rows
+  const int band = r / (kRowBand * gy);
+  const int rem = r - band * kRowBand * gy;
+  const int h = min(kRowBand, gy - band * kRowBand);  // rows in this band
+  const int lr = rem / h, jr = rem - lr * h;
+  i = 1 + bx * kBlock + threadIdx.x;
+  j = 1 + band * kRowBand + jr;
+  l = 1 + lr;
+  return i < g.n;
+}
+
 template <int DIM, typename T>
 __device__ __forceinline__ T apply_A_at(const T* __restrict__ x, int c, const Grid& g, T scale) {
   T s = (x[c - 1] + x[c + 1]) + (x[c - g.px] + x[c + g.px]);
@@ -77,7 +103,7 @@ template <int DIM, typename T>
 __global__ void __launch_bounds__(kBlock) k_resid_restrict(Grid f, Grid cg, const T* __restrict__ x,
                                                            const T* __restrict__ b, T* __restrict__ bc, T scale) {
   int i, j, l;
-  if (!node_of_thread<DIM>(cg, i, j, l)) return;
+  if (!node_of_thread_banded<DIM>(cg, i, j, l)) return;
   const int q = gidx<DIM>(f, 2 * i, 2 * j, 2 * l);
   auto r = [&](int p) { return b[p] - apply_A_at<DIM>(x, p, f, scale); };
   const int dx = 1, dy = f.px;
