@@ -99,7 +99,10 @@ typedef struct {
                            Newton solve that needs more                      */
     int mode;           /* FMG_PAPER: Algorithm 3.2 as stated; FMG_CONVERGED:
                            then repeat correction steps on the finest level
-                           until ||du||_2 <= converged_tol ||u||_2 (synchronous) */
+                           until ||du||_2 <= converged_tol ||u||_2 (synchronous).
+                           A stop because ||du|| no longer shrinks counts as
+                           converged only if ||du||/||u|| <= 1e3 converged_tol;
+                           otherwise the report says FMG_E_NOT_CONVERGED */
     int converged_max_steps;
     double converged_tol;
     int use_graph;      /* 1: capture the solve once into a hipGraph and replay */
@@ -187,7 +190,10 @@ int fmg_solve_batch(fmg_hierarchy *const *hs, const fmg_problem *probs,
                     double *const *outs, fmg_report *const *reports, int count,
                     void *stream);
 
-/* Release the hierarchy's host state and graph; never frees caller memory. */
+/* Release the hierarchy's host state and graphs; never frees caller memory.
+ * Waits for the device first (hipDeviceSynchronize), so solves still in
+ * flight on h finish before its graphs go; the caller's workspace must stay
+ * valid until this call returns. */
 int fmg_destroy(fmg_hierarchy *h);
 
 const char *fmg_status_str(int status);

@@ -39,23 +39,41 @@ def simplex_geometry(X: np.ndarray):
     return grads, vol, C
 
 
-def assemble_full(mesh: Mesh):
-    """Full stiffness matrix (all nodes, CSR) and lumped mass vector.
+# Element loops are taken in chunks of this many simplices, so that the 3D
+# 256^3 mesh (about 10^8 tetrahedra) fits in memory.  Meshes with fewer
+# simplices are assembled in one chunk (the same operations as an unchunked
+# loop); above it the duplicate entries of different chunks are added chunk by
+# chunk, which only changes the order of rounding of those sums.
+ELEMENT_CHUNK = 1 << 24
 
-    K_T[i,j] = |T| grad(lambda_i) . grad(lambda_j)  (local P1 stiffness).
-    """
-    T = mesh.simplices
+
+def _assemble_chunk(mesh: Mesh, T: np.ndarray, N: int):
     X = mesh.coords[T]
     grads, vol, _ = simplex_geometry(X)
     d = mesh.dim
     Kloc = vol[:, None, None] * np.einsum("eia,eja->eij", grads, grads)
     rows = np.repeat(T, d + 1, axis=1).reshape(-1)
     cols = np.tile(T, (1, d + 1)).reshape(-1)
-    N = mesh.coords.shape[0]
     K = sp.csr_matrix((Kloc.reshape(-1), (rows, cols)), shape=(N, N))
     K.sum_duplicates()
+    return K, vol
+
+
+def assemble_full(mesh: Mesh):
+    """Full stiffness matrix (all nodes, CSR) and lumped mass vector.
+
+    K_T[i,j] = |T| grad(lambda_i) . grad(lambda_j)  (local P1 stiffness).
+    """
+    d = mesh.dim
+    N = mesh.coords.shape[0]
     mass = np.zeros(N)
-    np.add.at(mass, T.reshape(-1), np.repeat(vol / (d + 1), d + 1))
+    K = None
+    for s in range(0, mesh.simplices.shape[0], ELEMENT_CHUNK):
+        T = mesh.simplices[s:s + ELEMENT_CHUNK]
+        Kc, vol = _assemble_chunk(mesh, T, N)
+        K = Kc if K is None else (K + Kc).tocsr()
+        del Kc
+        np.add.at(mass, T.reshape(-1), np.repeat(vol / (d + 1), d + 1))
     return K, mass
 
 
@@ -110,14 +128,22 @@ def interpolation_matrix(coarse: Mesh, fine_points: np.ndarray) -> sp.csr_matrix
     the nested spaces (eq. "FEM_Space_Series").  Columns are coarse interior
     nodes in ascending id order.
     """
-    sid, bary = locate_in_coarse(coarse, fine_points)
-    verts = coarse.simplices[sid]                       # (Nf, d+1) coarse node ids
     col_of = -np.ones(coarse.coords.shape[0], dtype=np.int64)
     col_of[coarse.interior] = np.arange(coarse.interior.size)
-    cols = col_of[verts]
-    rows = np.repeat(np.arange(fine_points.shape[0]), coarse.dim + 1).reshape(cols.shape)
-    keep = (cols >= 0) & (np.abs(bary) > 0)
-    P = sp.csr_matrix((bary[keep], (rows[keep], cols[keep])),
+    vals, rows_all, cols_all = [], [], []
+    # points are located independently, so taking them in chunks changes nothing
+    for s in range(0, fine_points.shape[0], ELEMENT_CHUNK):
+        pts = fine_points[s:s + ELEMENT_CHUNK]
+        sid, bary = locate_in_coarse(coarse, pts)
+        verts = coarse.simplices[sid]                   # (Nf, d+1) coarse node ids
+        cols = col_of[verts]
+        rows = np.repeat(np.arange(s, s + pts.shape[0]), coarse.dim + 1).reshape(cols.shape)
+        keep = (cols >= 0) & (np.abs(bary) > 0)
+        vals.append(bary[keep])
+        rows_all.append(rows[keep])
+        cols_all.append(cols[keep])
+        del sid, bary, verts, cols, rows, keep
+    P = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows_all), np.concatenate(cols_all))),
                       shape=(fine_points.shape[0], coarse.interior.size))
     P.sum_duplicates()
     return P

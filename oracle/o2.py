@@ -42,6 +42,10 @@ from .nonlinear import Nonlinearity
 
 JACOBI, CHEBYSHEV = 1, 2
 SCHUR_DROP = 1e-12
+# Converged mode: an update that no longer shrinks ends the iteration; it counts
+# as converged only if the relative update is within this factor of the
+# tolerance (rounding level), and as not converged otherwise.
+STAGNATION_FLOOR = 1e3
 
 
 def chebyshev_weights(nu: int, lo: float, hi: float) -> list[float]:
@@ -255,6 +259,7 @@ class FMGResult:
     level1_iters: int = 0
     extra_steps: int = 0
     last_update_rel: float = float("nan")
+    converged_ok: bool = True             # converged mode: reached the tolerance
     hierarchy: Hierarchy | None = None
 
     def full(self) -> np.ndarray:
@@ -281,13 +286,20 @@ def fmg(H: Hierarchy, g_fine_nodes: np.ndarray, nl: Nonlinearity,
         k = H.n_levels - 1
         g_k = H.g_on_level(g_fine_nodes, k)
         prev = np.inf
+        res.converged_ok = False
         for s in range(opts.converged_max_steps):
             unew, _ = correction_step(H, k, u, g_k, nl, opts)
             du = np.linalg.norm(unew - u)
             u = unew
             res.extra_steps = s + 1
             res.last_update_rel = du / max(np.linalg.norm(u), 1e-300)
-            if res.last_update_rel <= opts.converged_tol or du >= prev:
+            if res.last_update_rel <= opts.converged_tol:
+                res.converged_ok = True
+                break
+            if du >= prev:
+                # the update stopped shrinking: rounding level if it is already
+                # small, otherwise the iteration stagnates or diverges
+                res.converged_ok = res.last_update_rel <= STAGNATION_FLOOR * opts.converged_tol
                 break
             prev = du
     res.U = u

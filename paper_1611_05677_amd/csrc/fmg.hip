@@ -27,6 +27,9 @@ using namespace fmg;
 namespace {
 
 constexpr size_t kAlign = 256;
+// Converged mode: a stop on a non-shrinking update counts as converged only
+// within this factor of the tolerance.
+constexpr double kStagnationFloor = 1e3;
 constexpr int kNormBlocksMax = 1 << 20;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -1185,6 +1188,7 @@ int fmg_solve(fmg_hierarchy* h, const fmg_problem* prob, double* d_u_out, fmg_re
     double* nout = h->at<double>(p.off_norm_out);
     double prev = INFINITY, rel = 0.0;
     int steps = 0;
+    bool reached = false;
     for (int it = 0; it < o.converged_max_steps; ++it) {
       const dim3 grid = grid_of(F.g, p.dim);
       if (p.dim == 2) k_copy_interior<2, double><<<grid, kBlock, 0, s>>>(F.g, R.x[k], uprev);
@@ -1200,10 +1204,16 @@ int fmg_solve(fmg_hierarchy* h, const fmg_problem* prob, double* d_u_out, fmg_re
       steps = it + 1;
       const double du = std::sqrt(host[0]);
       rel = du / std::max(std::sqrt(host[1]), 1e-300);
-      if (rel <= o.converged_tol || du >= prev) break;
+      if (rel <= o.converged_tol) { reached = true; break; }
+      if (du >= prev) {
+        // the update stopped shrinking: rounding level only if it is already
+        // within kStagnationFloor of the tolerance; otherwise the iteration
+        // stagnates or diverges and the solve is reported as not converged
+        reached = rel <= kStagnationFloor * o.converged_tol;
+        break;
+      }
       prev = du;
     }
-    const bool reached = rel <= o.converged_tol || steps < o.converged_max_steps;
     // record the extra-step info on the device report, then finish
     fmg_report info;
     std::memset(&info, 0, sizeof(info));
@@ -1338,6 +1348,9 @@ int fmg_solve_batch(fmg_hierarchy* const* hs, const fmg_problem* probs, double* 
 
 int fmg_destroy(fmg_hierarchy* h) {
   if (!h) return FMG_E_INVALID;
+  // solves are asynchronous: a graph of h (or a batch graph holding h) may
+  // still run on some stream, so wait for the device before releasing them
+  (void)hipDeviceSynchronize();
   {
     std::lock_guard<std::mutex> lock(g_batch_mu);
     for (size_t i = 0; i < g_batches.size();) {

@@ -346,3 +346,16 @@ def serving_trace(count: int = 4000, rate_hz: float = 200.0, seed: int = SERVE_S
 def request_problem(req: Request, modes: int = 16) -> Problem:
     return fourier_problem(f"req_{req.rid}", req.dim, 4, req.refinements, req.f_kind,
                            req.seed, modes=modes)
+
+
+# Random linear functionals for comparing long nodal vectors: row i of the
+# sketch is a vector of i.i.d. N(0,1) weights from PCG64([seed, i]).  For any
+# difference vector e, the mean of (w_i . e)^2 over the rows estimates |e|^2,
+# so agreement of a few such functionals checks a whole vector, not a sample.
+SKETCH_SEED = 20161118
+SKETCH_ROWS = 16
+
+
+def sketch_row(count: int, i: int, seed: int = SKETCH_SEED) -> np.ndarray:
+    """Weights of sketch row i for vectors of `count` entries."""
+    return np.random.default_rng([seed, i]).standard_normal(count)

@@ -7,7 +7,11 @@ time, so this script stores, per workload:
   * the converged solution ubar_h (O2 in converged mode; its agreement with
     the fine-space Newton oracle O1 is pinned by the CPU tests) at the same
     sample, and the discretisation error disc = ||I_h u - ubar_h|| and the
-    algebraic error alg = ||u_FMG - ubar_h|| in the vertex-quadrature L2 norm.
+    algebraic error alg = ||u_FMG - ubar_h|| in the vertex-quadrature L2 norm;
+  * for both vectors, SKETCH_ROWS random linear functionals of the whole
+    vector (seeded Gaussian weights from the shared input module), which
+    compare every entry at once: the mean square of the functionals of a
+    difference estimates its squared L2 norm.
 
     python tests/golden/make_golden.py [--only NAME]
 """
@@ -36,7 +40,12 @@ SAMPLE_SEED = 20161117
 WORKLOADS = {
     "square_cubic_sin_expx_L9": lambda: W.square_cubic_sin_expx(9),
     "cube_u_plus_sin_L5": lambda: W.cube_u_plus_sin(5),
+    "cube_u_plus_sin_L6": lambda: W.cube_u_plus_sin(6),
 }
+
+
+def sketch(v: np.ndarray) -> list[float]:
+    return [float(W.sketch_row(v.size, i) @ v) for i in range(W.SKETCH_ROWS)]
 
 
 def sample_nodes(dim: int, n: int) -> np.ndarray:
@@ -73,6 +82,8 @@ def make(name: str) -> dict:
         "sample_idx": idx.tolist(),
         "paper_sample": [float(v) for v in up[idx]],
         "converged_sample": [float(v) for v in uc[idx]],
+        "paper_sketch": sketch(up),
+        "converged_sketch": sketch(uc),
         "paper_norm2": float(np.linalg.norm(up)),
         "paper_sum": float(np.sum(up)),
         "converged_norm2": float(np.linalg.norm(uc)),
@@ -83,7 +94,10 @@ def make(name: str) -> dict:
         "level1_iters": paper.level1_iters,
         "converged_extra_steps": conv.extra_steps,
         "converged_last_update_rel": conv.last_update_rel,
+        "converged_ok": bool(conv.converged_ok),
         "oracle_fmg_seconds": t2 - t1,
+        "oracle_hierarchy_seconds": t1 - t0,
+        "oracle_converged_seconds": t3 - t2,
     }
 
 
