@@ -1,6 +1,10 @@
 """Build the HIP library libfmg.so for gfx950 (in-tree, next to this file).
 
     python -m paper_1611_05677_amd.build
+
+The device code is split over several translation units (the host recorder
+and the multigrid kernels in fmg.hip; the nonlinearity-dependent kernels in
+fmg_kind_*.hip), compiled in parallel and linked into one shared library.
 """
 from __future__ import annotations
 
@@ -8,15 +12,16 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmg.so")
-SOURCES = ["fmg.hip"]
+SOURCES = ["fmg.hip", "fmg_kind_2d_a.hip", "fmg_kind_2d_b.hip", "fmg_kind_3d_a.hip", "fmg_kind_3d_b.hip"]
 ARCH = os.environ.get("FMG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
+    "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
     # packed float32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -30,16 +35,42 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES]]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libfmg.so")
-    os.replace(tmp, LIB)
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    cc = hipcc()
+    jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1))
+    with tempfile.TemporaryDirectory(prefix="fmg_build_") as tmpdir:
+        objs, pending = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, os.path.splitext(src)[0] + ".o")
+            cmd = [cc, *HIPCC_FLAGS, "-c", "-o", obj, os.path.join(CSRC, src)]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            objs.append(obj)
+            pending.append(cmd)
+        running = []
+        failed = []
+        while pending or running:
+            while pending and len(running) < jobs:
+                cmd = pending.pop(0)
+                running.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                                      text=True)))
+            cmd, proc = running.pop(0)
+            out, _ = proc.communicate()
+            if proc.returncode != 0:
+                failed.append((cmd, out))
+        if failed:
+            for cmd, out in failed:
+                sys.stderr.write(" ".join(cmd) + "\n" + out)
+            raise RuntimeError("hipcc failed building libfmg.so")
+        tmp = LIB + ".tmp"
+        link = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(link), flush=True)
+        res = subprocess.run(link, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("linking libfmg.so failed")
+        os.replace(tmp, LIB)
     return LIB
 
 

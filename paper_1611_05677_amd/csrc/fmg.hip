@@ -20,7 +20,7 @@
 #include "fmg_kernels_fused2d.h"
 #include "fmg_kernels_stream2d.h"
 #include "fmg_kernels_stream3d.h"
-#include "fmg_newton_reg.h"
+#include "fmg_launch.h"
 
 using namespace fmg;
 
@@ -574,7 +574,7 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   // step 1: linearised problem, m V-cycles from u^(l)
   if (!rhs_ready)
     FMG_LAUNCH(h, st, KC_RHS, k, N, 24.0 * N,
-               k_rhs<DIM, KIND><<<grid, kBlock, 0, st>>>(L.g, h->slot(), nf1, fs, R.x[k], b, L.m));
+               (launch_rhs<DIM, KIND>(grid, st, L.g, h->slot(), nf1, fs, R.x[k], b, L.m)));
   for (int c = 0; c < o.m_vcycles; ++c) {
     if (o.precision == FMG_FP64) {
       vcycle<DIM, double>(h, R, k, false, st);
@@ -596,9 +596,9 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   if (N <= o.aug_small_nodes) {
     // the whole augmented solve (and the update unless deferred) by one workgroup
     FMG_LAUNCH(h, st, KC_AUG_SMALL, k, N, 0.0,
-               (k_aug_solve_small<DIM, KIND><<<1, kTailThreads, fmg_tail_lds_bytes(p), st>>>(
-                   L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), k, o.newton_max,
-                   o.newton_tol, defer_update ? 0 : 1, fold_next ? 1 : 0,
+               (launch_aug_small<DIM, KIND>(
+                   fmg_tail_lds_bytes(p), st, L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(),
+                   h->rep(), k, o.newton_max, o.newton_tol, defer_update ? 0 : 1, fold_next ? 1 : 0,
                    fold_next ? transition_args(h, R, k + 1, defer_update) : TransitionArgs{})));
     return;
   }
@@ -607,30 +607,30 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   constexpr bool kFinishInPass = DIM == 2;
   if (npass == 1 && kFinishInPass)
     FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
-               (k_aug_pass<DIM, KIND, true, true><<<L.aug_blocks, L.aug_threads, lds, st>>>(
+               (launch_aug_pass<DIM, KIND, true, true>(L.aug_blocks, L.aug_threads, lds, st, 
                    L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, ticket, k,
                    o.newton_max, o.newton_tol)));
   else
     FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
-               (k_aug_pass<DIM, KIND, true, false><<<L.aug_blocks, L.aug_threads, lds, st>>>(
+               (launch_aug_pass<DIM, KIND, true, false>(L.aug_blocks, L.aug_threads, lds, st, 
                    L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps, ticket, k,
                    o.newton_max, o.newton_tol)));
   for (int pass = 1; pass < npass; ++pass) {
     if (pass == npass - 1 && kFinishInPass)
       FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
-                 (k_aug_pass<DIM, KIND, false, true><<<L.aug_blocks, L.aug_threads, lds, st>>>(
+                 (launch_aug_pass<DIM, KIND, false, true>(L.aug_blocks, L.aug_threads, lds, st, 
                      L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps,
                      ticket, k, o.newton_max, o.newton_tol)));
     else
       FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
-                 (k_aug_pass<DIM, KIND, false, false><<<L.aug_blocks, L.aug_threads, lds, st>>>(
+                 (launch_aug_pass<DIM, KIND, false, false>(L.aug_blocks, L.aug_threads, lds, st, 
                      L.g, L.aug, R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(), pq, ps,
                      ticket, k, o.newton_max, o.newton_tol)));
   }
-  if (!kFinishInPass)
+  if constexpr (!kFinishInPass)
     FMG_LAUNCH(h, st, KC_NEWTON_FINISH, k, N, 0.0,
-               k_newton_finish<DIM, KIND><<<1, kBlock, lds, st>>>(L.g, L.aug, R.x[k], h->slot(), A1, L.m, h->ns(),
-                                                                   h->rep(), o.newton_max, o.newton_tol));
+               (launch_newton_finish<DIM, KIND>(lds, st, L.g, L.aug, R.x[k], h->slot(), A1, L.m, h->ns(), h->rep(),
+                                                o.newton_max, o.newton_tol)));
   if (!defer_update)
     FMG_LAUNCH(h, st, KC_AUG_UPDATE, k, N, 16.0 * N,
                k_aug_update<DIM><<<grid, kBlock, 0, st>>>(L.g, L.aug, h->ns(), R.x[k]));
@@ -651,10 +651,10 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     const FmgTailParams* P = h->at<FmgTailParams>(p.off_fmgtail);
     if (o.precision == FMG_FP64)
       FMG_LAUNCH(h, st, KC_FMG_TAIL, T, interior(p.lev[T].g, DIM), 0.0,
-                 (k_fmg_tail<DIM, KIND, false><<<1, kTailThreads, lds, st>>>(P)));
+                 (launch_fmg_tail<DIM, KIND, false>(lds, st, P)));
     else
       FMG_LAUNCH(h, st, KC_FMG_TAIL, T, interior(p.lev[T].g, DIM), 0.0,
-                 (k_fmg_tail<DIM, KIND, true><<<1, kTailThreads, lds, st>>>(P)));
+                 (launch_fmg_tail<DIM, KIND, true>(lds, st, P)));
     // mirror the role swaps of the V-cycles inside
     const bool odd = (o.nu_pre + o.nu_post) & 1;
     for (int k = 2; k <= T; ++k)
@@ -671,12 +671,10 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     const size_t lds1 = sizeof(double) * (size_t)level1_lds_doubles(p.N1);
     folded = p.nlev >= 2 && interior(p.lev[2].g, DIM) <= kFoldTransitionNodes;
     FMG_LAUNCH(h, st, KC_LEVEL1, 1, p.N1, 0.0,
-               k_level1_newton<DIM, KIND><<<1, 256, lds1, st>>>(L1.g, p.N1, h->at<double>(p.off_A1), L1.m,
-                                                                h->slot(), nf1, 1 << (p.nlev - 1), R.x[1],
-                                                                h->rep(), o.newton_max, o.newton_tol, p.nlev,
-                                                                h->flag(), folded ? 1 : 0,
-                                                                folded ? transition_args(h, R, 2, false)
-                                                                       : TransitionArgs{}));
+               (launch_level1<DIM, KIND>(lds1, st, L1.g, p.N1, h->at<double>(p.off_A1), L1.m, h->slot(), nf1,
+                                         1 << (p.nlev - 1), R.x[1], h->rep(), o.newton_max, o.newton_tol, p.nlev,
+                                         h->flag(), folded ? 1 : 0,
+                                         folded ? transition_args(h, R, 2, false) : TransitionArgs{})));
   }
   // step 2: levels k = first..n
   bool pending_aug = false;   // last update of level k-1 left to the transition
@@ -686,12 +684,12 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     const long long N = interior(L.g, DIM);
     if (!folded && pending_aug)
       FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (3 * N + interior(C.g, DIM)),
-                 k_transition<DIM, KIND, true><<<grid_of(L.g, DIM), kBlock, 0, st>>>(
-                     transition_args(h, R, k, true), h->ns(), h->slot()));
+                 (launch_transition<DIM, KIND, true>(grid_of(L.g, DIM), st, transition_args(h, R, k, true), h->ns(),
+                                                     h->slot())));
     else if (!folded)
       FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (3 * N + interior(C.g, DIM)),
-                 k_transition<DIM, KIND, false><<<grid_of(L.g, DIM), kBlock, 0, st>>>(
-                     transition_args(h, R, k, false), h->ns(), h->slot()));
+                 (launch_transition<DIM, KIND, false>(grid_of(L.g, DIM), st, transition_args(h, R, k, false),
+                                                      h->ns(), h->slot())));
     folded = false;
     for (int l = 0; l < o.p_steps; ++l) {
       const bool defer = l == o.p_steps - 1 && (k < p.nlev || finish);

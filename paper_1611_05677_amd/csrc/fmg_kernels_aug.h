@@ -1132,7 +1132,7 @@ __device__ __forceinline__ void level1_newton_dev(const Grid& g1, int N1, const 
 // ---------------------------------------------------------------------------
 // Solve bookkeeping
 // ---------------------------------------------------------------------------
-__global__ void k_set_slot(ProblemSlot* slot, const double* g, double* u_out, fmg_report* rep_out, double param,
+static __global__ void k_set_slot(ProblemSlot* slot, const double* g, double* u_out, fmg_report* rep_out, double param,
                            int kind) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     slot->g = g; slot->u_out = u_out; slot->rep_out = rep_out; slot->param = param; slot->kind = kind;
@@ -1149,7 +1149,7 @@ __device__ __forceinline__ void begin_solve_dev(fmg_report* rep, int levels, int
   if (t < FMG_MAX_LEVELS) { rep->newton_iters[t] = 0; rep->newton_total[t] = 0; rep->alpha[t] = 0.0; }
 }
 
-__global__ void k_begin_solve(fmg_report* rep, int levels, int* flag) { begin_solve_dev(rep, levels, flag); }
+static __global__ void k_begin_solve(fmg_report* rep, int levels, int* flag) { begin_solve_dev(rep, levels, flag); }
 
 // Copy the finest solution out (packed layout, zero boundary) and flag
 // NaN/Inf.  Blocks take whole grid rows (one division per row, none per
@@ -1197,7 +1197,7 @@ __global__ void k_output_update(Grid g, AugShape s, const NewtonState* __restric
   output_rows<DIM, true>(g, s, ns, ut, slot, flag);
 }
 
-__global__ void k_end_solve(fmg_report* rep, const int* flag, const ProblemSlot* slot) {
+static __global__ void k_end_solve(fmg_report* rep, const int* flag, const ProblemSlot* slot) {
   if (threadIdx.x != 0) return;
   if (*flag) report_status(rep, FMG_E_NONFINITE);
   fmg_report* out = slot->rep_out;
@@ -1223,7 +1223,7 @@ __global__ void __launch_bounds__(kBlock) k_diff_norm_partials(Grid g, const dou
   if (threadIdx.x < 2) partials[(size_t)blockIdx.x * 2 + threadIdx.x] = t;
 }
 
-__global__ void k_sum_pairs(const double* __restrict__ partials, size_t count, double* __restrict__ out) {
+static __global__ void k_sum_pairs(const double* __restrict__ partials, size_t count, double* __restrict__ out) {
   __shared__ double lds[(kBlock / 64) * 2];
   double acc[2] = {0.0, 0.0};
   for (size_t b = threadIdx.x; b < count; b += blockDim.x) {

@@ -1,0 +1,102 @@
+// Definitions of the launchers declared in fmg_launch.h, and the macro that
+// instantiates them for one dimension and one nonlinearity.
+#pragma once
+
+#include "fmg_launch.h"
+#include "fmg_newton_reg.h"
+
+namespace fmg {
+
+template <int DIM, int KIND>
+void launch_rhs(dim3 grid, hipStream_t st, Grid g, const ProblemSlot* slot, int nf1, int fs, const double* u,
+                double* b, double m) {
+  k_rhs<DIM, KIND><<<grid, kBlock, 0, st>>>(g, slot, nf1, fs, u, b, m);
+}
+
+template <int DIM, int KIND>
+void launch_aug_small(size_t lds, hipStream_t st, Grid g, AugShape s, double* ut, const ProblemSlot* slot,
+                      int nf1, int fs, double scale, double m, const double* A1, NewtonState* ns, fmg_report* rep,
+                      int level, int newton_max, double tol, int do_update, int fold, TransitionArgs next) {
+  k_aug_solve_small<DIM, KIND><<<1, kTailThreads, lds, st>>>(g, s, ut, slot, nf1, fs, scale, m, A1, ns, rep, level,
+                                                             newton_max, tol, do_update, fold, next);
+}
+
+template <int DIM, int KIND, bool SETUP, bool FINISH>
+void launch_aug_pass(int blocks, int threads, size_t lds, hipStream_t st, Grid g, AugShape s, const double* ut,
+                     const ProblemSlot* slot, int nf1, int fs, double scale, double m, const double* A1,
+                     NewtonState* ns, fmg_report* rep, double* pq, double* ps, unsigned* tickets, int level,
+                     int newton_max, double tol) {
+  k_aug_pass<DIM, KIND, SETUP, FINISH><<<blocks, threads, lds, st>>>(g, s, ut, slot, nf1, fs, scale, m, A1, ns, rep,
+                                                                     pq, ps, tickets, level, newton_max, tol);
+}
+
+template <int DIM, int KIND>
+void launch_newton_finish(size_t lds, hipStream_t st, Grid g, AugShape s, const double* ut,
+                          const ProblemSlot* slot, const double* A1, double m, NewtonState* ns, fmg_report* rep,
+                          int newton_max, double tol) {
+  k_newton_finish<DIM, KIND><<<1, kBlock, lds, st>>>(g, s, ut, slot, A1, m, ns, rep, newton_max, tol);
+}
+
+template <int DIM, int KIND, bool MIXED>
+void launch_fmg_tail(size_t lds, hipStream_t st, const FmgTailParams* P) {
+  k_fmg_tail<DIM, KIND, MIXED><<<1, kTailThreads, lds, st>>>(P);
+}
+
+template <int DIM, int KIND>
+void launch_level1(size_t lds, hipStream_t st, Grid g1, int N1, const double* A1, double m1,
+                   const ProblemSlot* slot, int nf1, int fs, double* x1, fmg_report* rep, int newton_max,
+                   double tol, int levels, int* flag, int fold, TransitionArgs next) {
+  k_level1_newton<DIM, KIND><<<1, 256, lds, st>>>(g1, N1, A1, m1, slot, nf1, fs, x1, rep, newton_max, tol, levels,
+                                                  flag, fold, next);
+}
+
+template <int DIM, int KIND, bool AUG>
+void launch_transition(dim3 grid, hipStream_t st, TransitionArgs a, const NewtonState* ns,
+                       const ProblemSlot* slot) {
+  k_transition<DIM, KIND, AUG><<<grid, kBlock, 0, st>>>(a, ns, slot);
+}
+
+}  // namespace fmg
+
+// Every launcher for dimension D and nonlinearity K (the 2D recorder never
+// launches the separate Newton finisher, so it is only instantiated in 3D).
+#define FMG_INSTANTIATE_KIND(D, K)                                                                   \
+  namespace fmg {                                                                                    \
+  template void launch_rhs<D, K>(dim3, hipStream_t, Grid, const ProblemSlot*, int, int, const double*, \
+                                 double*, double);                                                   \
+  template void launch_aug_small<D, K>(size_t, hipStream_t, Grid, AugShape, double*, const ProblemSlot*, \
+                                       int, int, double, double, const double*, NewtonState*,         \
+                                       fmg_report*, int, int, double, int, int, TransitionArgs);       \
+  template void launch_aug_pass<D, K, true, true>(int, int, size_t, hipStream_t, Grid, AugShape,       \
+                                                  const double*, const ProblemSlot*, int, int, double,  \
+                                                  double, const double*, NewtonState*, fmg_report*,     \
+                                                  double*, double*, unsigned*, int, int, double);       \
+  template void launch_aug_pass<D, K, true, false>(int, int, size_t, hipStream_t, Grid, AugShape,      \
+                                                   const double*, const ProblemSlot*, int, int, double, \
+                                                   double, const double*, NewtonState*, fmg_report*,    \
+                                                   double*, double*, unsigned*, int, int, double);      \
+  template void launch_aug_pass<D, K, false, true>(int, int, size_t, hipStream_t, Grid, AugShape,      \
+                                                   const double*, const ProblemSlot*, int, int, double, \
+                                                   double, const double*, NewtonState*, fmg_report*,    \
+                                                   double*, double*, unsigned*, int, int, double);      \
+  template void launch_aug_pass<D, K, false, false>(int, int, size_t, hipStream_t, Grid, AugShape,     \
+                                                    const double*, const ProblemSlot*, int, int, double, \
+                                                    double, const double*, NewtonState*, fmg_report*,   \
+                                                    double*, double*, unsigned*, int, int, double);     \
+  template void launch_fmg_tail<D, K, false>(size_t, hipStream_t, const FmgTailParams*);              \
+  template void launch_fmg_tail<D, K, true>(size_t, hipStream_t, const FmgTailParams*);               \
+  template void launch_level1<D, K>(size_t, hipStream_t, Grid, int, const double*, double,             \
+                                    const ProblemSlot*, int, int, double*, fmg_report*, int, double,   \
+                                    int, int*, int, TransitionArgs);                                   \
+  template void launch_transition<D, K, true>(dim3, hipStream_t, TransitionArgs, const NewtonState*,   \
+                                              const ProblemSlot*);                                     \
+  template void launch_transition<D, K, false>(dim3, hipStream_t, TransitionArgs, const NewtonState*,  \
+                                               const ProblemSlot*);                                    \
+  }
+
+#define FMG_INSTANTIATE_FINISH(D, K)                                                                 \
+  namespace fmg {                                                                                    \
+  template void launch_newton_finish<D, K>(size_t, hipStream_t, Grid, AugShape, const double*,         \
+                                           const ProblemSlot*, const double*, double, NewtonState*,   \
+                                           fmg_report*, int, double);                                 \
+  }
