@@ -52,7 +52,9 @@ enum fmg_status {
     FMG_E_WORKSPACE = 3,      /* workspace too small or misaligned         */
     FMG_E_HIP = 4,            /* a HIP runtime call failed                 */
     FMG_E_NOT_CONVERGED = 5,  /* Newton cap hit (report) / converged mode  */
-    FMG_E_NONFINITE = 6       /* NaN or Inf in the solution (report)       */
+    FMG_E_NONFINITE = 6,      /* NaN or Inf in the solution (report)       */
+    FMG_E_SCRATCH = 7         /* fmg_solve_noalloc: problem needs more than
+                                 FMG_NOALLOC_SCRATCH_BYTES of workspace    */
 };
 
 /* Nonlinearity catalogue f(u); every entry is nondecreasing (Assumption A). */
@@ -171,6 +173,30 @@ int fmg_create_hierarchy(const fmg_mesh_desc *mesh, const fmg_options *opts,
  * mode; FMG_CONVERGED mode synchronises the stream once per extra step. */
 int fmg_solve(fmg_hierarchy *h, const fmg_problem *prob, double *d_u_out,
               fmg_report *report, void *stream);
+
+/* For callers that cannot allocate device memory (code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid hipMalloc): one solve
+ * as fmg_create_hierarchy + fmg_solve + fmg_destroy would do it, with the
+ * workspace in a static device buffer of FMG_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends, instead of a
+ * caller's workspace.  The call allocates nothing on the device or the host
+ * heap and captures no graph: it plans on the host stack, clears the level
+ * arrays of the buffer, forms the level-1 tables with a kernel and enqueues
+ * the solve's kernels on `stream` (asynchronous, stream-ordered).  The
+ * caller passes the load, the output d_u_out and (optionally) report exactly
+ * as for fmg_solve; the report pointer is the only way to get the status.
+ * Differences from the hierarchy path: the small levels of the V-cycle run as
+ * a single-workgroup cycle instead of a host-built dense operator (the same
+ * operations; results agree to rounding), and only FMG_PAPER mode without
+ * fuse_small_levels is supported (else FMG_E_UNSUPPORTED).  Sizes: a
+ * workspace above FMG_NOALLOC_SCRATCH_BYTES returns FMG_E_SCRATCH with
+ * nothing enqueued (2D up to 1024^2 and 3D up to 64^3 fit, both precisions).
+ * Every call on a GPU uses that GPU's one buffer, which keeps the last call's
+ * contents: calls that overlap on one GPU (two streams, two threads) race and
+ * must be serialised by the caller. */
+#define FMG_NOALLOC_SCRATCH_BYTES (64u << 20)
+int fmg_solve_noalloc(const fmg_mesh_desc *mesh, const fmg_options *opts, const fmg_problem *prob,
+                      double *d_u_out, fmg_report *report, void *stream);
 
 /* Copy the report of the last solve to host memory (synchronises `stream`). */
 int fmg_get_report(fmg_hierarchy *h, fmg_report *host_report, void *stream);

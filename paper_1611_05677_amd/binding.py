@@ -24,7 +24,8 @@ LIB_PATH = os.environ.get("FMG_LIBRARY", os.path.join(HERE, "libfmg.so"))
 
 FMG_MAX_LEVELS = 16
 FMG_OK, FMG_E_INVALID, FMG_E_UNSUPPORTED, FMG_E_WORKSPACE, FMG_E_HIP, FMG_E_NOT_CONVERGED, \
-    FMG_E_NONFINITE = range(7)
+    FMG_E_NONFINITE, FMG_E_SCRATCH = range(8)
+FMG_NOALLOC_SCRATCH_BYTES = 64 << 20
 FMG_FP64, FMG_MIXED = 0, 1
 FMG_SMOOTHER_DEFAULT, FMG_JACOBI, FMG_CHEBYSHEV = 0, 1, 2
 FMG_PAPER, FMG_CONVERGED = 0, 1
@@ -32,7 +33,7 @@ FMG_OP_APPLY_A, FMG_OP_SMOOTH, FMG_OP_RESTRICT, FMG_OP_PROLONG, FMG_OP_COARSE = 
 
 EXPORTED = ("fmg_default_options", "fmg_workspace_bytes", "fmg_create_hierarchy", "fmg_solve",
             "fmg_get_report", "fmg_solve_batch", "fmg_destroy", "fmg_status_str", "fmg_level_op",
-            "fmg_profile_solve", "fmg_kernel_name", "fmg_time_level_kernel")
+            "fmg_profile_solve", "fmg_kernel_name", "fmg_time_level_kernel", "fmg_solve_noalloc")
 
 
 class MeshDesc(ctypes.Structure):
@@ -116,6 +117,8 @@ def _load():
     lib.fmg_time_level_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
                                           P(ctypes.c_double), P(ctypes.c_double)]
     lib.fmg_time_level_kernel.restype = ctypes.c_int
+    lib.fmg_solve_noalloc.argtypes = [P(MeshDesc), P(Options), P(ProblemC), vp, vp, vp]
+    lib.fmg_solve_noalloc.restype = ctypes.c_int
     return lib
 
 
@@ -257,6 +260,35 @@ def solve_batch(hs: list, gs: list, kinds: list, params: list, outs: list, strea
                          for g, k, p in zip(gs, kinds, params)])
     O = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
     _check(LIB.fmg_solve_batch(H, P, O, None, n, ctypes.c_void_p(_stream_ptr(stream))), "fmg_solve_batch")
+
+
+def solve_noalloc(dim: int, coarse_cells: int, refinements: int, g, kind: int, param: float = 0.0,
+                  opts: Options | None = None, out=None, report=None, stream=None):
+    """One solve through fmg_solve_noalloc (the library's static scratch as
+    workspace; no device allocation inside the call).  `out` (float64,
+    (n+1)^d) and `report` (a device uint8 tensor of sizeof(fmg_report) bytes)
+    are caller-owned and may be preallocated; returns `out`."""
+    import torch
+    nodes = (coarse_cells * 2 ** refinements + 1) ** dim
+    if out is None:
+        out = torch.empty(nodes, dtype=torch.float64, device=g.device)
+    if g.dtype != torch.float64 or not g.is_contiguous() or g.numel() != nodes:
+        raise ValueError("g must be a contiguous float64 tensor with (n+1)^d entries")
+    mesh = MeshDesc(dim, coarse_cells, refinements)
+    o = opts if opts is not None else default_options(dim)
+    prob = ProblemC(int(kind), float(param), ctypes.c_void_p(g.data_ptr()))
+    _check(LIB.fmg_solve_noalloc(ctypes.byref(mesh), ctypes.byref(o), ctypes.byref(prob),
+                                 ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(report.data_ptr() if report is not None else 0),
+                                 ctypes.c_void_p(_stream_ptr(stream))), "fmg_solve_noalloc")
+    return out
+
+
+def report_from_device(buf) -> dict:
+    """Decode an fmg_report written by the device into a uint8 tensor."""
+    raw = bytes(buf.cpu().numpy().tobytes())
+    r = Report.from_buffer_copy(raw[:ctypes.sizeof(Report)])
+    return r.as_dict()
 
 
 def kernel_id(name: str) -> int:

@@ -27,6 +27,17 @@ using namespace fmg;
 namespace {
 
 constexpr size_t kAlign = 256;
+
+// Static device scratch of fmg_solve_noalloc: the workspace of one solve, in
+// a file-scope array that every GPU the library runs on holds until the
+// process ends (host code never uses the array's name as an address: it
+// takes the device address from hipGetSymbolAddress, per device).
+constexpr size_t kScratchBytes = FMG_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_tail_attr_set = false;
 // Converged mode: a stop on a non-shrinking update counts as converged only
 // within this factor of the tolerance.
 constexpr double kStagnationFloor = 1e3;
@@ -100,7 +111,9 @@ int resolve(int dim, const fmg_options* in, Resolved& r) {
   return FMG_OK;
 }
 
-int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p) {
+// host_tables = false: no table that only the host can build (the dense
+// V-cycle tail operators); the tail then runs as a single-workgroup cycle.
+int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p, bool host_tables = true) {
   if (!mesh) return FMG_E_INVALID;
   const int d = mesh->dim;
   if (d != 2 && d != 3) return FMG_E_UNSUPPORTED;
@@ -159,7 +172,7 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p) {
   p.tail_dense = 0;
   if (p.tail_top >= 2) {
     const long long m = p.lev[p.tail_top].g.n - 1;
-    p.tail_dense = (d == 2 ? m * m : m * m * m) <= kDenseTailMax ? 1 : 0;
+    p.tail_dense = host_tables && (d == 2 ? m * m : m * m * m) <= kDenseTailMax ? 1 : 0;
   }
   for (int k = 0; k <= FMG_MAX_LEVELS; ++k) p.off_tailB[k] = 0;
   if (p.tail_dense)
@@ -794,6 +807,68 @@ void build_level1(const Plan& p, std::vector<double>& A, std::vector<double>& Ai
   }
 }
 
+// build_level1 on the device (one workgroup, N <= 64 threads): the same
+// matrix, the same Gauss-Jordan elimination with the same pivots, and
+// products rounded before the subtraction as on the host, so the tables are
+// the same bits; for launches that may not copy from host memory.  smem holds
+// 2 N^2 doubles (M, then the inverse being formed).
+__global__ void k_level1_tables(int d, int nH, double s, double* __restrict__ A, double* __restrict__ Ainv,
+                                float* __restrict__ Ainv_f) {
+  extern __shared__ double smem[];
+  const int m = nH - 1;
+  const int N = d == 2 ? m * m : m * m * m;
+  double* M = smem;
+  double* V = smem + N * N;
+  const int t = threadIdx.x;
+  if (t < N) {
+    const int i = t % m, j = (t / m) % m, l = d == 3 ? t / (m * m) : 0;
+    for (int c = 0; c < N; ++c) { M[t * N + c] = 0.0; V[t * N + c] = c == t ? 1.0 : 0.0; }
+    M[t * N + t] = 2.0 * d * s;
+    auto link = [&](int ii, int jj, int ll) {
+      if (ii < 0 || jj < 0 || ll < 0 || ii >= m || jj >= m || ll >= (d == 3 ? m : 1)) return;
+      M[t * N + (ii + m * jj + m * m * ll)] = -s;
+    };
+    link(i - 1, j, l); link(i + 1, j, l); link(i, j - 1, l); link(i, j + 1, l);
+    if (d == 3) { link(i, j, l - 1); link(i, j, l + 1); }
+    for (int c = 0; c < N; ++c) A[t * N + c] = M[t * N + c];
+  }
+  __syncthreads();
+  __shared__ int piv_s;
+  for (int c = 0; c < N; ++c) {
+    if (t == 0) {
+      int piv = c;
+      for (int r = c + 1; r < N; ++r)
+        if (fabs(M[r * N + c]) > fabs(M[piv * N + c])) piv = r;
+      piv_s = piv;
+    }
+    __syncthreads();
+    const int piv = piv_s;
+    if (piv != c && t < N) {   // thread t swaps column t of the two rows
+      double a = M[c * N + t]; M[c * N + t] = M[piv * N + t]; M[piv * N + t] = a;
+      a = V[c * N + t]; V[c * N + t] = V[piv * N + t]; V[piv * N + t] = a;
+    }
+    __syncthreads();
+    const double inv = 1.0 / M[c * N + c];
+    __syncthreads();
+    if (t < N) { M[c * N + t] = __dmul_rn(M[c * N + t], inv); V[c * N + t] = __dmul_rn(V[c * N + t], inv); }
+    __syncthreads();
+    if (t < N && t != c) {     // thread t updates row t (row c is only read)
+      const double f = M[t * N + c];
+      if (f != 0.0)
+        for (int k = 0; k < N; ++k) {
+          M[t * N + k] = M[t * N + k] - __dmul_rn(f, M[c * N + k]);
+          V[t * N + k] = V[t * N + k] - __dmul_rn(f, V[c * N + k]);
+        }
+    }
+    __syncthreads();
+  }
+  if (t < N)
+    for (int c = 0; c < N; ++c) {
+      Ainv[t * N + c] = V[t * N + c];
+      Ainv_f[t * N + c] = (float)V[t * N + c];
+    }
+}
+
 // The V-cycle of levels k..1 from a zero start is a linear map b_k -> x_k
 // (pre-smoothing, residual, P^T, exact level-1 solve, P-correction,
 // post-smoothing; the same steps and weights as the device cycle).  Its
@@ -910,6 +985,39 @@ void build_tail_operators(const Plan& p, const Resolved& ro, const std::vector<d
 }  // namespace
 
 namespace {
+
+// The LDS-resident V-cycle tail may use up to the whole 160 KB of a workgroup.
+hipError_t set_tail_lds_limit() {
+  const int lim = (int)kTailLdsMax;
+  const void* fns[4] = {reinterpret_cast<const void*>(&k_vcycle_tail_lds<2, double>),
+                        reinterpret_cast<const void*>(&k_vcycle_tail_lds<2, float>),
+                        reinterpret_cast<const void*>(&k_vcycle_tail_lds<3, double>),
+                        reinterpret_cast<const void*>(&k_vcycle_tail_lds<3, float>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Device address of the static scratch on the current device, taken once
+// per device with that device current.
+int scratch_on_current_device(char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FMG_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FMG_E_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  if (!g_tail_attr_set) {
+    if (set_tail_lds_limit() != hipSuccess) return FMG_E_HIP;
+    g_tail_attr_set = true;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[dev]);
+  return FMG_OK;
+}
 
 // Capture the solve for nonlinearity `kind` once (paper mode) and keep both the
 // graph and its executable form.
@@ -1072,22 +1180,10 @@ int fmg_create_hierarchy(const fmg_mesh_desc* mesh, const fmg_options* opts, voi
   for (auto& g : h->graph) g = nullptr;
   h->prof = nullptr;
   if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete h; return FMG_E_HIP; }
-  // the LDS-resident V-cycle tail may use up to the whole 160 KB of a workgroup
-  {
-    const int lim = (int)kTailLdsMax;
-    const hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vcycle_tail_lds<2, double>),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    const hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vcycle_tail_lds<2, float>),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    const hipError_t e3 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vcycle_tail_lds<3, double>),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    const hipError_t e4 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vcycle_tail_lds<3, float>),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
-      (void)hipStreamDestroy(h->cap_stream);
-      delete h;
-      return FMG_E_HIP;
-    }
+  if (set_tail_lds_limit() != hipSuccess) {
+    (void)hipStreamDestroy(h->cap_stream);
+    delete h;
+    return FMG_E_HIP;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   // zero every level array once: the Dirichlet rings stay zero for good
@@ -1227,6 +1323,42 @@ int fmg_solve(fmg_hierarchy* h, const fmg_problem* prob, double* d_u_out, fmg_re
     k_end_solve<<<1, 64, 0, s>>>(h->rep(), h->flag(), h->slot());
     if (hipStreamSynchronize(s) != hipSuccess) return FMG_E_HIP;
   }
+  return hipGetLastError() == hipSuccess ? FMG_OK : FMG_E_HIP;
+}
+
+int fmg_solve_noalloc(const fmg_mesh_desc* mesh, const fmg_options* opts, const fmg_problem* prob,
+                      double* d_u_out, fmg_report* report, void* stream) {
+  if (!mesh || !d_u_out) return FMG_E_INVALID;
+  int st = check_problem(prob);
+  if (st != FMG_OK) return st;
+  Resolved ro;
+  if ((st = resolve(mesh->dim, opts, ro)) != FMG_OK) return st;
+  if (ro.o.mode != FMG_PAPER || ro.o.fuse_small_levels) return FMG_E_UNSUPPORTED;
+  fmg_hierarchy h;   // on the stack: plan, options and the scratch as workspace
+  if ((st = make_plan(mesh, ro, h.plan, false)) != FMG_OK) return st;
+  if (h.plan.total > kScratchBytes) return FMG_E_SCRATCH;
+  char* ws = nullptr;
+  if ((st = scratch_on_current_device(&ws)) != FMG_OK) return st;
+  h.ro = ro;
+  h.ws = ws;
+  h.ws_bytes = kScratchBytes;
+  h.cap_stream = nullptr;
+  for (auto& g : h.graph) g = nullptr;
+  h.prof = nullptr;
+  const Plan& p = h.plan;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the previous call's contents: clear the level arrays (their Dirichlet
+  // rings must read zero) and the ticket counter that follows them, then
+  // form the level-1 tables on the device
+  const size_t words = (p.total - p.off_x[1]) / sizeof(double);
+  k_fill<double><<<1024, 256, 0, s>>>(h.at<double>(p.off_x[1]), words, 0.0);
+  k_level1_tables<<<1, 64, sizeof(double) * 2 * p.N1 * p.N1, s>>>(
+      p.dim, p.nH, p.lev[1].scale, h.at<double>(p.off_A1), h.at<double>(p.off_A1inv), h.at<float>(p.off_A1inv_f));
+  k_set_slot<<<1, 64, 0, s>>>(h.slot(), prob->g_nodes, d_u_out, report, prob->param, prob->kind);
+  record_fn rec = p.dim == 2 ? pick_record<2>(prob->kind) : pick_record<3>(prob->kind);
+  Roles R;
+  canonical_roles(&h, R);
+  rec(&h, R, true, s);
   return hipGetLastError() == hipSuccess ? FMG_OK : FMG_E_HIP;
 }
 
@@ -1378,6 +1510,7 @@ const char* fmg_status_str(int status) {
     case FMG_E_HIP: return "HIP runtime error";
     case FMG_E_NOT_CONVERGED: return "Newton iteration did not converge";
     case FMG_E_NONFINITE: return "non-finite value in the solution";
+    case FMG_E_SCRATCH: return "problem larger than the static scratch of fmg_solve_noalloc";
     default: return "unknown status";
   }
 }

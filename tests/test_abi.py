@@ -151,3 +151,27 @@ def test_library_binds_to_torchs_hip_runtime():
     maps = open("/proc/self/maps").read()
     runtimes = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
     assert len(runtimes) == 1, runtimes
+
+
+def test_noalloc_rejects_before_enqueueing():
+    """fmg_solve_noalloc validates on the host and returns before any HIP call:
+    invalid arguments, unsupported modes and problems larger than the static
+    scratch (FMG_NOALLOC_SCRATCH_BYTES) are refused synchronously."""
+    mesh = B.MeshDesc(2, 4, 9)                       # 2048^2: needs about 130 MiB
+    fake = ctypes.c_void_p(0x1000)                   # never dereferenced
+    prob = B.ProblemC(2, 0.0, fake)
+    o = B.default_options(2)
+    call = B.LIB.fmg_solve_noalloc
+    assert call(ctypes.byref(mesh), ctypes.byref(o), ctypes.byref(prob), fake, None, None) == B.FMG_E_SCRATCH
+    small = B.MeshDesc(2, 4, 3)
+    assert call(None, ctypes.byref(o), ctypes.byref(prob), fake, None, None) == B.FMG_E_INVALID
+    assert call(ctypes.byref(small), ctypes.byref(o), ctypes.byref(prob), None, None, None) == B.FMG_E_INVALID
+    conv = B.default_options(2, mode=B.FMG_CONVERGED)
+    assert call(ctypes.byref(small), ctypes.byref(conv), ctypes.byref(prob), fake, None, None) == \
+        B.FMG_E_UNSUPPORTED
+    fused = B.default_options(2, fuse_small_levels=1)
+    assert call(ctypes.byref(small), ctypes.byref(fused), ctypes.byref(prob), fake, None, None) == \
+        B.FMG_E_UNSUPPORTED
+    bad = B.ProblemC(99, 0.0, fake)
+    assert call(ctypes.byref(small), ctypes.byref(o), ctypes.byref(bad), fake, None, None) == B.FMG_E_INVALID
+    assert B.status_str(B.FMG_E_SCRATCH).startswith("problem larger than the static scratch")
