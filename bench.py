@@ -142,7 +142,7 @@ def profile_mode(B, H, P, g, torch):
 # dominant streaming kernel per dimension (the V-cycle level kernel that moves
 # the most bytes) and the source file that defines it
 ROOF_KERNEL = {2: ("pre_sweeps_restrict_2d_stream_f64", "fmg_kernels_stream2d.h"),
-               3: ("smooth_f64", "fmg_kernels_mg.h")}
+               3: ("pre_sweep_pair_3d_f64", "fmg_kernels_pair3d.h")}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 FLOPS_FILE = os.path.join(ROOT, "profiles", "pmc_flops.json")
 # the fine quadrature pass of the augmented problem (float64 ALU bound)
@@ -181,7 +181,8 @@ def roofline_live(B, H, dim, workload, reps, stream=None):
            "launches_timed": reps, "avg_launch_us": ms * 1e3, "bytes_per_launch": nbytes,
            "bytes_model": "each nodal array of the launch read or written once: "
                           + ("s(3N + N_c), N, N_c interior nodes of the level and of the next coarser"
-                             if dim == 2 else "3sN (read x, b; write x'), N interior nodes of the level"),
+                             if dim == 2 else "3sN (read x, b; write x2 after two sweeps), N interior nodes "
+                                              "of the level"),
            "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT) if traffic is not None else None}
     if dim == 2:
         # the 2048^2 working set (x, b, x', b_c: about 109 MB) stays in the 256 MB

@@ -126,8 +126,11 @@ typedef struct {
     int sweep_rows;     /* 2D V(2,2) levels: rows marched by each wavefront of
                            the register-streaming level kernels (4..4096);
                            0 = chosen per level; -1 = LDS-tiled kernels.
-                           3D: a positive value also selects the
-                           plane-marching sweep (else one node per thread) */
+                           3D V(2,2) levels with n >= 16: 0 = each sweep pair
+                           (pre-smoothing; correction + post-smoothing) in one
+                           plane-marching launch; -1 = one launch per sweep,
+                           one node per thread; > 0 = one plane-marching
+                           launch per sweep                                  */
 } fmg_options;
 
 typedef struct {
@@ -245,8 +248,9 @@ int fmg_level_op(fmg_hierarchy *h, int op, int level, int precision,
  * `kernel` is a kernel class as reported by fmg_profile_solve and named by
  * fmg_kernel_name; supported: the fused 2D V(2,2) level kernels
  * ("pre_sweeps_restrict_2d*", "prolong_post_sweeps_2d*", whichever variant
- * the hierarchy's options select), the 3D plane-marching sweep
- * ("smooth_3d_stream_f64/f32") and the separate sweep
+ * the hierarchy's options select), the fused 3D sweep pairs
+ * ("pre_sweep_pair_3d_f64/f32", "prolong_sweep_pair_3d_f64/f32"), the 3D
+ * plane-marching sweep ("smooth_3d_stream_f64/f32") and the separate sweep
  * ("smooth_f64/f32"), residual-restriction and prolongation-correction
  * kernels, in float64 or (mixed-mode hierarchies) float32.  The kernel is
  * launched with the solve's launch shape on level `level` (2..levels) of the

@@ -20,6 +20,7 @@
 #include "fmg_kernels_fused2d.h"
 #include "fmg_kernels_stream2d.h"
 #include "fmg_kernels_stream3d.h"
+#include "fmg_kernels_pair3d.h"
 #include "fmg_launch.h"
 
 using namespace fmg;
@@ -235,7 +236,8 @@ enum KernelClass {
   KC_TRANSITION, KC_RHS, KC_RESID_F32, KC_ADD_F32, KC_AUG_PASS0, KC_AUG_PASS, KC_OUTPUT_UPDATE,
   KC_NEWTON_FINISH, KC_AUG_UPDATE, KC_LEVEL1, KC_BEGIN, KC_OUTPUT, KC_END, KC_FILL,
   KC_VCYCLE_TAIL64, KC_VCYCLE_TAIL32, KC_FMG_TAIL, KC_AUG_SMALL, KC_PRE2D64, KC_POST2D64, KC_PRE2D32, KC_POST2D32,
-  KC_PRE2S64, KC_POST2S64, KC_PRE2S32, KC_POST2S32, KC_SMOOTH3S64, KC_SMOOTH3S32, KC_COUNT
+  KC_PRE2S64, KC_POST2S64, KC_PRE2S32, KC_POST2S32, KC_SMOOTH3S64, KC_SMOOTH3S32,
+  KC_PRE3P64, KC_POST3P64, KC_PRE3P32, KC_POST3P32, KC_COUNT
 };
 const char* const kKernelNames[KC_COUNT] = {
   "smooth_f64", "smooth_f64_from_zero", "resid_restrict_f64", "prolong_add_f64", "coarse_solve_f64",
@@ -246,7 +248,8 @@ const char* const kKernelNames[KC_COUNT] = {
   "pre_sweeps_restrict_2d_f32", "prolong_post_sweeps_2d_f32",
   "pre_sweeps_restrict_2d_stream_f64", "prolong_post_sweeps_2d_stream_f64",
   "pre_sweeps_restrict_2d_stream_f32", "prolong_post_sweeps_2d_stream_f32",
-  "smooth_3d_stream_f64", "smooth_3d_stream_f32"};
+  "smooth_3d_stream_f64", "smooth_3d_stream_f32",
+  "pre_sweep_pair_3d_f64", "prolong_sweep_pair_3d_f64", "pre_sweep_pair_3d_f32", "prolong_sweep_pair_3d_f32"};
 
 // Event pairs around launches (fmg_profile_solve only).
 struct Prof {
@@ -389,6 +392,52 @@ double launch_post2(const fmg_hierarchy* h, int k, const T* x, const T* xc, cons
   return bytes;
 }
 
+// 3D V(2,2) levels: the two pre-smoothing sweeps in one launch (from x, or
+// from zero), and the coarse correction with the two post-smoothing sweeps in
+// one launch (fmg_kernels_pair3d.h).  Used unless sweep_rows asks for the
+// one-sweep kernels (-1: one node per thread; > 0: plane marching).
+inline bool use_pair3(const fmg_hierarchy* h, int k) {
+  const fmg_options& o = h->ro.o;
+  return h->plan.dim == 3 && o.nu_pre == 2 && o.nu_post == 2 && o.sweep_rows == 0 &&
+         h->plan.lev[k].g.n >= 16 && k > h->plan.tail_top;
+}
+
+template <typename T>
+double launch_pre3(const fmg_hierarchy* h, int k, const T* x, const T* b, T* t, bool zero_init, hipStream_t st) {
+  const LevelInfo& L = h->plan.lev[k];
+  const long long N = interior(L.g, 3);
+  const double bytes = sizeof(T) * (zero_init ? 2.0 : 3.0) * N;
+  const double D = 6.0 * L.scale;
+  const T wd1 = (T)(h->ro.pre[0] / D), wd2 = (T)(h->ro.pre[1] / D), scale = (T)L.scale;
+  const Pair3Shape sh = pair3_shape(L.g.n);
+  const int kc = Sel<T>::kc ? (KC_PRE3P32 - KC_PRE3P64) : 0;
+  if (zero_init)
+    FMG_LAUNCH(h, st, KC_PRE3P64 + kc, k, N, bytes,
+               (k_sweep_pair3<T, true, false><<<pair3_blocks(sh), kP3Threads, 0, st>>>(
+                   L.g, L.g, x, x, b, t, wd1, wd2, scale, sh.nsx, sh.ncy, sh.nzc, sh.zc_planes)));
+  else
+    FMG_LAUNCH(h, st, KC_PRE3P64 + kc, k, N, bytes,
+               (k_sweep_pair3<T, false, false><<<pair3_blocks(sh), kP3Threads, 0, st>>>(
+                   L.g, L.g, x, x, b, t, wd1, wd2, scale, sh.nsx, sh.ncy, sh.nzc, sh.zc_planes)));
+  return bytes;
+}
+
+template <typename T>
+double launch_post3(const fmg_hierarchy* h, int k, const T* x, const T* xc, const T* b, T* t, hipStream_t st) {
+  const LevelInfo& L = h->plan.lev[k];
+  const LevelInfo& C = h->plan.lev[k - 1];
+  const long long N = interior(L.g, 3), Nc = interior(C.g, 3);
+  const double bytes = sizeof(T) * (3.0 * N + Nc);
+  const double D = 6.0 * L.scale;
+  const T wd1 = (T)(h->ro.post[0] / D), wd2 = (T)(h->ro.post[1] / D), scale = (T)L.scale;
+  const Pair3Shape sh = pair3_shape(L.g.n);
+  const int kc = Sel<T>::kc ? (KC_PRE3P32 - KC_PRE3P64) : 0;
+  FMG_LAUNCH(h, st, KC_POST3P64 + kc, k, N, bytes,
+             (k_sweep_pair3<T, false, true><<<pair3_blocks(sh), kP3Threads, 0, st>>>(
+                 L.g, C.g, x, xc, b, t, wd1, wd2, scale, sh.nsx, sh.ncy, sh.nzc, sh.zc_planes)));
+  return bytes;
+}
+
 // One weighted-Jacobi sweep t = x + wd (b - A x) on level k: the grid kernel,
 // or in 3D on request (positive sweep_rows) the plane-marching kernel.
 template <int DIM, typename T>
@@ -468,6 +517,21 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
     std::swap(x, t);
     vcycle<DIM, T>(h, R, k - 1, true, st);
     launch_post2<T>(h, k, x, Sel<T>::x(R, k - 1), b, t, st);
+    std::swap(x, t);
+    return;
+  }
+  if (DIM == 3 && use_pair3(h, k)) {
+    // two sweeps, residual + restriction, coarse cycle, correction + two sweeps
+    // (each pair writes the spare array: one role swap)
+    launch_pre3<T>(h, k, x, b, t, zero_init, st);
+    std::swap(x, t);
+    const LevelInfo& C = p.lev[k - 1];
+    const long long Nc = interior(C.g, DIM);
+    FMG_LAUNCH(h, st, KC_RESTRICT64 + kc, k, N, s * (2 * N + Nc),
+               k_resid_restrict<DIM, T><<<grid_of(C.g, DIM), kBlock, 0, st>>>(L.g, C.g, x, b, Sel<T>::b(h, k - 1),
+                                                                             scale));
+    vcycle<DIM, T>(h, R, k - 1, true, st);
+    launch_post3<T>(h, k, x, Sel<T>::x(R, k - 1), b, t, st);
     std::swap(x, t);
     return;
   }
@@ -1623,6 +1687,14 @@ int time_launch(fmg_hierarchy* h, int base, int k, hipStream_t st, double& bytes
       if (DIM != 2 || (base == KC_POST2S64) != (rows > 0)) return FMG_E_UNSUPPORTED;
       bytes = launch_post2<T>(h, k, x, Sel<T>::x(R, k - 1), b, t, st);
       return FMG_OK;
+    case KC_PRE3P64:
+      if (DIM != 3 || !use_pair3(h, k)) return FMG_E_UNSUPPORTED;
+      bytes = launch_pre3<T>(h, k, x, b, t, false, st);
+      return FMG_OK;
+    case KC_POST3P64:
+      if (DIM != 3 || !use_pair3(h, k)) return FMG_E_UNSUPPORTED;
+      bytes = launch_post3<T>(h, k, x, Sel<T>::x(R, k - 1), b, t, st);
+      return FMG_OK;
     case KC_SMOOTH64:
       bytes = 3 * s * N;
       k_smooth<DIM, T, false><<<grid_of(L.g, DIM), kBlock, 0, st>>>(L.g, x, b, t, (T)(h->ro.pre[0] / D), scale);
@@ -1652,7 +1724,11 @@ int time_launch_any(fmg_hierarchy* h, int kernel, int k, hipStream_t st, double&
   switch (kernel) {
     case KC_SMOOTH64: case KC_RESTRICT64: case KC_PROLONG64_ADD:
     case KC_PRE2D64: case KC_POST2D64: case KC_PRE2S64: case KC_POST2S64: case KC_SMOOTH3S64:
+    case KC_PRE3P64: case KC_POST3P64:
       return time_launch<DIM, double>(h, kernel, k, st, bytes);
+    case KC_PRE3P32: case KC_POST3P32:
+      if (!h->plan.off_xs[k]) return FMG_E_UNSUPPORTED;
+      return time_launch<DIM, float>(h, kernel - (KC_PRE3P32 - KC_PRE3P64), k, st, bytes);
     case KC_SMOOTH3S32:
       if (!h->plan.off_xs[k]) return FMG_E_UNSUPPORTED;
       return time_launch<DIM, float>(h, KC_SMOOTH3S64, k, st, bytes);

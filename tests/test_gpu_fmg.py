@@ -292,6 +292,31 @@ def test_plane_marching_3d_sweep_matches_grid_sweep(precision):
         assert rel(u_s, expect) <= PARITY
 
 
+@pytest.mark.parametrize("precision", [B.FMG_FP64, B.FMG_MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("P", [W.cube_u_plus_sin(2), W.cube_u_plus_sin(3), W.cube_u_plus_sin(5),
+                               W.fourier_problem("pair_nH3", 3, 3, 4, W.F_CUBIC, [8, 1]),
+                               W.fourier_problem("pair_jac", 3, 4, 4, W.F_ABS_U_U, [8, 2])],
+                         ids=["n16", "n32", "n128", "nH3_n48", "n64"])
+def test_fused_3d_sweep_pairs_match_separate_sweeps(P, precision):
+    """3D V(2,2) levels with the two pre-smoothing sweeps in one launch and the
+    coarse correction plus the two post-smoothing sweeps in one launch (tiles
+    of 60 x 12 owned nodes, plane chunks, ragged last strips, rows and chunks)
+    against one launch per sweep and per correction: to float64 rounding (the
+    same expressions in the same order), or to float32 rounding of the mixed
+    mode's corrections; and against the oracle's replica in float64."""
+    opts = dict(precision=precision, tail_max_nodes=0)
+    if P.name == "pair_jac":
+        opts["smoother"] = B.FMG_JACOBI
+    u_p, r1 = gpu_solve(P, **opts)
+    u_s, r2 = gpu_solve(P, sweep_rows=-1, **opts)
+    assert r1["status"] == 0 and r2["status"] == 0
+    assert rel(u_p, u_s) <= (1e-13 if precision == B.FMG_FP64 else 1e-9), rel(u_p, u_s)
+    if precision == B.FMG_FP64:
+        o2opt = O2Options(smoother=1) if P.name == "pair_jac" else O2Options()
+        expect = o2_fmg(o2_hier(P), P.g_nodes, Nonlinearity(P.f_kind, P.f_param), o2opt).full()
+        assert rel(u_p, expect) <= PARITY
+
+
 def test_paper_examples_converge_at_the_optimal_rate():
     """The paper's 3D Examples 1-3 through the same path: nodal L2 errors
     against the exact solution fall by about 4 per refinement (O(h^2)) for
