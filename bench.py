@@ -413,7 +413,7 @@ def roofline_leg(args, B, torch, factory, depth):
     print(json.dumps({"roofline": roof, "copy_bytes_each_way": 8 * n, "copies": 3}), flush=True)
 
 
-def measure_workload(args, B, W, torch, key, profile=True):
+def measure_workload(args, B, W, torch, key, profile=True, only=None):
     """Float64 and mixed solves of one configuration: throughput, latency,
     accuracy gate, per-kernel profile; returns (record, hierarchies, problem)."""
     desc, factory, depth, gkey = WORKLOADS[key]
@@ -424,6 +424,8 @@ def measure_workload(args, B, W, torch, key, profile=True):
     uc, conv_info = converged_solution(B, torch, P, g, golden)
     modes, hier = {}, {}
     for name, prec in (("fp64", B.FMG_FP64), ("mixed", B.FMG_MIXED)):
+        if only and name != only:
+            continue
         H, res = run_mode(B, torch, P, g, prec, args.steps, args.warmup, golden, uc)
         modes[name] = res
         hier[name] = H
@@ -431,7 +433,7 @@ def measure_workload(args, B, W, torch, key, profile=True):
             f"p50 {res['latency_ms_p50']:.3f} ms p99 {res['latency_ms_p99']:.3f} ms, "
             f"alg/disc {res['alg_over_disc']:.3f}, gate {res['gate_pass']}")
     if profile:
-        for name in ("fp64", "mixed"):
+        for name in modes:
             total_ms, rows = profile_mode(B, hier[name], P, g, torch)
             by_kernel = roofline_from_profile(rows)
             modes[name]["profile_event_ms_total"] = total_ms
@@ -439,9 +441,11 @@ def measure_workload(args, B, W, torch, key, profile=True):
             modes[name]["profile_ms_by_kernel"] = {k: round(v, 4) for k, v in
                                                    sorted(by_kernel.items(), key=lambda kv: -kv[1])}
     rec = {"workload": desc, "dofs": P.interior_dofs, "levels": P.n_levels,
-           "dof_per_s_fp64": modes["fp64"]["dof_per_s"], "dof_per_s_mixed": modes["mixed"]["dof_per_s"],
-           "mixed_speedup_vs_fp64": modes["mixed"]["dof_per_s"] / modes["fp64"]["dof_per_s"],
            "converged_reference": conv_info, "modes": modes}
+    for name in modes:
+        rec[f"dof_per_s_{name}"] = modes[name]["dof_per_s"]
+    if len(modes) == 2:
+        rec["mixed_speedup_vs_fp64"] = modes["mixed"]["dof_per_s"] / modes["fp64"]["dof_per_s"]
     return rec, hier, P
 
 
@@ -521,6 +525,8 @@ def main():
     ap.add_argument("--roof-reps", type=int, default=200, help="launches timed for the roofline kernel")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the roofline leg (dominant kernel + a reference copy), for counter runs")
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
+                    help="time one precision only (for traces and counter runs); no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver runs on a single "
@@ -544,6 +550,13 @@ def main():
     desc, factory, depth, gkey = WORKLOADS[args.workload]
     if args.roofline_only:
         roofline_leg(args, B, torch, factory, depth)
+        return
+    if args.only:
+        rec, hier, P = measure_workload(args, B, W, torch, args.workload, profile=not args.no_profile,
+                                        only=args.only)
+        for H in hier.values():
+            H.close()
+        log(json.dumps({k: v for k, v in rec.items() if k != "modes"}))
         return
     rec, hier, P = measure_workload(args, B, W, torch, args.workload, profile=not args.no_profile)
     modes = rec["modes"]
