@@ -520,7 +520,7 @@ def main():
     ap.add_argument("--workload", default="cube256",
                     choices=sorted(WORKLOADS) + ["batch64", "serve", "examples"])
     ap.add_argument("--max-depth", type=int, default=6, help="examples: deepest refinement")
-    ap.add_argument("--requests", type=int, default=1200, help="serve: requests in the trace")
+    ap.add_argument("--requests", type=int, default=4000, help="serve: requests in the trace")
     ap.add_argument("--inflight", type=int, default=8, help="serve: concurrent solves")
     ap.add_argument("--roof-reps", type=int, default=200, help="launches timed for the roofline kernel")
     ap.add_argument("--roofline-only", action="store_true",

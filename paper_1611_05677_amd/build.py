@@ -17,6 +17,12 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmg.so")
+# the same library with AddressSanitizer and UndefinedBehaviorSanitizer on the
+# host code (planner, launch sequence, C ABI); device code is built as usual.
+# For CPU runs of the ABI tests: preload the ASan runtime (asan_runtime()).
+LIB_HOSTSAN = os.path.join(HERE, "libfmg_hostsan.so")
+HOSTSAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
 SOURCES = ["fmg.hip", "fmg_kind_2d_a.hip", "fmg_kind_2d_b.hip", "fmg_kind_3d_a.hip", "fmg_kind_3d_b.hip"]
 ARCH = os.environ.get("FMG_OFFLOAD_ARCH", "gfx950")
 
@@ -35,14 +41,27 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+def asan_runtime() -> str:
+    """Path of the shared ASan runtime of the ROCm clang (to LD_PRELOAD)."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "lib", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/lib/llvm/bin/clang"
+    out = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return out.stdout.strip()
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    return build(verbose, lib=LIB_HOSTSAN, extra=HOSTSAN_FLAGS)
+
+
+def build(verbose: bool = False, jobs: int | None = None, lib: str = LIB, extra=()) -> str:
     cc = hipcc()
     jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1))
     with tempfile.TemporaryDirectory(prefix="fmg_build_") as tmpdir:
         objs, pending = [], []
         for src in SOURCES:
             obj = os.path.join(tmpdir, os.path.splitext(src)[0] + ".o")
-            cmd = [cc, *HIPCC_FLAGS, "-c", "-o", obj, os.path.join(CSRC, src)]
+            cmd = [cc, *HIPCC_FLAGS, *extra, "-c", "-o", obj, os.path.join(CSRC, src)]
             if verbose:
                 print(" ".join(cmd), flush=True)
             objs.append(obj)
@@ -62,16 +81,16 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
             for cmd, out in failed:
                 sys.stderr.write(" ".join(cmd) + "\n" + out)
             raise RuntimeError("hipcc failed building libfmg.so")
-        tmp = LIB + ".tmp"
-        link = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        tmp = lib + ".tmp"
+        link = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra, "-o", tmp, *objs]
         if verbose:
             print(" ".join(link), flush=True)
         res = subprocess.run(link, capture_output=True, text=True)
         if res.returncode != 0:
             sys.stderr.write(res.stdout + res.stderr)
             raise RuntimeError("linking libfmg.so failed")
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

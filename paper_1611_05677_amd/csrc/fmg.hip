@@ -402,23 +402,39 @@ inline bool use_pair3(const fmg_hierarchy* h, int k) {
          h->plan.lev[k].g.n >= 16 && k > h->plan.tail_top;
 }
 
+Pair3Args pair3_args(const fmg_hierarchy* h, int k, const double* w) {
+  const LevelInfo& L = h->plan.lev[k];
+  const Pair3Shape sh = pair3_shape(L.g.n);
+  Pair3Args a;
+  std::memset(&a, 0, sizeof(a));
+  a.g = L.g;
+  a.cg = k > 1 ? h->plan.lev[k - 1].g : L.g;
+  const double D = 6.0 * L.scale;
+  a.wd1 = w[0] / D;
+  a.wd2 = w[1] / D;
+  a.scale = L.scale;
+  a.nsx = sh.nsx; a.ncy = sh.ncy; a.nzc = sh.nzc; a.zc_planes = sh.zc_planes;
+  return a;
+}
+
+template <typename T, int MODE>
+void launch_pair3_kernel(const Pair3Args& a, hipStream_t st) {
+  const Pair3Shape sh{a.nsx, a.ncy, a.nzc, a.zc_planes};
+  k_sweep_pair3<T, MODE><<<pair3_blocks(sh), kP3Threads, 0, st>>>(a);
+}
+
 template <typename T>
 double launch_pre3(const fmg_hierarchy* h, int k, const T* x, const T* b, T* t, bool zero_init, hipStream_t st) {
   const LevelInfo& L = h->plan.lev[k];
   const long long N = interior(L.g, 3);
   const double bytes = sizeof(T) * (zero_init ? 2.0 : 3.0) * N;
-  const double D = 6.0 * L.scale;
-  const T wd1 = (T)(h->ro.pre[0] / D), wd2 = (T)(h->ro.pre[1] / D), scale = (T)L.scale;
-  const Pair3Shape sh = pair3_shape(L.g.n);
+  Pair3Args a = pair3_args(h, k, h->ro.pre);
+  a.x = x; a.b = b; a.out = t;
   const int kc = Sel<T>::kc ? (KC_PRE3P32 - KC_PRE3P64) : 0;
   if (zero_init)
-    FMG_LAUNCH(h, st, KC_PRE3P64 + kc, k, N, bytes,
-               (k_sweep_pair3<T, true, false><<<pair3_blocks(sh), kP3Threads, 0, st>>>(
-                   L.g, L.g, x, x, b, t, wd1, wd2, scale, sh.nsx, sh.ncy, sh.nzc, sh.zc_planes)));
+    FMG_LAUNCH(h, st, KC_PRE3P64 + kc, k, N, bytes, (launch_pair3_kernel<T, kP3Zero>(a, st)));
   else
-    FMG_LAUNCH(h, st, KC_PRE3P64 + kc, k, N, bytes,
-               (k_sweep_pair3<T, false, false><<<pair3_blocks(sh), kP3Threads, 0, st>>>(
-                   L.g, L.g, x, x, b, t, wd1, wd2, scale, sh.nsx, sh.ncy, sh.nzc, sh.zc_planes)));
+    FMG_LAUNCH(h, st, KC_PRE3P64 + kc, k, N, bytes, (launch_pair3_kernel<T, kP3Plain>(a, st)));
   return bytes;
 }
 
@@ -428,13 +444,10 @@ double launch_post3(const fmg_hierarchy* h, int k, const T* x, const T* xc, cons
   const LevelInfo& C = h->plan.lev[k - 1];
   const long long N = interior(L.g, 3), Nc = interior(C.g, 3);
   const double bytes = sizeof(T) * (3.0 * N + Nc);
-  const double D = 6.0 * L.scale;
-  const T wd1 = (T)(h->ro.post[0] / D), wd2 = (T)(h->ro.post[1] / D), scale = (T)L.scale;
-  const Pair3Shape sh = pair3_shape(L.g.n);
+  Pair3Args a = pair3_args(h, k, h->ro.post);
+  a.x = x; a.xc = xc; a.b = b; a.out = t;
   const int kc = Sel<T>::kc ? (KC_PRE3P32 - KC_PRE3P64) : 0;
-  FMG_LAUNCH(h, st, KC_POST3P64 + kc, k, N, bytes,
-             (k_sweep_pair3<T, false, true><<<pair3_blocks(sh), kP3Threads, 0, st>>>(
-                 L.g, C.g, x, xc, b, t, wd1, wd2, scale, sh.nsx, sh.ncy, sh.nzc, sh.zc_planes)));
+  FMG_LAUNCH(h, st, KC_POST3P64 + kc, k, N, bytes, (launch_pair3_kernel<T, kP3Prolong>(a, st)));
   return bytes;
 }
 
@@ -587,6 +600,28 @@ template <int DIM>
 bool mixed_cycle_fused(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st) {
   const Plan& p = h->plan;
   const fmg_options& o = h->ro.o;
+  if (DIM == 3 && use_pair3(h, k)) {
+    // float64 residual inside the first float32 sweep pair, the float32
+    // cycle, and the correction added to the float64 iterate inside the last
+    const LevelInfo& L = p.lev[k];
+    const LevelInfo& C = p.lev[k - 1];
+    const long long N = interior(L.g, 3), Nc = interior(C.g, 3);
+    float* r32 = h->at<float>(p.off_bs[k]);
+    Pair3Args a = pair3_args(h, k, h->ro.pre);
+    a.x = R.x[k]; a.b = h->at<double>(p.off_b[k]); a.out = R.ts[k]; a.r32 = r32;
+    FMG_LAUNCH(h, st, KC_PRE3P32, k, N, 16.0 * N + 8.0 * N, (launch_pair3_kernel<float, kP3Resid>(a, st)));
+    std::swap(R.xs[k], R.ts[k]);
+    FMG_LAUNCH(h, st, KC_RESTRICT32, k, N, 4.0 * (2 * N + Nc),
+               k_resid_restrict<3, float><<<grid_of(C.g, 3), kBlock, 0, st>>>(L.g, C.g, R.xs[k], r32,
+                                                                            h->at<float>(p.off_bs[k - 1]),
+                                                                            (float)L.scale));
+    vcycle<DIM, float>(h, R, k - 1, true, st);
+    Pair3Args q = pair3_args(h, k, h->ro.post);
+    q.x = R.xs[k]; q.xc = R.xs[k - 1]; q.b = r32; q.u64 = R.x[k];
+    FMG_LAUNCH(h, st, KC_POST3P32, k, N, 4.0 * (2 * N + Nc) + 16.0 * N,
+               (launch_pair3_kernel<float, kP3ProlongAdd>(q, st)));
+    return true;
+  }
   if (DIM != 2 || o.nu_pre != 2 || o.nu_post != 2 || k <= p.tail_top || k < 2) return false;
   const LevelInfo& L = p.lev[k];
   const LevelInfo& C = p.lev[k - 1];

@@ -121,3 +121,90 @@ def test_served_requests_wait_for_memory():
     assert srv.max_concurrent == 1
     assert srv.pool.stats.peak_bytes <= budget and srv.pool.stats.created == 1
     srv.close()
+
+
+def test_poisoned_member_of_a_batch_leaves_the_others_unchanged():
+    """One problem of a batch has a non-finite load: its report says so, and
+    every other member's result is bitwise its result solved alone."""
+    probs = [W.fourier_problem(f"p{i}", P.dim, 4, P.refinements, P.f_kind, [11, i]) for i, P in enumerate(BATCH)]
+    bad = 2
+    probs[bad].g_nodes = probs[bad].g_nodes.copy()
+    probs[bad].g_nodes[len(probs[bad].g_nodes) // 2] = np.nan
+    hs = [B.Hierarchy(P.dim, 4, P.refinements, B.default_options(P.dim, precision=B.FMG_MIXED), device=DEV)
+          for P in probs]
+    gs = [torch.from_numpy(P.g_nodes).to(DEV) for P in probs]
+    outs = [torch.empty(h.nodes(), dtype=torch.float64, device=DEV) for h in hs]
+    B.solve_batch(hs, gs, [P.f_kind for P in probs], [0.0] * len(probs), outs)
+    torch.cuda.synchronize()
+    for i, (h, o, P) in enumerate(zip(hs, outs, probs)):
+        rep = h.report()
+        if i == bad:
+            assert rep["status"] in (B.FMG_E_NONFINITE, B.FMG_E_NOT_CONVERGED), rep
+        else:
+            assert rep["status"] == 0
+            assert torch.equal(o, alone(P, B.FMG_MIXED)[0]), i
+    for h in hs:
+        h.close()
+
+
+def test_poisoned_request_in_the_served_mix_leaves_the_others_unchanged():
+    """A served request whose load is not finite completes with a non-finite
+    status; the requests around it (same shapes, overlapping on the device)
+    are bitwise the same as alone."""
+    trace = W.serving_trace(count=16, rate_hz=4000.0, depths2d=(3, 6), depths3d=(2, 3))
+    reqs = S.requests_from_trace(trace)
+    bad = 5
+    reqs[bad].coef = reqs[bad].coef.copy()
+    reqs[bad].coef[0, 0] = np.nan
+    ex = S.DeviceExecutor(B.FMG_MIXED, DEV, max_inflight=4)
+    srv = S.Server(ex, budget_bytes=2 << 30, max_inflight=4, keep_results=True)
+    out = srv.run(reqs)
+    torch.cuda.synchronize()
+    for r in out:
+        if r.rid == bad:
+            assert r.status in (B.FMG_E_NONFINITE, B.FMG_E_NOT_CONVERGED), r.status
+            continue
+        assert r.status == 0
+        g = W.fourier_load_device(r.coef, 4 * 2 ** r.refinements, DEV)
+        H = B.Hierarchy(r.dim, 4, r.refinements, B.default_options(r.dim, precision=B.FMG_MIXED), device=DEV)
+        u, rep = H.solve(g, r.f_kind)
+        H.close()
+        assert torch.equal(u, r.result), r.rid
+    srv.close()
+
+
+@pytest.mark.parametrize("dim,depth,kind", [(2, 7, W.F_ABS_U_U), (3, 4, W.F_U_PLUS_SIN)], ids=["2d_512", "3d_64"])
+def test_served_results_at_serving_depths_meet_the_gate(dim, depth, kind):
+    """Requests at the served workload's depths (random-Fourier loads, mixed
+    precision) against the oracle: the served result is within 5 % of the
+    float64 algebraic error of the oracle's replica, and its algebraic error
+    is at most half the discretisation error, estimated with no exact
+    solution by Richardson extrapolation from the oracle's converged
+    solutions on this level and the next coarser one (O(h^2))."""
+    coef = W.fourier_coefficients(dim, 16, [161105678, 9000 + dim])
+    req = S.ServedRequest(0, 0.0, dim, depth, kind, 0.0, coef)
+    ex = S.DeviceExecutor(B.FMG_MIXED, DEV, max_inflight=2)
+    srv = S.Server(ex, budget_bytes=4 << 30, max_inflight=2, keep_results=True)
+    (r,) = srv.run([req])
+    torch.cuda.synchronize()
+    assert r.status == 0
+    u = r.result.cpu().numpy()
+    srv.close()
+    n = 4 * 2 ** depth
+    g = W.fourier_load_nodes(coef, n)
+    nl = Nonlinearity(kind)
+    Hf = O2H(dim, 4, depth)
+    paper = o2_fmg(Hf, g, nl).full()
+    ubar = o2_fmg(Hf, g, nl, converged=True).full()
+    gc = W.fourier_load_nodes(coef, n // 2)
+    ubar_c = o2_fmg(O2H(dim, 4, depth - 1), gc, nl, converged=True).full()
+    h = 1.0 / n
+    nodal = lambda v: float(np.sqrt(h ** dim * np.sum(v * v)))
+    inject = ubar.reshape((n + 1,) * dim)[tuple(slice(None, None, 2) for _ in range(dim))].ravel()
+    # in the coarse nodal norm (weights (2h)^d), ||ubar_h - ubar_2h|| at the
+    # shared nodes ~ |e_2h - e_h| = 3 ||e_h|| for an O(h^2) error e
+    disc = nodal(inject - ubar_c) * (2.0 ** dim) ** 0.5 / 3.0
+    alg64 = nodal(paper - ubar)
+    alg = nodal(u - ubar)
+    assert nodal(u - paper) <= 0.05 * alg64, (nodal(u - paper), alg64)
+    assert alg <= 0.5 * disc, (alg, disc)
