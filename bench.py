@@ -288,7 +288,7 @@ def cpu_baseline(P, W):
 
 BATCH_DESC = ("batched: 64 independent 2D unit-square problems, depths U{6..10} (seeded), f = u^3, "
               "g = random Fourier series (16x16 modes, N(0,1)/(1+|k|^2)), mixed precision, one graph launch")
-SERVE_DESC = ("serving: Poisson arrivals (seeded, 200 req/s) mixing 2D (depths 7-10) and 3D (coarse 4^3 refined "
+SERVE_DESC = ("serving: Poisson arrivals (seeded; 200 req/s unless --rate says otherwise) mixing 2D (depths 7-10) and 3D (coarse 4^3 refined "
               "3-6 times), f in {u^3, u+sin u, |u|u}, random-Fourier g, resident hierarchies, admission by "
               "device-memory footprint (64 GB), mixed precision")
 
@@ -362,7 +362,7 @@ def serve_mode(args, B, W, torch):
     from paper_1611_05677_amd import serving as S
     count = args.requests
     warm = min(200, count // 5)
-    trace = W.serving_trace(count=count)
+    trace = W.serving_trace(count=count, rate_hz=args.rate)
     reqs = S.requests_from_trace(trace)
     ex = S.DeviceExecutor(B.FMG_MIXED, "cuda:0", max_inflight=args.inflight)
     srv = S.Server(ex, budget_bytes=64 << 30, max_inflight=args.inflight)
@@ -388,7 +388,7 @@ def serve_mode(args, B, W, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
         "data": "synthetic",
         "config": {"workload": SERVE_DESC, "requests": count, "measured_after": warm,
-                   "max_inflight": args.inflight},
+                   "max_inflight": args.inflight, "rate_hz": args.rate},
         "latency_ms_p50": summ["latency_ms_p50"], "latency_ms_p99": summ["latency_ms_p99"],
         "latency_ms_mean": summ["latency_ms_mean"], "solves_per_s": summ["solves_per_s"],
         "all_status_ok": summ["ok"] == summ["requests"], "max_concurrent": srv.max_concurrent,
@@ -522,6 +522,7 @@ def main():
     ap.add_argument("--max-depth", type=int, default=6, help="examples: deepest refinement")
     ap.add_argument("--requests", type=int, default=4000, help="serve: requests in the trace")
     ap.add_argument("--inflight", type=int, default=8, help="serve: concurrent solves")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrival rate (requests/s)")
     ap.add_argument("--roof-reps", type=int, default=200, help="launches timed for the roofline kernel")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the roofline leg (dominant kernel + a reference copy), for counter runs")

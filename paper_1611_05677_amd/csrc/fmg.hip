@@ -590,14 +590,19 @@ inline size_t fmg_tail_lds_bytes(const Plan& p) {
   return std::max(aug, lev1) * sizeof(double);
 }
 
-// Mixed mode, one float32 V(2,2) cycle on the correction equation at a 2D
-// level that uses the streaming kernels: the float64 residual is formed inside
-// the pre-smoothing kernel and the correction is added to the float64 iterate
-// inside the post-smoothing kernel (same operations as the separate residual
-// and add kernels, two launches and two passes over the level fewer).
+// Mixed mode: the m V-cycles of a correction step run in float32 on the
+// correction equation A e = r, r = b - A u formed once in float64 from the
+// step's iterate u, and u += e once after the last cycle (u + V^m(0, r) equals
+// m cycles from u in exact arithmetic: the cycle is affine in its start).
+// Here one float32 V(2,2) cycle of that sequence at a level that uses the
+// fused level kernels (2D streaming, 3D sweep pairs): the first cycle forms
+// the float64 residual inside its pre-smoothing kernel, the last adds e to the
+// float64 iterate inside its post-smoothing kernel (the separate residual and
+// add kernels' operations, two launches and two passes over the level fewer);
+// the cycles between run from the current e with r as right-hand side.
 // Returns false where this does not apply.
 template <int DIM>
-bool mixed_cycle_fused(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st) {
+bool mixed_cycle_fused(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bool first, bool last) {
   const Plan& p = h->plan;
   const fmg_options& o = h->ro.o;
   if (DIM == 3 && use_pair3(h, k)) {
@@ -607,19 +612,28 @@ bool mixed_cycle_fused(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st) 
     const LevelInfo& C = p.lev[k - 1];
     const long long N = interior(L.g, 3), Nc = interior(C.g, 3);
     float* r32 = h->at<float>(p.off_bs[k]);
-    Pair3Args a = pair3_args(h, k, h->ro.pre);
-    a.x = R.x[k]; a.b = h->at<double>(p.off_b[k]); a.out = R.ts[k]; a.r32 = r32;
-    FMG_LAUNCH(h, st, KC_PRE3P32, k, N, 16.0 * N + 8.0 * N, (launch_pair3_kernel<float, kP3Resid>(a, st)));
+    if (first) {
+      Pair3Args a = pair3_args(h, k, h->ro.pre);
+      a.x = R.x[k]; a.b = h->at<double>(p.off_b[k]); a.out = R.ts[k]; a.r32 = r32;
+      FMG_LAUNCH(h, st, KC_PRE3P32, k, N, 16.0 * N + 8.0 * N, (launch_pair3_kernel<float, kP3Resid>(a, st)));
+    } else {
+      launch_pre3<float>(h, k, R.xs[k], r32, R.ts[k], false, st);
+    }
     std::swap(R.xs[k], R.ts[k]);
     FMG_LAUNCH(h, st, KC_RESTRICT32, k, N, 4.0 * (2 * N + Nc),
                k_resid_restrict<3, float><<<grid_of(C.g, 3), kBlock, 0, st>>>(L.g, C.g, R.xs[k], r32,
                                                                             h->at<float>(p.off_bs[k - 1]),
                                                                             (float)L.scale));
     vcycle<DIM, float>(h, R, k - 1, true, st);
-    Pair3Args q = pair3_args(h, k, h->ro.post);
-    q.x = R.xs[k]; q.xc = R.xs[k - 1]; q.b = r32; q.u64 = R.x[k];
-    FMG_LAUNCH(h, st, KC_POST3P32, k, N, 4.0 * (2 * N + Nc) + 16.0 * N,
-               (launch_pair3_kernel<float, kP3ProlongAdd>(q, st)));
+    if (last) {
+      Pair3Args q = pair3_args(h, k, h->ro.post);
+      q.x = R.xs[k]; q.xc = R.xs[k - 1]; q.b = r32; q.u64 = R.x[k];
+      FMG_LAUNCH(h, st, KC_POST3P32, k, N, 4.0 * (2 * N + Nc) + 16.0 * N,
+                 (launch_pair3_kernel<float, kP3ProlongAdd>(q, st)));
+    } else {
+      launch_post3<float>(h, k, R.xs[k], R.xs[k - 1], r32, R.ts[k], st);
+      std::swap(R.xs[k], R.ts[k]);
+    }
     return true;
   }
   if (DIM != 2 || o.nu_pre != 2 || o.nu_post != 2 || k <= p.tail_top || k < 2) return false;
@@ -633,18 +647,27 @@ bool mixed_cycle_fused(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st) 
   const double* b64 = h->at<double>(p.off_b[k]);
   float* r32 = h->at<float>(p.off_bs[k]);
   int nch = 0;
-  const int gpre = stream_blocks(L.g.n, kResStrip, rows, nch);
-  FMG_LAUNCH(h, st, KC_PRE2S32, k, N, 16.0 * N + 8.0 * N + 4.0 * Nc,
-             k_pre2s_resid<<<gpre, 64 * kStreamWaves, 0, st>>>(
-                 L.g, C.g, u, b64, r32, R.ts[k], h->at<float>(p.off_bs[k - 1]), (float)(h->ro.pre[0] / D),
-                 (float)(h->ro.pre[1] / D), (float)L.scale, L.scale, rows, nch));
+  if (first) {
+    const int gpre = stream_blocks(L.g.n, kResStrip, rows, nch);
+    FMG_LAUNCH(h, st, KC_PRE2S32, k, N, 16.0 * N + 8.0 * N + 4.0 * Nc,
+               k_pre2s_resid<<<gpre, 64 * kStreamWaves, 0, st>>>(
+                   L.g, C.g, u, b64, r32, R.ts[k], h->at<float>(p.off_bs[k - 1]), (float)(h->ro.pre[0] / D),
+                   (float)(h->ro.pre[1] / D), (float)L.scale, L.scale, rows, nch));
+  } else {
+    launch_pre2<float>(h, k, R.xs[k], r32, R.ts[k], h->at<float>(p.off_bs[k - 1]), false, st);
+  }
   std::swap(R.xs[k], R.ts[k]);
   vcycle<DIM, float>(h, R, k - 1, true, st);
-  const int gpost = stream_blocks(L.g.n, kPostStrip, rows, nch);
-  FMG_LAUNCH(h, st, KC_POST2S32, k, N, 8.0 * N + 16.0 * N + 4.0 * Nc,
-             k_post2s<float, true><<<gpost, 64 * kStreamWaves, 0, st>>>(
-                 C.g, L.g, R.xs[k], R.xs[k - 1], r32, nullptr, u, (float)(h->ro.post[0] / D),
-                 (float)(h->ro.post[1] / D), (float)L.scale, rows, nch));
+  if (last) {
+    const int gpost = stream_blocks(L.g.n, kPostStrip, rows, nch);
+    FMG_LAUNCH(h, st, KC_POST2S32, k, N, 8.0 * N + 16.0 * N + 4.0 * Nc,
+               k_post2s<float, true><<<gpost, 64 * kStreamWaves, 0, st>>>(
+                   C.g, L.g, R.xs[k], R.xs[k - 1], r32, nullptr, u, (float)(h->ro.post[0] / D),
+                   (float)(h->ro.post[1] / D), (float)L.scale, rows, nch));
+  } else {
+    launch_post2<float>(h, k, R.xs[k], R.xs[k - 1], r32, R.ts[k], st);
+    std::swap(R.xs[k], R.ts[k]);
+  }
   return true;
 }
 
@@ -690,14 +713,17 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   for (int c = 0; c < o.m_vcycles; ++c) {
     if (o.precision == FMG_FP64) {
       vcycle<DIM, double>(h, R, k, false, st);
-    } else if (!mixed_cycle_fused<DIM>(h, R, k, st)) {
-      // float32 cycle on the correction equation, float64 residual and update
-      FMG_LAUNCH(h, st, KC_RESID_F32, k, N, 20.0 * N,
-                 k_resid_to_f32<DIM><<<grid, kBlock, 0, st>>>(L.g, R.x[k], b, h->at<float>(p.off_bs[k]),
-                                                              L.scale));
-      vcycle<DIM, float>(h, R, k, true, st);
-      FMG_LAUNCH(h, st, KC_ADD_F32, k, N, 20.0 * N,
-                 k_add_f32<DIM><<<grid, kBlock, 0, st>>>(L.g, R.x[k], R.xs[k]));
+    } else if (!mixed_cycle_fused<DIM>(h, R, k, st, c == 0, c == o.m_vcycles - 1)) {
+      // float32 cycles on the correction equation: float64 residual before the
+      // first, float64 update after the last
+      if (c == 0)
+        FMG_LAUNCH(h, st, KC_RESID_F32, k, N, 20.0 * N,
+                   k_resid_to_f32<DIM><<<grid, kBlock, 0, st>>>(L.g, R.x[k], b, h->at<float>(p.off_bs[k]),
+                                                                L.scale));
+      vcycle<DIM, float>(h, R, k, c == 0, st);
+      if (c == o.m_vcycles - 1)
+        FMG_LAUNCH(h, st, KC_ADD_F32, k, N, 20.0 * N,
+                   k_add_f32<DIM><<<grid, kBlock, 0, st>>>(L.g, R.x[k], R.xs[k]));
     }
   }
   // step 2: semilinear problem on V_H + span{u~}

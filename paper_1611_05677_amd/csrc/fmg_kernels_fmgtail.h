@@ -170,9 +170,11 @@ __global__ void __launch_bounds__(kTailThreads) k_fmg_tail(const FmgTailParams* 
         if (!MIXED) {
           vcycle_tail_dev<DIM, double>(V, x64, t64, k, false);
         } else {
-          blk_resid_to_f32<DIM>(V.g[k], x64[k], V.b[k], P->v32.b[k], V.scale[k]);
-          vcycle_tail_dev<DIM, float>(P->v32, x32, t32, k, true);
-          blk_add_f32<DIM>(V.g[k], x64[k], x32[k]);
+          // float32 cycles on the correction equation: the float64 residual
+          // before the first, the float64 update after the last
+          if (c == 0) blk_resid_to_f32<DIM>(V.g[k], x64[k], V.b[k], P->v32.b[k], V.scale[k]);
+          vcycle_tail_dev<DIM, float>(P->v32, x32, t32, k, c == 0);
+          if (c == P->m_vcycles - 1) blk_add_f32<DIM>(V.g[k], x64[k], x32[k]);
         }
       }
       aug_solve_dev<DIM, KIND>(V.g[k], P->aug[k], x64[k], P->slot, P->nf1, fs, V.scale[k], P->m[k], P->A1, P->ns,

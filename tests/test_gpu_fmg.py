@@ -29,6 +29,13 @@ from paper_1611_05677_amd import workloads as W  # noqa: E402
 
 DEV = "cuda:0"
 PARITY = 1e-10
+# Two mixed-precision code paths (or mixed precision against the float64
+# oracle) differ by float32 rounding of the corrections: a step's m float32
+# cycles accumulate their correction in float32 before the one float64 update,
+# so results agree to about 1e-7 of the corrections, far below the algebraic
+# error (the bar that decides mixed mode: the discretisation gate, and its
+# difference to the float64 path below 5 % of that path's algebraic error).
+MIXED_TOL = 1e-8
 
 _O2 = {}
 
@@ -220,7 +227,7 @@ def test_fused_small_levels_match_replica(P, precision):
     u, rep = gpu_solve(P, precision=precision, fuse_small_levels=1)
     assert rep["status"] == 0
     u_ref, _ = gpu_solve(P, precision=precision)
-    assert rel(u, u_ref) <= (1e-12 if precision == B.FMG_FP64 else 1e-9)
+    assert rel(u, u_ref) <= (1e-12 if precision == B.FMG_FP64 else MIXED_TOL)
     if precision == B.FMG_FP64:
         expect = o2_fmg(o2_hier(P), P.g_nodes, Nonlinearity(P.f_kind, P.f_param)).full()
         assert rel(u, expect) <= PARITY
@@ -236,7 +243,7 @@ def test_tail_kernel_matches_grid_launches(P, precision):
     u_tail, r1 = gpu_solve(P, precision=precision)
     u_grid, r2 = gpu_solve(P, precision=precision, tail_max_nodes=0)
     assert r1["status"] == 0 and r2["status"] == 0
-    assert rel(u_tail, u_grid) <= (1e-13 if precision == B.FMG_FP64 else 1e-9)
+    assert rel(u_tail, u_grid) <= (1e-13 if precision == B.FMG_FP64 else MIXED_TOL)
 
 
 @pytest.mark.parametrize("blocks", [64, 16384])
@@ -261,7 +268,7 @@ def test_streaming_level_kernels_match_lds_tiles(precision, rows):
     u_s, r1 = gpu_solve(P, precision=precision, sweep_rows=rows, tail_max_nodes=0)
     u_t, r2 = gpu_solve(P, precision=precision, sweep_rows=-1, tail_max_nodes=0)
     assert r1["status"] == 0 and r2["status"] == 0
-    assert rel(u_s, u_t) <= (1e-13 if precision == B.FMG_FP64 else 1e-9)
+    assert rel(u_s, u_t) <= (1e-13 if precision == B.FMG_FP64 else MIXED_TOL)
     if precision == B.FMG_FP64 and rows == 12:
         expect = o2_fmg(o2_hier(P), P.g_nodes, Nonlinearity(P.f_kind, P.f_param)).full()
         assert rel(u_s, expect) <= PARITY
@@ -286,7 +293,7 @@ def test_plane_marching_3d_sweep_matches_grid_sweep(precision):
     u_s, r1 = gpu_solve(P, precision=precision, tail_max_nodes=0, sweep_rows=8)
     u_g, r2 = gpu_solve(P, precision=precision, tail_max_nodes=0, sweep_rows=-1)
     assert r1["status"] == 0 and r2["status"] == 0
-    assert rel(u_s, u_g) <= (1e-13 if precision == B.FMG_FP64 else 1e-9)
+    assert rel(u_s, u_g) <= (1e-13 if precision == B.FMG_FP64 else MIXED_TOL)
     if precision == B.FMG_FP64:
         expect = o2_fmg(o2_hier(P), P.g_nodes, Nonlinearity(P.f_kind, P.f_param)).full()
         assert rel(u_s, expect) <= PARITY
@@ -310,7 +317,7 @@ def test_fused_3d_sweep_pairs_match_separate_sweeps(P, precision):
     u_p, r1 = gpu_solve(P, **opts)
     u_s, r2 = gpu_solve(P, sweep_rows=-1, **opts)
     assert r1["status"] == 0 and r2["status"] == 0
-    assert rel(u_p, u_s) <= (1e-13 if precision == B.FMG_FP64 else 1e-9), rel(u_p, u_s)
+    assert rel(u_p, u_s) <= (1e-13 if precision == B.FMG_FP64 else MIXED_TOL), rel(u_p, u_s)
     if precision == B.FMG_FP64:
         o2opt = O2Options(smoother=1) if P.name == "pair_jac" else O2Options()
         expect = o2_fmg(o2_hier(P), P.g_nodes, Nonlinearity(P.f_kind, P.f_param), o2opt).full()
@@ -376,8 +383,8 @@ def test_full_size_matches_stored_oracle(name, factory, precision):
     configuration (default options, one captured graph), the solve reproduces
     the oracle's stored values (tests/golden/fmg_reference.json, written from
     the oracle alone):
-      * 2048 seeded nodes and the full-vector norm to 1e-10 in float64 (1e-9
-        in mixed mode, whose float32 cycles perturb the last bits);
+      * 2048 seeded nodes and the full-vector norm to 1e-10 in float64
+        (MIXED_TOL in mixed mode, whose float32 cycles perturb the last bits);
       * 16 random linear functionals of the whole vector: their root mean
         square difference (an estimate of the L2 norm of the difference over
         every node) to the same tolerance relative to the norm;
@@ -395,7 +402,8 @@ def test_full_size_matches_stored_oracle(name, factory, precision):
     u, rep = gpu_solve(P, precision=precision)
     assert rep["status"] == 0
     idx = np.asarray(G["sample_idx"], dtype=np.int64)
-    tol = PARITY if precision == B.FMG_FP64 else 1e-9
+    tol = PARITY if precision == B.FMG_FP64 else MIXED_TOL
+    print(f"{name} precision={precision}: samples {rel(u[idx], np.asarray(G['paper_sample'])):.2e}", flush=True)
     assert rel(u[idx], np.asarray(G["paper_sample"])) <= tol
     assert abs(np.linalg.norm(u) / G["paper_norm2"] - 1.0) <= tol
     assert sketch_rms(u, G["paper_sketch"]) <= tol * G["paper_norm2"]
@@ -433,7 +441,8 @@ def test_full_vector_2048_against_live_oracle(precision):
     u, rep = gpu_solve(P, precision=precision)
     assert rep["status"] == 0
     expect = _LIVE["u"]
-    tol = PARITY if precision == B.FMG_FP64 else 1e-9
+    tol = PARITY if precision == B.FMG_FP64 else MIXED_TOL
+    print(f"2048^2 precision={precision}: {rel(u, expect):.2e}", flush=True)
     assert rel(u, expect) <= tol, rel(u, expect)
     inner = np.ones(u.size, dtype=bool).reshape(P.n + 1, P.n + 1)
     inner[[0, -1], :] = False

@@ -1,6 +1,6 @@
 """fmg_solve_noalloc (the entry point for callers that cannot allocate) against
 the hierarchy entry points (fmg_create_hierarchy + fmg_solve) on the same
-inputs: float64 to 1e-10 relative L2 and mixed precision to 1e-9 (the two
+inputs: float64 to 1e-10 relative L2 and mixed precision to 1e-8 (the two
 paths run the small levels' V-cycle as a dense operator and as a recursive
 single-workgroup cycle, equal up to rounding), on consecutive calls where the
 second is smaller than the first (the static scratch keeps the previous
@@ -57,7 +57,7 @@ SEQUENCES = [
 
 @pytest.mark.parametrize("name,problems,precision", SEQUENCES, ids=[s[0] for s in SEQUENCES])
 def test_noalloc_matches_hierarchy_path_on_consecutive_calls(name, problems, precision):
-    tol = 1e-10 if precision == B.FMG_FP64 else 1e-9
+    tol = 1e-10 if precision == B.FMG_FP64 else 1e-8
     first = problems[0]
     assert problems[1].interior_dofs < first.interior_dofs or problems[1].dim != first.dim
     for P in problems:
