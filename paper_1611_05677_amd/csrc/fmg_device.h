@@ -214,6 +214,17 @@ __device__ __forceinline__ double fast_rsqrt(double d) {
   return y;
 }
 
+// 1 / d for d != 0: the hardware estimate refined by two Newton steps
+// (e <- 1 - d y, y <- y + y e), full double accuracy in a short dependent chain.
+__device__ __forceinline__ double fast_rcp(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-d, y, 1.0);
+  y = fma(y, e, y);
+  return y;
+}
+
 // Maximum over the 64 lanes (inputs >= 0), returned to every lane.
 __device__ __forceinline__ double wave_max_nonneg(double v) {
   v = fmax(v, dpp_move<0xb1>(v));

@@ -533,33 +533,64 @@ __device__ __forceinline__ void newton_core(const AugShape& s, const double* cs,
   wave_copy(nsg, ns);
 }
 
+// Partial-sum units per thread kept in flight by the last block of a pass.
+template <int DIM>
+__host__ __device__ constexpr int sum_units() { return DIM == 2 ? 4 : 12; }
+
 // Reduce the per-block partials of one pass into per-cell sums: every
 // (cell, accumulator) item is split into segments of consecutive blocks so
 // that all threads take part; segment sums are combined in a fixed order.
+// The partials were written by blocks on other XCDs, so each load is a trip
+// to the memory side: a thread keeps the loads of kSumUnits items (two
+// blocks' partials of each) in flight at once instead of one at a time;
+// kSumUnits is smaller where the block's register budget is (1024 threads).
 // tmp: LDS of at least blockDim doubles.
-template <int NACC>
+template <int NACC, int kSumUnits>
 __device__ __forceinline__ void cell_sums_from_partials(const double* __restrict__ partials, int ncell, int bpc,
-                                               double* cs, double* tmp) {
+                                                        double* cs, double* tmp) {
   const int W = ncell * NACC;
   const int S = max(1, min(bpc, (int)blockDim.x / W));
   const int seg = (bpc + S - 1) / S;
-  for (int idx = threadIdx.x; idx < W * S; idx += blockDim.x) {
-    const int item = idx % W, sg = idx / W;
-    const int cell = item / NACC, q = item % NACC;
-    const int b0 = sg * seg, b1 = min(bpc, b0 + seg);
-    const double* p = partials + ((size_t)cell * bpc) * NACC + q;
-    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-    int b = b0;
-    for (; b + 3 < b1; b += 4) {
-      t0 += p[(size_t)b * NACC];
-      t1 += p[(size_t)(b + 1) * NACC];
-      t2 += p[(size_t)(b + 2) * NACC];
-      t3 += p[(size_t)(b + 3) * NACC];
+  const int U = W * S;
+  for (int u0 = threadIdx.x; u0 < U; u0 += kSumUnits * blockDim.x) {
+    const double* p[kSumUnits];
+    int n[kSumUnits];
+    double t0[kSumUnits], t1[kSumUnits];
+#pragma unroll
+    for (int k = 0; k < kSumUnits; ++k) {
+      const int u = u0 + k * blockDim.x;
+      const int uc = u < U ? u : 0;
+      const int item = uc % W, sg = uc / W;
+      const int b0 = sg * seg;
+      n[k] = u < U ? max(0, min(bpc, b0 + seg) - b0) : 0;
+      p[k] = partials + ((size_t)(item / NACC) * bpc + min(b0, bpc - 1)) * NACC + item % NACC;
+      t0[k] = 0.0;
+      t1[k] = 0.0;
     }
-    for (; b < b1; ++b) t0 += p[(size_t)b * NACC];
-    const double t = (t0 + t1) + (t2 + t3);
-    if (S == 1) cs[item] = t;
-    else tmp[sg * W + item] = t;
+    for (int b = 0; b < seg; b += 2) {
+      double x0[kSumUnits], x1[kSumUnits];
+#pragma unroll
+      for (int k = 0; k < kSumUnits; ++k) {
+        x0[k] = b < n[k] ? p[k][(size_t)b * NACC] : 0.0;
+        x1[k] = b + 1 < n[k] ? p[k][(size_t)(b + 1) * NACC] : 0.0;
+      }
+      // every load is issued before the first add waits for one
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < kSumUnits; ++k) {
+        t0[k] += x0[k];
+        t1[k] += x1[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kSumUnits; ++k) {
+      const int u = u0 + k * blockDim.x;
+      if (u < U) {
+        const int item = u % W, sg = u / W;
+        if (S == 1) cs[item] = t0[k] + t1[k];
+        else tmp[sg * W + item] = t0[k] + t1[k];
+      }
+    }
   }
   __syncthreads();
   if (S > 1) {
@@ -572,35 +603,39 @@ __device__ __forceinline__ void cell_sums_from_partials(const double* __restrict
   }
 }
 
-// Fold per-cell setup sums into Q^T A u~, u~^T A u~, Q^T M g, u~^T M g.
+// Fold per-cell setup sums into Q^T A u~, u~^T A u~, Q^T M g, u~^T M g: each
+// coarse node gathers the 2^d cells that touch it (vertex e of cell A - e),
+// in ascending e; the two scalars are sums over the cells by one wavefront.
 template <int DIM>
 __device__ __forceinline__ void setup_scatter(const AugShape& s, const double* cs, double m, NewtonState* ns) {
   using AC = Acc<DIM>;
-  const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
-  for (int a = threadIdx.x; a < s.N1; a += blockDim.x) { ns->bH[a] = 0.0; ns->GH[a] = 0.0; }
-  __syncthreads();
-  for (int colour = 0; colour < (1 << DIM); ++colour) {
-    for (int idx = threadIdx.x; idx < ncell * AC::NV; idx += blockDim.x) {
-      const int cell = idx / AC::NV, a = idx % AC::NV;
-      int cx, cy, cz;
-      cell_of<DIM>(cell, s.nH, cx, cy, cz);
-      const int col = (cx & 1) | ((cy & 1) << 1) | (DIM == 3 ? (cz & 1) << 2 : 0);
-      if (col != colour) continue;
-      const int A = coarse_vertex<DIM>(s.nH, cx, cy, cz, a);
-      if (A < 0) continue;
-      ns->bH[A] += cs[cell * AC::NS + AC::S_BH + a];
-      ns->GH[A] += m * cs[cell * AC::NS + AC::S_GH + a];
+  const int nH = s.nH;
+  const int ncell = DIM == 2 ? nH * nH : nH * nH * nH;
+  for (int A = threadIdx.x; A < s.N1; A += blockDim.x) {
+    int ax, ay, az;
+    coarse_coords<DIM>(nH, A, ax, ay, az);
+    double bh = 0.0, gh = 0.0;
+#pragma unroll
+    for (int e = 0; e < AC::NV; ++e) {
+      const int cx = ax - (e & 1), cy = ay - ((e >> 1) & 1), cz = DIM == 3 ? az - ((e >> 2) & 1) : 0;
+      const double* cc = cs + (cx + nH * (cy + nH * cz)) * AC::NS;
+      bh += cc[AC::S_BH + e];
+      gh += cc[AC::S_GH + e];
     }
-    __syncthreads();
+    ns->bH[A] = bh;
+    ns->GH[A] = m * gh;
   }
-  if (threadIdx.x == 0) {
-    double c = 0.0, gu = 0.0;
-    for (int cell = 0; cell < ncell; ++cell) {
-      c += cs[cell * AC::NS + AC::S_C];
-      gu += cs[cell * AC::NS + AC::S_GU];
+  if (threadIdx.x < 64) {
+    double v[2] = {0.0, 0.0};
+    for (int cell = threadIdx.x; cell < ncell; cell += 64) {
+      v[0] += cs[cell * AC::NS + AC::S_C];
+      v[1] += cs[cell * AC::NS + AC::S_GU];
     }
-    ns->c = c;
-    ns->Gu = m * gu;
+    wave_sum_n<2>(v);
+    if (threadIdx.x == 0) {
+      ns->c = v[0];
+      ns->Gu = m * v[1];
+    }
   }
   __syncthreads();
 }
@@ -610,7 +645,7 @@ __device__ __forceinline__ void setup_reduce(const AugShape& s, const double* __
                                     NewtonState* ns, double* cs, double* tmp) {
   using AC = Acc<DIM>;
   const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
-  cell_sums_from_partials<AC::NS>(partials_s, ncell, 1 << s.bpc_log, cs, tmp);
+  cell_sums_from_partials<AC::NS, sum_units<DIM>()>(partials_s, ncell, 1 << s.bpc_log, cs, tmp);
   setup_scatter<DIM>(s, cs, m, ns);
 }
 
@@ -699,7 +734,7 @@ __global__ void __launch_bounds__(aug_threads<DIM>()) k_aug_pass(Grid g, AugShap
     if (threadIdx.x == 0) newton_state_reset(ns, s.N1, level);
     setup_reduce<DIM>(s, ps, m, ns, cs, tmp);
   }
-  cell_sums_from_partials<AC::NQ>(pq, ncell, bpc, cs, tmp);
+  cell_sums_from_partials<AC::NQ, sum_units<DIM>()>(pq, ncell, bpc, cs, tmp);
   newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   if (FINISH) {
     // last pass of the launch sequence: this block completes the Newton solve

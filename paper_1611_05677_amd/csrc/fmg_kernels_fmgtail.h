@@ -117,13 +117,19 @@ __device__ __forceinline__ void aug_solve_dev(const Grid& g, const AugShape& s, 
   __syncthreads();
 }
 
+// Threads of the single-workgroup augmented solve: 512, so that the per-node
+// accumulators and the Newton step get the registers that a 1024-thread block
+// (128 per thread) would make them spill.
+template <int DIM>
+__host__ __device__ constexpr int aug_small_threads() { return 512; }
+
 // The augmented problem of one correction step on a small level, solved by
 // one workgroup in one launch (setup sums, every Newton iteration, and the
 // update unless the caller defers it).
 // With fold, the block then also performs the transition into the next
 // (small) level, reading (w, alpha) from LDS.
 template <int DIM, int KIND>
-__global__ void __launch_bounds__(kTailThreads) k_aug_solve_small(Grid g, AugShape s, double* __restrict__ ut,
+__global__ void __launch_bounds__(aug_small_threads<DIM>()) k_aug_solve_small(Grid g, AugShape s, double* __restrict__ ut,
                                                                   const ProblemSlot* __restrict__ slot, int nf1,
                                                                   int fs, double scale, double m,
                                                                   const double* __restrict__ A1, NewtonState* ns,

@@ -17,7 +17,7 @@ template <int DIM, int KIND>
 void launch_aug_small(size_t lds, hipStream_t st, Grid g, AugShape s, double* ut, const ProblemSlot* slot,
                       int nf1, int fs, double scale, double m, const double* A1, NewtonState* ns, fmg_report* rep,
                       int level, int newton_max, double tol, int do_update, int fold, TransitionArgs next) {
-  k_aug_solve_small<DIM, KIND><<<1, kTailThreads, lds, st>>>(g, s, ut, slot, nf1, fs, scale, m, A1, ns, rep, level,
+  k_aug_solve_small<DIM, KIND><<<1, aug_small_threads<DIM>(), lds, st>>>(g, s, ut, slot, nf1, fs, scale, m, A1, ns, rep, level,
                                                              newton_max, tol, do_update, fold, next);
 }
 

@@ -2,8 +2,8 @@
 // side (N_1 = 9 unknowns in 2D, 27 in 3D), executed by one wavefront.  Lane A
 // owns coarse unknown A (and lane N_1 the coefficient alpha of u~): its row
 // of the Newton matrix lives in registers, A_1 w comes from the coarse
-// stencil through lane shuffles, the Cholesky factorisation broadcasts
-// columns with shuffles, and one LDS transpose serves the backward solve.
+// stencil through lane shuffles, and Gauss-Jordan elimination broadcasts the
+// pivot row with lane reads, so no backward substitution is needed.
 // Same damping, stopping and degenerate-direction rules as newton_core.
 #pragma once
 
@@ -26,55 +26,41 @@ __device__ __forceinline__ double stencil_shfl(double v, int A, int ax, int ay, 
   return node ? s1 * (2.0 * DIM * v - nb) : 0.0;
 }
 
-// Cholesky of the NY x NY matrix whose row `lane` is jr[] (lower part used),
-// steps k = 0..NY-2, with the forward substitution L y = b carried along: v
-// holds b_lane on entry; on exit lanes 0..NY-2 hold y_lane and lane NY-1 holds
-// b minus the contributions of y_0..y_{NY-2} (not yet divided by its pivot).
-// jr returns the factor rows and myrd the reciprocal of the lane's pivot; the
-// Schur complement of the last row is left in lane NY-1's jr[NY-1] (not
-// square-rooted).  Entries above the diagonal are updated too (it keeps the
-// updates free of lane masks) and are never read.
+// Gauss-Jordan elimination without pivoting of the symmetric positive definite
+// NY x NY system J x = b whose row `lane` is jr[] (full rows; lanes >= NY
+// hold zero rows) and whose right-hand side entry `lane` is v.  Steps
+// k = 0..NY-2 eliminate column k from every other row (rows above the pivot
+// too, so no backward substitution follows); all pivots are positive, being
+// those of the Cholesky factorisation squared.  On exit lane i < NY-1 holds
+// its pivot in piv and, in jr[NY-1], its remaining coupling to the last
+// unknown; the return value, in every lane, is the last pivot: the Schur
+// complement of the leading (NY-1) x (NY-1) block.  gj_finish then gives x.
 template <int NY>
-__device__ __forceinline__ void chol_fwd_reg(double (&jr)[NY], double& myrd, double& v) {
+__device__ __forceinline__ double gj_elim_reg(double (&jr)[NY], double& piv, double& v) {
   const int lane = threadIdx.x;
 #pragma unroll
   for (int k = 0; k < NY - 1; ++k) {
-    const double dkk = lane_value(jr[k], k);
-    const double rk = fast_rsqrt(dkk);
-    const double lik = lane > k ? jr[k] * rk : 0.0;
-    const double yk = lane_value(v, k) * rk;
-    if (lane == k) { jr[k] = dkk * rk; myrd = rk; }
-    else if (lane > k) jr[k] = lik;
-    v = lane == k ? yk : v - lik * yk;
+    const double pk = lane_value(jr[k], k);
+    const double f = lane == k ? 0.0 : jr[k] * fast_rcp(pk);
+    if (lane == k) piv = pk;
+    v -= f * lane_value(v, k);
 #pragma unroll
-    for (int j = k + 1; j < NY; ++j) jr[j] -= lik * lane_value(lik, j);
+    for (int j = k + 1; j < NY; ++j) jr[j] -= f * lane_value(jr[j], k);
   }
+  const double schur = lane_value(jr[NY - 1], NY - 1);
+  if (lane == NY - 1) piv = schur;
+  return schur;
 }
 
-// Backward substitution L^T x = y for the leading nn unknowns (v holds y_lane
-// on entry and x_lane on exit; 0 for lanes >= nn).  Lt: LDS scratch of NY*NY
-// doubles for the transpose.
+// Solution entry of lane `lane` after gj_elim_reg: the last unknown is
+// v_last / schur, or 0 when keep_last is false (the other entries then solve
+// the leading (NY-1) x (NY-1) system alone); 0 for lanes >= NY.
 template <int NY>
-__device__ __forceinline__ double chol_bwd_reg(const double (&jr)[NY], double myrd, int nn, double v,
-                                               double* __restrict__ Lt) {
+__device__ __forceinline__ double gj_finish(const double (&jr)[NY], double piv, double v, bool keep_last) {
   const int lane = threadIdx.x;
-#pragma unroll
-  for (int j = 0; j < NY; ++j)
-    if (lane < NY && j <= lane) Lt[lane * NY + j] = jr[j];
-  wave_sync();
-  double colr[NY];
-#pragma unroll
-  for (int j = 0; j < NY; ++j) colr[j] = (lane < NY && j > lane) ? Lt[j * NY + lane] : 0.0;
-#pragma unroll
-  for (int j = NY - 1; j >= 0; --j) {
-    if (j < nn) {
-      if (lane == j) v *= myrd;
-      const double xj = lane_value(v, j);
-      if (lane < j) v -= colr[j] * xj;
-    }
-  }
-  wave_sync();
-  return lane < nn ? v : 0.0;
+  const double xl = keep_last ? lane_value(v, NY - 1) / lane_value(piv, NY - 1) : 0.0;
+  if (lane == NY - 1) return xl;
+  return lane < NY ? (v - jr[NY - 1] * xl) / piv : 0.0;
 }
 
 // Pair index of cell vertices (a, b), a subset of b, as a constant expression.
@@ -90,7 +76,7 @@ __host__ __device__ constexpr int pair_of(int a, int b) {
   return -1;
 }
 
-// Newton step (see newton_core) with the state in registers.  LDS: J (NY*NY).
+// Newton step (see newton_core) with the state in registers.  LDS: J ((NY + 1) rows of NY | 1).
 template <int DIM, int NY>
 __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double* cs, double m, NewtonState* nsg,
                                                 fmg_report* rep, int newton_max, double tol, double* sm) {
@@ -104,6 +90,7 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
   const double s1 = DIM == 2 ? 1.0 : 1.0 / nH;
   const bool act = lane < NY, node = lane < N1;
   double* J = sm;
+  constexpr int JS = NY | 1;   // odd row stride: lanes reading their rows hit distinct LDS banks
   // ---- state ----
   const double yt = act ? nsg->ytry[lane] : 0.0;
   const double yold = act ? nsg->y[lane] : 0.0;
@@ -192,7 +179,7 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
     // scratch row NY (zeros), so no store or load needs a lane mask
     const int row = act ? lane : NY;
 #pragma unroll
-    for (int B = 0; B < NY; ++B) J[row * NY + B] = 0.0;
+    for (int B = 0; B < NY; ++B) J[row * JS + B] = 0.0;
     wave_sync();
     if (node) {
 #pragma unroll
@@ -203,23 +190,21 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
         const int B = A + dx + mm * dy + mm * mm * dz;
         const int nz = (dx != 0) + (dy != 0) + (dz != 0);
         const double a1 = nz == 0 ? 2.0 * DIM * s1 : (nz == 1 ? -s1 : 0.0);
-        J[A * NY + B] = a1 + m * st[q];
+        J[A * JS + B] = a1 + m * st[q];
       }
-      J[A * NY + N1] = jAu;
-      J[N1 * NY + A] = jAu;
+      J[A * JS + N1] = jAu;
+      J[N1 * JS + A] = jAu;
     }
-    if (lane == N1) J[N1 * NY + N1] = Juu;
+    if (lane == N1) J[N1 * JS + N1] = Juu;
     wave_sync();
     double jr[NY];
 #pragma unroll
-    for (int B = 0; B < NY; ++B) jr[B] = J[row * NY + B];
+    for (int B = 0; B < NY; ++B) jr[B] = J[row * JS + B];
     wave_sync();
-    double myrd = 0.0, v = act ? -Rl : 0.0;
-    chol_fwd_reg<NY>(jr, myrd, v);
-    const double schur = lane_value(jr[N1], N1);
+    double piv = 1.0, v = act ? -Rl : 0.0;
+    const double schur = gj_elim_reg<NY>(jr, piv, v);
     const bool drop = !(schur > kSchurDrop * Juu);
-    if (!drop && lane == N1) { myrd = fast_rsqrt(schur); jr[N1] = schur * myrd; v *= myrd; }
-    const double dv = chol_bwd_reg<NY>(jr, myrd, drop ? N1 : NY, v, J);
+    const double dv = gj_finish<NY>(jr, piv, v, !drop);
     dnew = dv;
     slope = wave_allsum(Rl * dv);
     tnew = 1.0;
@@ -305,10 +290,9 @@ __device__ __forceinline__ void level1_newton_reg(const Grid& g1, double m1, con
       const int nz = abs(bx - ax) + abs(by - ay) + abs(bz - az);
       jr[B] = !node ? 0.0 : (nz == 0 ? 2.0 * DIM * s1 + m1 * df : (nz == 1 ? -s1 : 0.0));
     }
-    double myrd = 0.0, v = node ? -R : 0.0;
-    chol_fwd_reg<N1>(jr, myrd, v);
-    if (lane == N1 - 1) { myrd = fast_rsqrt(jr[N1 - 1]); jr[N1 - 1] = jr[N1 - 1] * myrd; v *= myrd; }
-    const double D = chol_bwd_reg<N1>(jr, myrd, N1, v, sm);
+    double piv = 1.0, v = node ? -R : 0.0;
+    gj_elim_reg<N1>(jr, piv, v);
+    const double D = gj_finish<N1>(jr, piv, v, true);
     {   // a small direction is applied in full without evaluating the energy there
       const bool dfin = __all(isfinite(D));
       double mx[2] = {node ? fabs(D) : 0.0, node ? fabs(U) : 0.0};
