@@ -13,6 +13,11 @@ steps converge to it.
 Stopping: ||dU||_2 <= tol ||U||_2 or stagnation of ||dU|| (update norms, not
 residual norms, because the relative residual has a rounding floor near
 1e-10 at a few million unknowns).
+
+With quadrature="element" the pairings use the degree-2 element rule of
+oracle/quadrature.py instead: A U + N(U) = G with N_i = (f(u_h), phi_i),
+G_i = (g_I, phi_i), and Newton matrix A + K(f'(u_h)) (the f'-weighted mass
+matrix of the same rule).
 """
 from __future__ import annotations
 
@@ -26,6 +31,7 @@ from .fem import assemble_interior
 from .mesh import Mesh, unit_mesh
 from .newton import newton_minimize
 from .nonlinear import Nonlinearity
+from .quadrature import ElementQuadrature, full_vector
 
 DIRECT_LIMIT = 1_200_000
 
@@ -63,25 +69,44 @@ def _linear_solver(dim, N):
 
 def solve_fine(dim: int, n: int, g_nodes: np.ndarray, nl: Nonlinearity,
                U0=None, tol: float = 1e-14, max_iter: int = 60,
-               mesh: Mesh | None = None, A=None, m=None) -> O1Result:
+               mesh: Mesh | None = None, A=None, m=None, quadrature: str = "vertex") -> O1Result:
     """ubar_h on the (0,1)^dim mesh with n cells per side; g at all nodes."""
     mesh = mesh if mesh is not None else unit_mesh(dim, n)
     if A is None or m is None:
         A, m = assemble_interior(mesh)
-    g = np.asarray(g_nodes, dtype=np.float64)[mesh.interior]
-    mg = m * g
     N = mesh.interior.size
+    if quadrature == "vertex":
+        g = np.asarray(g_nodes, dtype=np.float64)[mesh.interior]
+        mg = m * g
 
-    def grad_hess(U):
-        R = A @ U + m * nl.f(U) - mg
-        J = (A + sp.diags(m * nl.df(U))).tocsr()
-        return R, J
+        def grad_hess(U):
+            R = A @ U + m * nl.f(U) - mg
+            J = (A + sp.diags(m * nl.df(U))).tocsr()
+            return R, J
 
-    def energy(U):
-        t1 = 0.5 * float(U @ (A @ U))
-        t2 = float(m @ nl.F(U))
-        t3 = float(mg @ U)
-        return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
+        def energy(U):
+            t1 = 0.5 * float(U @ (A @ U))
+            t2 = float(m @ nl.F(U))
+            t3 = float(mg @ U)
+            return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
+    elif quadrature == "element":
+        I = mesh.interior
+        Qd = ElementQuadrature(mesh)
+        mg = Qd.load(g_nodes)[I]
+
+        def grad_hess(U):
+            uf = full_vector(mesh, U)
+            R = A @ U + Qd.nonlinear(uf, nl)[I] - mg
+            J = (A + Qd.jacobian(uf, nl)[I][:, I]).tocsr()
+            return R, J
+
+        def energy(U):
+            t1 = 0.5 * float(U @ (A @ U))
+            t2 = Qd.energy(full_vector(mesh, U), nl)
+            t3 = float(mg @ U)
+            return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
+    else:
+        raise ValueError(quadrature)
 
     def converged(step, U):
         return np.linalg.norm(step) <= tol * max(np.linalg.norm(U), 1e-300)

@@ -16,7 +16,10 @@ Readings of what the paper leaves open (shared with the GPU library):
     weights: 2D w = 4/5 every sweep; 3D the degree-nu Chebyshev weights for
     D^{-1}A on [1/3, 2], w_i = 1/(c + r cos(pi (2i-1)/(2 nu))), c = 7/6, r = 5/6.
   * All L2 pairings use vertex quadrature on the current finest level k,
-    including those of the augmented problem eq. "coarse problem".
+    including those of the augmented problem eq. "coarse problem"; with
+    Options.quadrature = "element" they use instead the degree-2 element rule
+    of oracle/quadrature.py on the level-k simplices, everywhere: the
+    linearised load (g - f(u^(l)), v), the augmented problem, and level 1.
   * The augmented problem is solved by damped Newton in the coordinates
     (w, alpha) of z = Q_k w + alpha u~ (Q_k = P_k ... P_2), started at
     (0, 1), i.e. z = u~ (the good initial guess of the Remark after
@@ -39,6 +42,7 @@ from .fem import assemble_interior, prolongation
 from .mesh import Mesh, unit_mesh
 from .newton import newton_minimize
 from .nonlinear import Nonlinearity
+from .quadrature import ElementQuadrature, full_vector
 
 JACOBI, CHEBYSHEV = 1, 2
 SCHUR_DROP = 1e-12
@@ -68,6 +72,7 @@ class Options:
     newton_max: int = 30
     converged_tol: float = 1e-13
     converged_max_steps: int = 40
+    quadrature: str = "vertex"  # or "element"
 
     def weights(self, dim: int):
         kind = self.smoother or (JACOBI if dim == 2 else CHEBYSHEV)
@@ -109,6 +114,13 @@ class Hierarchy:
                 lev.Q = (lev.P @ self.levels[-1].Q).tocsr()
             self.levels.append(lev)
         self.A1 = self.levels[0].A.toarray()
+        self._quad = {}
+
+    def quad(self, k: int) -> ElementQuadrature:
+        """Element rule on the level-k simplices (built on first use)."""
+        if k not in self._quad:
+            self._quad[k] = ElementQuadrature(self.levels[k].mesh)
+        return self._quad[k]
 
     @property
     def n_levels(self) -> int:
@@ -121,6 +133,17 @@ class Hierarchy:
         s = fine.n // mesh.n
         ids = np.zeros(mesh.interior.size, dtype=np.int64)
         ijk = mesh.ijk[mesh.interior] * s
+        for a in range(self.dim - 1, -1, -1):
+            ids = ids * (fine.n + 1) + ijk[:, a]
+        return np.asarray(g_fine_nodes, dtype=np.float64)[ids]
+
+    def g_full_on_level(self, g_fine_nodes: np.ndarray, k: int) -> np.ndarray:
+        """Nodal g at all level-k nodes, boundary nodes included (element rule)."""
+        fine = self.levels[-1].mesh
+        mesh = self.levels[k].mesh
+        s = fine.n // mesh.n
+        ids = np.zeros(mesh.coords.shape[0], dtype=np.int64)
+        ijk = mesh.ijk * s
         for a in range(self.dim - 1, -1, -1):
             ids = ids * (fine.n + 1) + ijk[:, a]
         return np.asarray(g_fine_nodes, dtype=np.float64)[ids]
@@ -175,18 +198,33 @@ def _solve_augmented(J, R):
     return np.linalg.solve(J, R)
 
 
-def level1_solve(H: Hierarchy, g1: np.ndarray, nl: Nonlinearity, opts: Options):
-    """Algorithm 3.2, step 1: a(u, v) + (f(u), v) = (g, v) on V_{h_1}."""
+def level1_solve(H: Hierarchy, g1: np.ndarray, nl: Nonlinearity, opts: Options,
+                 g1_full: np.ndarray | None = None):
+    """Algorithm 3.2, step 1: a(u, v) + (f(u), v) = (g, v) on V_{h_1}.
+    g1: interior nodal load; g1_full: load at all level-1 nodes (element rule)."""
     lev = H.levels[0]
     A, m = H.A1, lev.m
-    mg = m * g1
+    if opts.quadrature == "element":
+        Qd, mesh = H.quad(0), lev.mesh
+        I = mesh.interior
+        mg = Qd.load(g1_full)[I]
 
-    def grad_hess(U):
-        return A @ U + m * nl.f(U) - mg, A + np.diag(m * nl.df(U))
+        def grad_hess(U):
+            uf = full_vector(mesh, U)
+            return A @ U + Qd.nonlinear(uf, nl)[I] - mg, A + Qd.jacobian(uf, nl)[I][:, I].toarray()
 
-    def energy(U):
-        t1, t2, t3 = 0.5 * U @ A @ U, m @ nl.F(U), mg @ U
-        return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
+        def energy(U):
+            t1, t2, t3 = 0.5 * U @ A @ U, Qd.energy(full_vector(mesh, U), nl), mg @ U
+            return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
+    else:
+        mg = m * g1
+
+        def grad_hess(U):
+            return A @ U + m * nl.f(U) - mg, A + np.diag(m * nl.df(U))
+
+        def energy(U):
+            t1, t2, t3 = 0.5 * U @ A @ U, m @ nl.F(U), mg @ U
+            return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
 
     U, it, ok = newton_minimize(np.zeros(A.shape[0]), grad_hess, energy, _solve_dense,
                                 _small_converged(opts.newton_tol), opts.newton_max,
@@ -195,29 +233,45 @@ def level1_solve(H: Hierarchy, g1: np.ndarray, nl: Nonlinearity, opts: Options):
 
 
 def augmented_solve(H: Hierarchy, k: int, ut: np.ndarray, g_k: np.ndarray,
-                    nl: Nonlinearity, opts: Options):
+                    nl: Nonlinearity, opts: Options, g_full: np.ndarray | None = None):
     """Algorithm 3.1, step 2: solve eq. "coarse problem" on V_H + span{u~}.
 
     Basis B = [Q_k, u~] (columns are fine nodal vectors), z = B y, y = (w, alpha).
-    R(y) = B^T (A z + M f(z) - M g), J(y) = B^T (A + M diag f'(z)) B.
+    R(y) = B^T (A z + M f(z) - M g), J(y) = B^T (A + M diag f'(z)) B
+    (element rule: B^T (A z + N(z) - G) and B^T (A + K(f'(z))) B).
     """
     lev = H.levels[k]
     A, m, Q = lev.A, lev.m, lev.Q
     B = sp.hstack([Q, sp.csr_matrix(ut.reshape(-1, 1))]).tocsr()
     BtAB = (B.T @ (A @ B)).toarray()
-    mg = m * g_k
-    Btmg = B.T @ mg
+    if opts.quadrature == "element":
+        Qd, mesh = H.quad(k), lev.mesh
+        I = mesh.interior
+        Btmg = B.T @ Qd.load(g_full)[I]
 
-    def grad_hess(y):
-        z = B @ y
-        R = BtAB @ y + B.T @ (m * nl.f(z)) - Btmg
-        J = BtAB + (B.T @ sp.diags(m * nl.df(z)) @ B).toarray()
-        return R, J
+        def grad_hess(y):
+            zf = full_vector(mesh, B @ y)
+            R = BtAB @ y + B.T @ Qd.nonlinear(zf, nl)[I] - Btmg
+            J = BtAB + (B.T @ Qd.jacobian(zf, nl)[I][:, I] @ B).toarray()
+            return R, J
 
-    def energy(y):
-        z = B @ y
-        t1, t2, t3 = 0.5 * y @ BtAB @ y, m @ nl.F(z), Btmg @ y
-        return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
+        def energy(y):
+            t1, t2, t3 = 0.5 * y @ BtAB @ y, Qd.energy(full_vector(mesh, B @ y), nl), Btmg @ y
+            return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
+    else:
+        mg = m * g_k
+        Btmg = B.T @ mg
+
+        def grad_hess(y):
+            z = B @ y
+            R = BtAB @ y + B.T @ (m * nl.f(z)) - Btmg
+            J = BtAB + (B.T @ sp.diags(m * nl.df(z)) @ B).toarray()
+            return R, J
+
+        def energy(y):
+            z = B @ y
+            t1, t2, t3 = 0.5 * y @ BtAB @ y, m @ nl.F(z), Btmg @ y
+            return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
 
     y0 = np.zeros(Q.shape[1] + 1)
     y0[-1] = 1.0
@@ -236,17 +290,23 @@ class StepInfo:
 
 
 def correction_step(H: Hierarchy, k: int, u: np.ndarray, g_k: np.ndarray,
-                    nl: Nonlinearity, opts: Options, info: list | None = None):
-    """Algorithm 3.1: u^(l+1) = SemilinearMG(V_H, u^(l), V_{h_k})."""
+                    nl: Nonlinearity, opts: Options, info: list | None = None,
+                    g_full: np.ndarray | None = None):
+    """Algorithm 3.1: u^(l+1) = SemilinearMG(V_H, u^(l), V_{h_k}).
+    g_k: interior nodal load; g_full: load at all level-k nodes (element rule)."""
     lev = H.levels[k]
     pre, post = opts.weights(H.dim)
     # Step 1: linearised problem eq. "linearized": a(u^, v) = (g - f(u^(l)), v)
-    b = lev.m * (g_k - nl.f(u))
+    if opts.quadrature == "element":
+        Qd, I = H.quad(k), lev.mesh.interior
+        b = Qd.load(g_full)[I] - Qd.nonlinear(full_vector(lev.mesh, u), nl)[I]
+    else:
+        b = lev.m * (g_k - nl.f(u))
     ut = u.copy()
     for _ in range(opts.m_vcycles):
         ut = vcycle(H, k, ut, b, pre, post)
     # Step 2: semilinear problem on V_H + span{u~}
-    unew, y, it, ok = augmented_solve(H, k, ut, g_k, nl, opts)
+    unew, y, it, ok = augmented_solve(H, k, ut, g_k, nl, opts, g_full)
     if info is not None:
         info.append(StepInfo(k + 1, it, ok, float(y[-1])))
     return unew, ut
@@ -275,20 +335,25 @@ def fmg(H: Hierarchy, g_fine_nodes: np.ndarray, nl: Nonlinearity,
     ||du||_2 <= converged_tol ||u||_2 (converged mode, which tends to ubar_h)."""
     opts = opts or Options()
     res = FMGResult(None, hierarchy=H)
-    u, it, _ = level1_solve(H, H.g_on_level(g_fine_nodes, 0), nl, opts)
+    element = opts.quadrature == "element"
+
+    def g_full(k):
+        return H.g_full_on_level(g_fine_nodes, k) if element else None
+
+    u, it, _ = level1_solve(H, H.g_on_level(g_fine_nodes, 0), nl, opts, g_full(0))
     res.level1_iters = it
     for k in range(1, H.n_levels):
         u = H.levels[k].P @ u                     # u^(0) = u_{h_{k-1}}
-        g_k = H.g_on_level(g_fine_nodes, k)
+        g_k, gf = H.g_on_level(g_fine_nodes, k), g_full(k)
         for _ in range(opts.p_steps):
-            u, _ = correction_step(H, k, u, g_k, nl, opts, res.steps)
+            u, _ = correction_step(H, k, u, g_k, nl, opts, res.steps, gf)
     if converged:
         k = H.n_levels - 1
-        g_k = H.g_on_level(g_fine_nodes, k)
+        g_k, gf = H.g_on_level(g_fine_nodes, k), g_full(k)
         prev = np.inf
         res.converged_ok = False
         for s in range(opts.converged_max_steps):
-            unew, _ = correction_step(H, k, u, g_k, nl, opts)
+            unew, _ = correction_step(H, k, u, g_k, nl, opts, None, gf)
             du = np.linalg.norm(unew - u)
             u = unew
             res.extra_steps = s + 1
