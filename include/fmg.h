@@ -71,6 +71,7 @@ enum fmg_nonlinearity {
 enum fmg_precision { FMG_FP64 = 0, FMG_MIXED = 1 };
 enum fmg_smoother { FMG_SMOOTHER_DEFAULT = 0, FMG_JACOBI = 1, FMG_CHEBYSHEV = 2 };
 enum fmg_mode { FMG_PAPER = 0, FMG_CONVERGED = 1 };
+enum fmg_quadrature { FMG_QUAD_VERTEX = 0, FMG_QUAD_ELEMENT = 1 };
 
 typedef struct {
     int dim;            /* 2 or 3                                           */
@@ -122,7 +123,7 @@ typedef struct {
                            (2D) or 512-thread (3D) workgroups, fewer of them */
     int aug_small_nodes; /* levels with at most this many interior nodes solve
                             the augmented problem in one single-workgroup
-                            launch (0: never; default 4096 in 2D, 0 in 3D)   */
+                            launch (0: never; default 4096 in 2D, 343 in 3D) */
     int sweep_rows;     /* 2D V(2,2) levels: rows marched by each wavefront of
                            the register-streaming level kernels (4..4096);
                            0 = chosen per level; -1 = LDS-tiled kernels.
@@ -131,14 +132,27 @@ typedef struct {
                            plane-marching launch; -1 = one launch per sweep,
                            one node per thread; > 0 = one plane-marching
                            launch per sweep                                  */
+    int quadrature;     /* FMG_QUAD_VERTEX (default): the L2 pairings (f(u),v)
+                           and (g,v) of eq. "FEM_form" and of the augmented
+                           problem by the vertex rule, m_j w(x_j);
+                           FMG_QUAD_ELEMENT: on every fine simplex a symmetric
+                           degree-2 rule (3 points per triangle, 4 per
+                           tetrahedron) with u_h, v_h and g as P1
+                           interpolants, used everywhere (linearised load,
+                           augmented problem, level 1).  Element mode ignores
+                           aug_small_nodes and rejects fuse_small_levels = 1
+                           and fmg_solve_noalloc with FMG_E_UNSUPPORTED      */
 } fmg_options;
 
 typedef struct {
     int kind;               /* enum fmg_nonlinearity                        */
     double param;           /* c (LINEAR) or q (SIGNED_POW)                 */
     const double *g_nodes;  /* device; load g at the finest nodes, (n+1)^dim,
-                               boundary entries ignored; must stay valid until
-                               the solve has completed on the stream         */
+                               boundary entries ignored by the vertex rule
+                               (the element rule interpolates g on every
+                               simplex, boundary vertices included); must stay
+                               valid until the solve has completed on the
+                               stream                                        */
 } fmg_problem;
 
 typedef struct {
@@ -190,8 +204,9 @@ int fmg_solve(fmg_hierarchy *h, const fmg_problem *prob, double *d_u_out,
  * as for fmg_solve; the report pointer is the only way to get the status.
  * Differences from the hierarchy path: the small levels of the V-cycle run as
  * a single-workgroup cycle instead of a host-built dense operator (the same
- * operations; results agree to rounding), and only FMG_PAPER mode without
- * fuse_small_levels is supported (else FMG_E_UNSUPPORTED).  Sizes: a
+ * operations; results agree to rounding), and only FMG_PAPER mode with the
+ * vertex rule and without fuse_small_levels is supported (else
+ * FMG_E_UNSUPPORTED).  Sizes: a
  * workspace above FMG_NOALLOC_SCRATCH_BYTES returns FMG_E_SCRATCH with
  * nothing enqueued (2D up to 1024^2 and 3D up to 64^3 fit, both precisions).
  * Every call on a GPU uses that GPU's one buffer, which keeps the last call's

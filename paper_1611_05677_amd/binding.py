@@ -29,6 +29,7 @@ FMG_NOALLOC_SCRATCH_BYTES = 64 << 20
 FMG_FP64, FMG_MIXED = 0, 1
 FMG_SMOOTHER_DEFAULT, FMG_JACOBI, FMG_CHEBYSHEV = 0, 1, 2
 FMG_PAPER, FMG_CONVERGED = 0, 1
+FMG_QUAD_VERTEX, FMG_QUAD_ELEMENT = 0, 1
 FMG_OP_APPLY_A, FMG_OP_SMOOTH, FMG_OP_RESTRICT, FMG_OP_PROLONG, FMG_OP_COARSE = range(5)
 
 EXPORTED = ("fmg_default_options", "fmg_workspace_bytes", "fmg_create_hierarchy", "fmg_solve",
@@ -49,7 +50,8 @@ class Options(ctypes.Structure):
                 ("converged_max_steps", ctypes.c_int), ("converged_tol", ctypes.c_double),
                 ("use_graph", ctypes.c_int), ("tail_max_nodes", ctypes.c_int),
                 ("fuse_small_levels", ctypes.c_int), ("aug_max_blocks", ctypes.c_int),
-                ("aug_small_nodes", ctypes.c_int), ("sweep_rows", ctypes.c_int)]
+                ("aug_small_nodes", ctypes.c_int), ("sweep_rows", ctypes.c_int),
+                ("quadrature", ctypes.c_int)]
 
 
 class ProblemC(ctypes.Structure):

@@ -95,6 +95,8 @@ int resolve(int dim, const fmg_options* in, Resolved& r) {
   if (o.tail_max_nodes < 0 || (o.fuse_small_levels != 0 && o.fuse_small_levels != 1)) return FMG_E_INVALID;
   if (o.aug_max_blocks < 64 || o.aug_max_blocks > 16384 || o.aug_small_nodes < 0) return FMG_E_INVALID;
   if (o.sweep_rows < -1 || (o.sweep_rows > 0 && o.sweep_rows < 4) || o.sweep_rows > 4096) return FMG_E_INVALID;
+  if (o.quadrature != FMG_QUAD_VERTEX && o.quadrature != FMG_QUAD_ELEMENT) return FMG_E_INVALID;
+  if (o.quadrature == FMG_QUAD_ELEMENT && o.fuse_small_levels) return FMG_E_UNSUPPORTED;
   r.o = o;
   r.smoother = o.smoother ? o.smoother : (dim == 2 ? FMG_JACOBI : FMG_CHEBYSHEV);
   if (r.smoother == FMG_JACOBI) {
@@ -147,7 +149,7 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p, bool host_
     const double h = 1.0 / L.g.n;
     L.scale = d == 2 ? 1.0 : h;
     L.m = d == 2 ? h * h : h * h * h;
-    if (k >= 2) {
+    {   // every level: level 1 takes the augmented passes in element mode
       const int nodes_log = d * (k - 1);
       // large levels: 1024-thread (2D) or 512-thread (3D) blocks, fewer of them
       const bool wide = nodes_log >= (d == 2 ? aug_wide_nodes_log<2>() : aug_wide_nodes_log<3>());
@@ -237,7 +239,7 @@ enum KernelClass {
   KC_NEWTON_FINISH, KC_AUG_UPDATE, KC_LEVEL1, KC_BEGIN, KC_OUTPUT, KC_END, KC_FILL,
   KC_VCYCLE_TAIL64, KC_VCYCLE_TAIL32, KC_FMG_TAIL, KC_AUG_SMALL, KC_PRE2D64, KC_POST2D64, KC_PRE2D32, KC_POST2D32,
   KC_PRE2S64, KC_POST2S64, KC_PRE2S32, KC_POST2S32, KC_SMOOTH3S64, KC_SMOOTH3S32,
-  KC_PRE3P64, KC_POST3P64, KC_PRE3P32, KC_POST3P32, KC_COUNT
+  KC_PRE3P64, KC_POST3P64, KC_PRE3P32, KC_POST3P32, KC_RHS_ELEM, KC_COUNT
 };
 const char* const kKernelNames[KC_COUNT] = {
   "smooth_f64", "smooth_f64_from_zero", "resid_restrict_f64", "prolong_add_f64", "coarse_solve_f64",
@@ -249,7 +251,8 @@ const char* const kKernelNames[KC_COUNT] = {
   "pre_sweeps_restrict_2d_stream_f64", "prolong_post_sweeps_2d_stream_f64",
   "pre_sweeps_restrict_2d_stream_f32", "prolong_post_sweeps_2d_stream_f32",
   "smooth_3d_stream_f64", "smooth_3d_stream_f32",
-  "pre_sweep_pair_3d_f64", "prolong_sweep_pair_3d_f64", "pre_sweep_pair_3d_f32", "prolong_sweep_pair_3d_f32"};
+  "pre_sweep_pair_3d_f64", "prolong_sweep_pair_3d_f64", "pre_sweep_pair_3d_f32", "prolong_sweep_pair_3d_f32",
+  "rhs_element"};
 
 // Event pairs around launches (fmg_profile_solve only).
 struct Prof {
@@ -696,6 +699,41 @@ TransitionArgs transition_args(const fmg_hierarchy* h, const Roles& R, int k, bo
   return a;
 }
 
+// Algorithm 3.1, step 2 with the element rule on level k (k = 1: the level-1
+// problem of Algorithm 3.2, step 1, as the augmented problem with u~ = 0, so
+// that V_H + span{u~} = V_H): the setup pass, the quadrature passes of the
+// launch sequence, the finisher, and the update u = Q w + alpha u~ unless
+// deferred.
+template <int DIM, int KIND>
+void aug_solve_elem(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bool defer_update) {
+  const Plan& p = h->plan;
+  const LevelInfo& L = p.lev[k];
+  const fmg_options& o = h->ro.o;
+  const long long N = interior(L.g, DIM);
+  const int nf1 = p.lev[p.nlev].g.n + 1, fs = 1 << (p.nlev - k);
+  double* pq = h->at<double>(p.off_pq);
+  double* ps = h->at<double>(p.off_ps);
+  unsigned* ticket = h->at<unsigned>(p.off_ticket);
+  const double* A1 = h->at<double>(p.off_A1);
+  const size_t lds = aug_pass_lds_bytes(p);
+  FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, 16.0 * N,
+             (launch_aug_pass<DIM, KIND, true, false, true>(L.aug_blocks, L.aug_threads, lds, st, L.g, L.aug, R.x[k],
+                                                            h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(), h->rep(),
+                                                            pq, ps, ticket, k, o.newton_max, o.newton_tol)));
+  for (int pass = 1; pass < o.newton_passes; ++pass)
+    FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
+               (launch_aug_pass<DIM, KIND, false, false, true>(L.aug_blocks, L.aug_threads, lds, st, L.g, L.aug,
+                                                               R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1, h->ns(),
+                                                               h->rep(), pq, ps, ticket, k, o.newton_max,
+                                                               o.newton_tol)));
+  FMG_LAUNCH(h, st, KC_NEWTON_FINISH, k, N, 0.0,
+             (launch_newton_finish<DIM, KIND, true>(lds, st, L.g, L.aug, R.x[k], h->slot(), A1, L.m, h->ns(),
+                                                    h->rep(), o.newton_max, o.newton_tol)));
+  if (!defer_update)
+    FMG_LAUNCH(h, st, KC_AUG_UPDATE, k, N, 16.0 * N,
+               k_aug_update<DIM><<<grid_of(L.g, DIM), kBlock, 0, st>>>(L.g, L.aug, h->ns(), R.x[k]));
+}
+
 template <int DIM, int KIND>
 void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bool rhs_ready,
                      bool defer_update, bool fold_next) {
@@ -706,8 +744,14 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   const long long N = interior(L.g, DIM);
   const int nf1 = p.lev[p.nlev].g.n + 1, fs = 1 << (p.nlev - k);
   double* b = h->at<double>(p.off_b[k]);
-  // step 1: linearised problem, m V-cycles from u^(l)
-  if (!rhs_ready)
+  const bool elem = o.quadrature == FMG_QUAD_ELEMENT;
+  // step 1: linearised problem, m V-cycles from u^(l); the element rule's
+  // load couples neighbouring nodes, so it is formed here, after the
+  // transition has written u (the transition's vertex-rule b is replaced)
+  if (elem)
+    FMG_LAUNCH(h, st, KC_RHS_ELEM, k, N, 16.0 * N,
+               (launch_rhs_elem<DIM, KIND>(grid, st, L.g, h->slot(), nf1, fs, R.x[k], b, L.m)));
+  else if (!rhs_ready)
     FMG_LAUNCH(h, st, KC_RHS, k, N, 24.0 * N,
                (launch_rhs<DIM, KIND>(grid, st, L.g, h->slot(), nf1, fs, R.x[k], b, L.m)));
   for (int c = 0; c < o.m_vcycles; ++c) {
@@ -731,6 +775,10 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   double* ps = h->at<double>(p.off_ps);
   unsigned* ticket = h->at<unsigned>(p.off_ticket);
   const double* A1 = h->at<double>(p.off_A1);
+  if (elem) {
+    aug_solve_elem<DIM, KIND>(h, R, k, st, defer_update);
+    return;
+  }
   if (N <= o.aug_small_nodes) {
     // the whole augmented solve (and the update unless deferred) by one workgroup
     FMG_LAUNCH(h, st, KC_AUG_SMALL, k, N, 0.0,
@@ -803,6 +851,14 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
             else std::swap(R.xs[j], R.ts[j]);
           }
     first = T + 1;
+  } else if (o.quadrature == FMG_QUAD_ELEMENT) {
+    // report reset; Algorithm 3.2, step 1 as the augmented problem on level 1
+    // with u~ = 0 (its u~ direction adds nothing and is dropped), then u = w
+    FMG_LAUNCH(h, st, KC_BEGIN, 0, 0, 0.0, k_begin_solve<<<1, 64, 0, st>>>(h->rep(), p.nlev, h->flag()));
+    const LevelInfo& L1 = p.lev[1];
+    FMG_LAUNCH(h, st, KC_FILL, 1, p.N1, 0.0,
+               k_fill<double><<<64, 256, 0, st>>>(R.x[1], L1.count, 0.0));
+    aug_solve_elem<DIM, KIND>(h, R, 1, st, false);
   } else {
     // report reset and Algorithm 3.2, step 1: exact semilinear solve on V_{h_1}
     const LevelInfo& L1 = p.lev[1];
@@ -832,7 +888,7 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     for (int l = 0; l < o.p_steps; ++l) {
       const bool defer = l == o.p_steps - 1 && (k < p.nlev || finish);
       // the last small-level augmented solve also performs a small next transition
-      const bool fold = defer && k < p.nlev && N <= o.aug_small_nodes &&
+      const bool fold = o.quadrature == FMG_QUAD_VERTEX && defer && k < p.nlev && N <= o.aug_small_nodes &&
                         interior(p.lev[k + 1].g, DIM) <= kFoldTransitionNodes;
       correction_step<DIM, KIND>(h, R, k, st, l == 0, defer, fold);
       pending_aug = defer;
@@ -1273,8 +1329,9 @@ void fmg_default_options(int dim, fmg_options* o) {
   o->aug_max_blocks = 512;
   // the single-workgroup augmented solve pays off for the 10 unknowns of the
   // 2D problem; the 28 of 3D run faster through the multi-workgroup passes
-  o->aug_small_nodes = dim == 2 ? 4096 : 0;
+  o->aug_small_nodes = dim == 2 ? 4096 : 343;
   o->sweep_rows = 0;
+  o->quadrature = FMG_QUAD_VERTEX;
 }
 
 size_t fmg_workspace_bytes(const fmg_mesh_desc* mesh, const fmg_options* opts) {
@@ -1458,7 +1515,8 @@ int fmg_solve_noalloc(const fmg_mesh_desc* mesh, const fmg_options* opts, const 
   if (st != FMG_OK) return st;
   Resolved ro;
   if ((st = resolve(mesh->dim, opts, ro)) != FMG_OK) return st;
-  if (ro.o.mode != FMG_PAPER || ro.o.fuse_small_levels) return FMG_E_UNSUPPORTED;
+  if (ro.o.mode != FMG_PAPER || ro.o.fuse_small_levels || ro.o.quadrature != FMG_QUAD_VERTEX)
+    return FMG_E_UNSUPPORTED;
   fmg_hierarchy h;   // on the stack: plan, options and the scratch as workspace
   if ((st = make_plan(mesh, ro, h.plan, false)) != FMG_OK) return st;
   if (h.plan.total > kScratchBytes) return FMG_E_SCRATCH;

@@ -241,6 +241,130 @@ __device__ __forceinline__ void quad_accumulate(const Grid& g, const AugShape& s
   });
 }
 
+}  // namespace fmg
+
+#include "fmg_elem.h"
+
+namespace fmg {
+
+// Element rule: per-cell quadrature sums at z = Q w + alpha u~ for one block's
+// range of fine cells, unweighted (the caller scales them by ElemRule::W).
+template <int DIM, int KIND>
+__device__ __forceinline__ void quad_accumulate_elem(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                                     const double* ytry, double param, int cell, int t0, int t1,
+                                                     int tid, int nthreads, double* acc) {
+  using AC = Acc<DIM>;
+  int cx, cy, cz;
+  cell_of<DIM>(cell, s.nH, cx, cy, cz);
+  double wv[AC::NV];
+#pragma unroll
+  for (int a = 0; a < AC::NV; ++a) {
+    const int gi = coarse_vertex<DIM>(s.nH, cx, cy, cz, a);
+    wv[a] = gi >= 0 ? ytry[gi] : 0.0;
+  }
+  const double alpha = ytry[s.N1];
+  for_cell_cells<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, ut,
+                      [&](int, int, int, int lx, int ly, int lz, const double* uc) {
+    elem_cell<DIM, KIND, false>(s, lx, ly, lz, uc, nullptr, wv, alpha, param, acc, nullptr);
+  });
+}
+
+// Element rule, setup pass: the stiffness terms (A u~) phi_a, (A u~) u~ at the
+// cell's lower corner node (as in the vertex rule: they are exact matrix
+// products), the load terms W g phi_a, W g u~ at the points, and the
+// (unweighted) quadrature sums at the Newton start z = u~.
+template <int DIM, int KIND>
+__device__ __forceinline__ void setup_quad_accumulate_elem(const Grid& g, const AugShape& s,
+                                                           const double* __restrict__ ut,
+                                                           const double* __restrict__ gl, int nf1, int fs,
+                                                           double scale, double param, int cell, int t0, int t1,
+                                                           int tid, int nthreads, double* acc_s, double* acc_q) {
+  using AC = Acc<DIM>;
+  int cx, cy, cz;
+  cell_of<DIM>(cell, s.nH, cx, cy, cz);
+  double wv[AC::NV];
+#pragma unroll
+  for (int a = 0; a < AC::NV; ++a) wv[a] = 0.0;
+  const double inv_r = 1.0 / (1 << s.log2r);
+  for_cell_cells<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, ut,
+                      [&](int i, int j, int l, int lx, int ly, int lz, const double* uc) {
+    if (i != 0 && j != 0 && (DIM == 2 || l != 0)) {
+      const double tl[3] = {lx * inv_r, ly * inv_r, lz * inv_r};
+      double phi[AC::NV];
+      kuhn_phi<DIM>(tl, phi);
+      const double au = apply_A_at<DIM>(ut, gidx<DIM>(g, i, j, l), g, scale);
+#pragma unroll
+      for (int a = 0; a < AC::NV; ++a) acc_s[AC::S_BH + a] += phi[a] * au;
+      acc_s[AC::S_C] += uc[0] * au;
+    }
+    double gc[AC::NV];
+#pragma unroll
+    for (int e = 0; e < AC::NV; ++e)
+      gc[e] = gl[fine_load_index(nf1, fs, i + (e & 1), j + ((e >> 1) & 1), DIM == 3 ? l + ((e >> 2) & 1) : 0)];
+    elem_cell<DIM, KIND, true>(s, lx, ly, lz, uc, gc, wv, 1.0, param, acc_q, acc_s);
+  });
+}
+
+// Linearised right-hand side with the element rule (Alg. 3.1 step 1):
+// b = (g_I - f(u_h), phi) at interior node (i, j, l): over the 2^d fine cells
+// around the node, their Kuhn simplices with the node as a vertex, and the
+// points of each, (g - f(u)) at the point times the node's barycentric
+// coordinate there; times m W.
+template <int DIM, int KIND, int S>
+__device__ __forceinline__ double rhs_elem_simplex(int corner, const double* uc, const double* gc, double param) {
+  using R = ElemRule<DIM>;
+  using KC = KuhnChain<DIM, S>;
+  const int m = corner == 0 ? 0
+              : corner == KC::v1 ? 1
+              : corner == KC::vl ? DIM
+              : (DIM == 3 && corner == KC::v2) ? 2 : -1;
+  if (m < 0) return 0.0;
+  double uv[DIM + 1], gv[DIM + 1];
+  uv[0] = uc[0]; uv[1] = uc[KC::v1]; uv[DIM] = uc[KC::vl];
+  gv[0] = gc[0]; gv[1] = gc[KC::v1]; gv[DIM] = gc[KC::vl];
+  if (DIM == 3) { uv[2] = uc[KC::v2]; gv[2] = gc[KC::v2]; }
+  double usum = 0.0, gsum = 0.0;
+#pragma unroll
+  for (int k = 0; k <= DIM; ++k) { usum += uv[k]; gsum += gv[k]; }
+  double acc = 0.0;
+#pragma unroll 1
+  for (int p = 0; p <= DIM; ++p) {
+    const double uq = elem_interp<DIM>(uv, usum, p);
+    const double gq = elem_interp<DIM>(gv, gsum, p);
+    acc += (p == m ? R::A : R::B) * (gq - NL<KIND>::f(uq, param));
+  }
+  return acc;
+}
+
+template <int DIM, int KIND>
+__global__ void __launch_bounds__(kBlock) k_rhs_elem(Grid g, const ProblemSlot* __restrict__ slot, int nf1, int s,
+                                                     const double* __restrict__ u, double* __restrict__ b,
+                                                     double m) {
+  constexpr int NV = 1 << DIM;
+  int i, j, l;
+  if (!node_of_thread<DIM>(g, i, j, l)) return;
+  const double* __restrict__ gl = slot->g;
+  const double param = slot->param;
+  double acc = 0.0;
+#pragma unroll 1
+  for (int e = 0; e < NV; ++e) {
+    // the fine cell whose corner e is this node
+    const int ci = i - (e & 1), cj = j - ((e >> 1) & 1), cl = DIM == 3 ? l - ((e >> 2) & 1) : 0;
+    double uc[NV], gc[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      const int x = ci + (c & 1), y = cj + ((c >> 1) & 1), z = DIM == 3 ? cl + ((c >> 2) & 1) : 0;
+      uc[c] = u[gidx<DIM>(g, x, y, z)];
+      gc[c] = gl[fine_load_index(nf1, s, x, y, z)];
+    }
+    acc += rhs_elem_simplex<DIM, KIND, 0>(e, uc, gc, param) + rhs_elem_simplex<DIM, KIND, 1>(e, uc, gc, param);
+    if constexpr (DIM == 3)
+      acc += (rhs_elem_simplex<DIM, KIND, 2>(e, uc, gc, param) + rhs_elem_simplex<DIM, KIND, 3>(e, uc, gc, param)) +
+             (rhs_elem_simplex<DIM, KIND, 4>(e, uc, gc, param) + rhs_elem_simplex<DIM, KIND, 5>(e, uc, gc, param));
+  }
+  b[gidx<DIM>(g, i, j, l)] = m * ElemRule<DIM>::W * acc;
+}
+
 // ---------------------------------------------------------------------------
 // Small dense linear algebra in LDS, executed by the first wavefront of the
 // block (n <= 64 = wave size).  Lanes of one wavefront issue their LDS
@@ -525,6 +649,7 @@ __device__ __forceinline__ void newton_core(const AugShape& s, const double* cs,
       rep->newton_iters[k] = iter_new;
       rep->newton_total[k] += iter_new;
       rep->alpha[k] = ns->y[N1];
+      if (k == 0) rep->level1_iters = iter_new;   // level 1 solved as the augmented problem with u~ = 0
       if (!finite) report_status(rep, FMG_E_NONFINITE);
       else if (!ok) report_status(rep, FMG_E_NOT_CONVERGED);
     }
@@ -670,7 +795,7 @@ __device__ __forceinline__ void newton_step_dev(const AugShape& s, const double*
                                                 double m, NewtonState* ns, fmg_report* rep, int newton_max,
                                                 double tol, double* sm);
 
-template <int DIM, int KIND>
+template <int DIM, int KIND, bool ELEM = false>
 __device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShape& s, const double* __restrict__ ut,
                                            const double* ytry, double param, double* cs);
 
@@ -680,9 +805,11 @@ __device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShap
 // as per-block partials.  The last block to finish (atomic ticket,
 // release/acquire at device scope) reduces all partials, cell by cell in a
 // fixed block order, into the cell sums and performs the Newton step.
-// tickets[0]: zero between launches.
+// tickets[0]: zero between launches.  ELEM: the element rule (the block's
+// node range is a range of fine cells); the completion of a Newton solve that
+// needs more passes is then left to k_newton_finish.
 // LDS: newton_kernel_lds_doubles(ncell, NQ, N1, blockDim).
-template <int DIM, int KIND, bool SETUP, bool FINISH>
+template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM = false>
 __global__ void __launch_bounds__(aug_threads<DIM>()) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
                                                      const ProblemSlot* __restrict__ slot, int nf1, int fs,
                                                      double scale, double m, const double* __restrict__ A1,
@@ -690,6 +817,7 @@ __global__ void __launch_bounds__(aug_threads<DIM>()) k_aug_pass(Grid g, AugShap
                                                      double* __restrict__ pq, double* __restrict__ ps,
                                                      unsigned* __restrict__ tickets, int level, int newton_max,
                                                      double tol) {
+  static_assert(!(ELEM && FINISH), "element-rule passes leave the completion to k_newton_finish");
   using AC = Acc<DIM>;
   extern __shared__ double smem[];
   __shared__ int is_last;
@@ -705,17 +833,26 @@ __global__ void __launch_bounds__(aug_threads<DIM>()) k_aug_pass(Grid g, AugShap
     double acc[AC::NS + AC::NQ];
 #pragma unroll
     for (int q = 0; q < AC::NS + AC::NQ; ++q) acc[q] = 0.0;
-    setup_quad_accumulate<DIM, KIND>(g, s, ut, slot->g, nf1, fs, scale, param, cell, t0, t1, threadIdx.x,
-                                     blockDim.x, acc, acc + AC::NS);
-    const double tot = block_sum_many<AC::NS + AC::NQ>(acc, smem);
+    if (ELEM)
+      setup_quad_accumulate_elem<DIM, KIND>(g, s, ut, slot->g, nf1, fs, scale, param, cell, t0, t1, threadIdx.x,
+                                            blockDim.x, acc, acc + AC::NS);
+    else
+      setup_quad_accumulate<DIM, KIND>(g, s, ut, slot->g, nf1, fs, scale, param, cell, t0, t1, threadIdx.x,
+                                       blockDim.x, acc, acc + AC::NS);
+    double tot = block_sum_many<AC::NS + AC::NQ>(acc, smem);
+    if (ELEM && threadIdx.x >= AC::NS) tot *= ElemRule<DIM>::W;
     if (threadIdx.x < AC::NS) ps[(size_t)blockIdx.x * AC::NS + threadIdx.x] = tot;
     else if (threadIdx.x < AC::NS + AC::NQ) pq[(size_t)blockIdx.x * AC::NQ + threadIdx.x - AC::NS] = tot;
   } else {
     double acc[AC::NQ];
 #pragma unroll
     for (int q = 0; q < AC::NQ; ++q) acc[q] = 0.0;
-    quad_accumulate<DIM, KIND>(g, s, ut, ns->ytry, param, cell, t0, t1, threadIdx.x, blockDim.x, acc);
-    const double tot = block_sum_many<AC::NQ>(acc, smem);
+    if (ELEM)
+      quad_accumulate_elem<DIM, KIND>(g, s, ut, ns->ytry, param, cell, t0, t1, threadIdx.x, blockDim.x, acc);
+    else
+      quad_accumulate<DIM, KIND>(g, s, ut, ns->ytry, param, cell, t0, t1, threadIdx.x, blockDim.x, acc);
+    double tot = block_sum_many<AC::NQ>(acc, smem);
+    if (ELEM) tot *= ElemRule<DIM>::W;
     if (threadIdx.x < AC::NQ) pq[(size_t)blockIdx.x * AC::NQ + threadIdx.x] = tot;
   }
   // ---- the last block reduces every cell's partials and takes the Newton step ----
@@ -753,7 +890,7 @@ __global__ void __launch_bounds__(aug_threads<DIM>()) k_aug_pass(Grid g, AugShap
 // spread over a segment of LPC = min(64, r^d) lanes, so a wavefront holds
 // 64 / LPC cells and reduces each accumulator over its segment only; the last
 // lane of a segment writes the cell's sums.  No block barrier inside.
-template <int DIM, int KIND, int LPC>
+template <int DIM, int KIND, int LPC, bool ELEM>
 __device__ __forceinline__ void quad_cells_seg(const Grid& g, const AugShape& s, const double* __restrict__ ut,
                                                const double* ytry, double param, double* cs) {
   using AC = Acc<DIM>;
@@ -767,25 +904,28 @@ __device__ __forceinline__ void quad_cells_seg(const Grid& g, const AugShape& s,
     double acc[AC::NQ];
 #pragma unroll
     for (int q = 0; q < AC::NQ; ++q) acc[q] = 0.0;
-    if (cell < ncell) quad_accumulate<DIM, KIND>(g, s, ut, ytry, param, cell, 0, nodes, sub, LPC, acc);
+    if (cell < ncell) {
+      if (ELEM) quad_accumulate_elem<DIM, KIND>(g, s, ut, ytry, param, cell, 0, nodes, sub, LPC, acc);
+      else quad_accumulate<DIM, KIND>(g, s, ut, ytry, param, cell, 0, nodes, sub, LPC, acc);
+    }
 #pragma unroll
     for (int q = 0; q < AC::NQ; ++q) {
-      const double v = seg_sum<LPC>(acc[q]);
+      const double v = seg_sum<LPC>(acc[q]) * (ELEM ? ElemRule<DIM>::W : 1.0);
       if (sub == LPC - 1 && cell < ncell) cs[cell * AC::NQ + q] = v;
     }
   }
   __syncthreads();
 }
 
-template <int DIM, int KIND>
+template <int DIM, int KIND, bool ELEM>
 __device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShape& s, const double* __restrict__ ut,
                                            const double* ytry, double param, double* cs) {
   const int nodes_log = DIM * s.log2r;
-  if (nodes_log <= 2) quad_cells_seg<DIM, KIND, 4>(g, s, ut, ytry, param, cs);
-  else if (nodes_log == 3) quad_cells_seg<DIM, KIND, 8>(g, s, ut, ytry, param, cs);
-  else if (nodes_log == 4) quad_cells_seg<DIM, KIND, 16>(g, s, ut, ytry, param, cs);
-  else if (nodes_log == 5) quad_cells_seg<DIM, KIND, 32>(g, s, ut, ytry, param, cs);
-  else quad_cells_seg<DIM, KIND, 64>(g, s, ut, ytry, param, cs);
+  if (nodes_log <= 2) quad_cells_seg<DIM, KIND, 4, ELEM>(g, s, ut, ytry, param, cs);
+  else if (nodes_log == 3) quad_cells_seg<DIM, KIND, 8, ELEM>(g, s, ut, ytry, param, cs);
+  else if (nodes_log == 4) quad_cells_seg<DIM, KIND, 16, ELEM>(g, s, ut, ytry, param, cs);
+  else if (nodes_log == 5) quad_cells_seg<DIM, KIND, 32, ELEM>(g, s, ut, ytry, param, cs);
+  else quad_cells_seg<DIM, KIND, 64, ELEM>(g, s, ut, ytry, param, cs);
 }
 
 template <int DIM, int LPC>
@@ -871,8 +1011,9 @@ __device__ __forceinline__ void setup_quad_cells_by_waves(const Grid& g, const A
 }
 
 // Completes a Newton solve that the passes of the launch sequence did not
-// finish: one block evaluates the fine quadrature itself (3D).
-template <int DIM, int KIND>
+// finish: one block evaluates the fine quadrature itself (3D, and the element
+// rule in 2D).
+template <int DIM, int KIND, bool ELEM = false>
 __global__ void __launch_bounds__(kBlock) k_newton_finish(Grid g, AugShape s, const double* __restrict__ ut,
                                                           const ProblemSlot* __restrict__ slot,
                                                           const double* __restrict__ A1, double m,
@@ -886,7 +1027,7 @@ __global__ void __launch_bounds__(kBlock) k_newton_finish(Grid g, AugShape s, co
   while (true) {
     __syncthreads();
     if (ns->done) return;
-    quad_cells_by_waves<DIM, KIND>(g, s, ut, ns->ytry, slot->param, cs);
+    quad_cells_by_waves<DIM, KIND, ELEM>(g, s, ut, ns->ytry, slot->param, cs);
     newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   }
 }

@@ -20,13 +20,17 @@ void launch_aug_small(size_t lds, hipStream_t st, Grid g, AugShape s, double* ut
                       int nf1, int fs, double scale, double m, const double* A1, NewtonState* ns, fmg_report* rep,
                       int level, int newton_max, double tol, int do_update, int fold, TransitionArgs next);
 
-template <int DIM, int KIND, bool SETUP, bool FINISH>
+template <int DIM, int KIND>
+void launch_rhs_elem(dim3 grid, hipStream_t st, Grid g, const ProblemSlot* slot, int nf1, int fs, const double* u,
+                     double* b, double m);
+
+template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM = false>
 void launch_aug_pass(int blocks, int threads, size_t lds, hipStream_t st, Grid g, AugShape s, const double* ut,
                      const ProblemSlot* slot, int nf1, int fs, double scale, double m, const double* A1,
                      NewtonState* ns, fmg_report* rep, double* pq, double* ps, unsigned* tickets, int level,
                      int newton_max, double tol);
 
-template <int DIM, int KIND>
+template <int DIM, int KIND, bool ELEM = false>
 void launch_newton_finish(size_t lds, hipStream_t st, Grid g, AugShape s, const double* ut,
                           const ProblemSlot* slot, const double* A1, double m, NewtonState* ns, fmg_report* rep,
                           int newton_max, double tol);

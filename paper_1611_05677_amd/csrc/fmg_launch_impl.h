@@ -21,20 +21,27 @@ void launch_aug_small(size_t lds, hipStream_t st, Grid g, AugShape s, double* ut
                                                              newton_max, tol, do_update, fold, next);
 }
 
-template <int DIM, int KIND, bool SETUP, bool FINISH>
+template <int DIM, int KIND>
+void launch_rhs_elem(dim3 grid, hipStream_t st, Grid g, const ProblemSlot* slot, int nf1, int fs, const double* u,
+                     double* b, double m) {
+  k_rhs_elem<DIM, KIND><<<grid, kBlock, 0, st>>>(g, slot, nf1, fs, u, b, m);
+}
+
+template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM>
 void launch_aug_pass(int blocks, int threads, size_t lds, hipStream_t st, Grid g, AugShape s, const double* ut,
                      const ProblemSlot* slot, int nf1, int fs, double scale, double m, const double* A1,
                      NewtonState* ns, fmg_report* rep, double* pq, double* ps, unsigned* tickets, int level,
                      int newton_max, double tol) {
-  k_aug_pass<DIM, KIND, SETUP, FINISH><<<blocks, threads, lds, st>>>(g, s, ut, slot, nf1, fs, scale, m, A1, ns, rep,
-                                                                     pq, ps, tickets, level, newton_max, tol);
+  k_aug_pass<DIM, KIND, SETUP, FINISH, ELEM><<<blocks, threads, lds, st>>>(g, s, ut, slot, nf1, fs, scale, m, A1, ns,
+                                                                           rep, pq, ps, tickets, level, newton_max,
+                                                                           tol);
 }
 
-template <int DIM, int KIND>
+template <int DIM, int KIND, bool ELEM>
 void launch_newton_finish(size_t lds, hipStream_t st, Grid g, AugShape s, const double* ut,
                           const ProblemSlot* slot, const double* A1, double m, NewtonState* ns, fmg_report* rep,
                           int newton_max, double tol) {
-  k_newton_finish<DIM, KIND><<<1, kBlock, lds, st>>>(g, s, ut, slot, A1, m, ns, rep, newton_max, tol);
+  k_newton_finish<DIM, KIND, ELEM><<<1, kBlock, lds, st>>>(g, s, ut, slot, A1, m, ns, rep, newton_max, tol);
 }
 
 template <int DIM, int KIND, bool MIXED>
@@ -99,4 +106,26 @@ void launch_transition(dim3 grid, hipStream_t st, TransitionArgs a, const Newton
   template void launch_newton_finish<D, K>(size_t, hipStream_t, Grid, AugShape, const double*,         \
                                            const ProblemSlot*, const double*, double, NewtonState*,   \
                                            fmg_report*, int, double);                                 \
+  }
+
+// The element-rule kernels for dimension D and nonlinearity K: right-hand
+// side, setup and quadrature passes, and the Newton finisher (both
+// dimensions).  Instantiated in fmg_kind_{2d,3d}_e.hip.
+#define FMG_INSTANTIATE_ELEM(D, K)                                                                   \
+  namespace fmg {                                                                                    \
+  template void launch_rhs_elem<D, K>(dim3, hipStream_t, Grid, const ProblemSlot*, int, int,          \
+                                      const double*, double*, double);                              \
+  template void launch_aug_pass<D, K, true, false, true>(int, int, size_t, hipStream_t, Grid, AugShape, \
+                                                         const double*, const ProblemSlot*, int, int,  \
+                                                         double, double, const double*, NewtonState*,  \
+                                                         fmg_report*, double*, double*, unsigned*, int, \
+                                                         int, double);                                 \
+  template void launch_aug_pass<D, K, false, false, true>(int, int, size_t, hipStream_t, Grid, AugShape, \
+                                                          const double*, const ProblemSlot*, int, int, \
+                                                          double, double, const double*, NewtonState*, \
+                                                          fmg_report*, double*, double*, unsigned*, int, \
+                                                          int, double);                                \
+  template void launch_newton_finish<D, K, true>(size_t, hipStream_t, Grid, AugShape, const double*,   \
+                                                 const ProblemSlot*, const double*, double, NewtonState*, \
+                                                 fmg_report*, int, double);                           \
   }

@@ -241,6 +241,7 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
       rep->newton_iters[k] = iter_new;
       rep->newton_total[k] += iter_new;
       rep->alpha[k] = alpha_new;
+      if (k == 0) rep->level1_iters = iter_new;   // level 1 solved as the augmented problem with u~ = 0
       if (!finite) report_status(rep, FMG_E_NONFINITE);
       else if (!ok) report_status(rep, FMG_E_NOT_CONVERGED);
     }

@@ -172,6 +172,20 @@ def test_noalloc_rejects_before_enqueueing():
     fused = B.default_options(2, fuse_small_levels=1)
     assert call(ctypes.byref(small), ctypes.byref(fused), ctypes.byref(prob), fake, None, None) == \
         B.FMG_E_UNSUPPORTED
+    elem = B.default_options(2, quadrature=B.FMG_QUAD_ELEMENT)
+    assert call(ctypes.byref(small), ctypes.byref(elem), ctypes.byref(prob), fake, None, None) == \
+        B.FMG_E_UNSUPPORTED
     bad = B.ProblemC(99, 0.0, fake)
     assert call(ctypes.byref(small), ctypes.byref(o), ctypes.byref(bad), fake, None, None) == B.FMG_E_INVALID
     assert B.status_str(B.FMG_E_SCRATCH).startswith("problem larger than the static scratch")
+
+
+def test_element_rule_option_is_validated_on_the_host():
+    """fmg_options.quadrature: vertex (default) or element; the element rule
+    with the fused small-level kernel (vertex rule only) is refused."""
+    assert B.default_options(2).quadrature == B.FMG_QUAD_VERTEX
+    assert B.workspace_bytes(2, 4, 3, B.default_options(2, quadrature=B.FMG_QUAD_ELEMENT)) > 0
+    assert B.workspace_bytes(3, 4, 2, B.default_options(3, quadrature=B.FMG_QUAD_ELEMENT)) > 0
+    assert B.workspace_bytes(2, 4, 3, B.default_options(2, quadrature=2)) == 0
+    assert B.workspace_bytes(2, 4, 3, B.default_options(2, quadrature=B.FMG_QUAD_ELEMENT,
+                                                         fuse_small_levels=1)) == 0
