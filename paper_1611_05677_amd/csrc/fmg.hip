@@ -76,6 +76,7 @@ struct Plan {
   size_t off_uprev;
   size_t off_fmgtail;
   size_t off_ticket;
+  size_t off_econtrib;     // element rule: per-corner cell contributions of the right-hand side
   size_t norm_blocks;
   size_t total;
 };
@@ -202,6 +203,10 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p, bool host_
   p.off_uprev = ro.o.mode == FMG_CONVERGED ? take(sizeof(double) * F.count) : 0;
   p.off_fmgtail = take(sizeof(FmgTailParams));
   p.off_ticket = take(sizeof(unsigned));
+  if (ro.o.quadrature == FMG_QUAD_ELEMENT) {
+    const size_t nf = (size_t)F.g.n;
+    p.off_econtrib = take(sizeof(double) * (d == 2 ? 4 * nf * nf : 8 * nf * nf * nf));
+  }
   p.total = off;
   return FMG_OK;
 }
@@ -749,8 +754,9 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   // load couples neighbouring nodes, so it is formed here, after the
   // transition has written u (the transition's vertex-rule b is replaced)
   if (elem)
-    FMG_LAUNCH(h, st, KC_RHS_ELEM, k, N, 16.0 * N,
-               (launch_rhs_elem<DIM, KIND>(grid, st, L.g, h->slot(), nf1, fs, R.x[k], b, L.m)));
+    FMG_LAUNCH(h, st, KC_RHS_ELEM, k, N, (DIM == 2 ? 88.0 : 152.0) * N,
+               (launch_rhs_elem<DIM, KIND>(grid, st, L.g, h->slot(), nf1, fs, R.x[k],
+                                           h->at<double>(p.off_econtrib), b, L.m)));
   else if (!rhs_ready)
     FMG_LAUNCH(h, st, KC_RHS, k, N, 24.0 * N,
                (launch_rhs<DIM, KIND>(grid, st, L.g, h->slot(), nf1, fs, R.x[k], b, L.m)));

@@ -305,20 +305,17 @@ __device__ __forceinline__ void setup_quad_accumulate_elem(const Grid& g, const 
   });
 }
 
-// Linearised right-hand side with the element rule (Alg. 3.1 step 1):
-// b = (g_I - f(u_h), phi) at interior node (i, j, l): over the 2^d fine cells
-// around the node, their Kuhn simplices with the node as a vertex, and the
-// points of each, (g - f(u)) at the point times the node's barycentric
-// coordinate there; times m W.
+// Linearised right-hand side with the element rule (Alg. 3.1 step 1),
+// b = (g_I - f(u_h), phi) at every interior node, in two launches: every fine
+// cell evaluates g - f(u) once at each point of its Kuhn simplices and
+// writes, per corner, the sum of those values times the corner's barycentric
+// coordinate there (contrib[corner][cell]); every interior node then adds the
+// 2^d contributions of the cells around it (it is corner e of cell node - e),
+// in ascending e, times m W.
 template <int DIM, int KIND, int S>
-__device__ __forceinline__ double rhs_elem_simplex(int corner, const double* uc, const double* gc, double param) {
+__device__ __forceinline__ void rhs_elem_simplex(const double* uc, const double* gc, double param, double* acc) {
   using R = ElemRule<DIM>;
   using KC = KuhnChain<DIM, S>;
-  const int m = corner == 0 ? 0
-              : corner == KC::v1 ? 1
-              : corner == KC::vl ? DIM
-              : (DIM == 3 && corner == KC::v2) ? 2 : -1;
-  if (m < 0) return 0.0;
   double uv[DIM + 1], gv[DIM + 1];
   uv[0] = uc[0]; uv[1] = uc[KC::v1]; uv[DIM] = uc[KC::vl];
   gv[0] = gc[0]; gv[1] = gc[KC::v1]; gv[DIM] = gc[KC::vl];
@@ -326,43 +323,70 @@ __device__ __forceinline__ double rhs_elem_simplex(int corner, const double* uc,
   double usum = 0.0, gsum = 0.0;
 #pragma unroll
   for (int k = 0; k <= DIM; ++k) { usum += uv[k]; gsum += gv[k]; }
-  double acc = 0.0;
+  double vsum = 0.0, own[DIM + 1];
+#pragma unroll
+  for (int k = 0; k <= DIM; ++k) own[k] = 0.0;
 #pragma unroll 1
   for (int p = 0; p <= DIM; ++p) {
-    const double uq = elem_interp<DIM>(uv, usum, p);
-    const double gq = elem_interp<DIM>(gv, gsum, p);
-    acc += (p == m ? R::A : R::B) * (gq - NL<KIND>::f(uq, param));
+    const double val = elem_interp<DIM>(gv, gsum, p) - NL<KIND>::f(elem_interp<DIM>(uv, usum, p), param);
+    vsum += val;
+#pragma unroll
+    for (int k = 0; k <= DIM; ++k) own[k] += p == k ? val : 0.0;
   }
-  return acc;
+  // chain vertex k: coordinate A at its own point, B at the others
+  constexpr double D = R::A - R::B;
+  acc[0] += R::B * vsum + D * own[0];
+  acc[KC::v1] += R::B * vsum + D * own[1];
+  if (DIM == 3) acc[KC::v2] += R::B * vsum + D * own[2];
+  acc[KC::vl] += R::B * vsum + D * own[DIM];
 }
 
 template <int DIM, int KIND>
-__global__ void __launch_bounds__(kBlock) k_rhs_elem(Grid g, const ProblemSlot* __restrict__ slot, int nf1, int s,
-                                                     const double* __restrict__ u, double* __restrict__ b,
-                                                     double m) {
+__global__ void __launch_bounds__(kBlock) k_rhs_elem_cells(Grid g, const ProblemSlot* __restrict__ slot, int nf1,
+                                                           int s, const double* __restrict__ u,
+                                                           double* __restrict__ contrib) {
   constexpr int NV = 1 << DIM;
+  const long long n = g.n;
+  const long long ncells = DIM == 2 ? n * n : n * n * n;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  const int i = (int)(c % n), j = (int)((c / n) % n), l = DIM == 3 ? (int)(c / (n * n)) : 0;
+  const double* __restrict__ gl = slot->g;
+  double uc[NV], gc[NV], acc[NV];
+#pragma unroll
+  for (int e = 0; e < NV; ++e) {
+    const int x = i + (e & 1), y = j + ((e >> 1) & 1), z = DIM == 3 ? l + ((e >> 2) & 1) : 0;
+    uc[e] = u[gidx<DIM>(g, x, y, z)];
+    gc[e] = gl[fine_load_index(nf1, s, x, y, z)];
+    acc[e] = 0.0;
+  }
+  const double param = slot->param;
+  rhs_elem_simplex<DIM, KIND, 0>(uc, gc, param, acc);
+  rhs_elem_simplex<DIM, KIND, 1>(uc, gc, param, acc);
+  if constexpr (DIM == 3) {
+    rhs_elem_simplex<DIM, KIND, 2>(uc, gc, param, acc);
+    rhs_elem_simplex<DIM, KIND, 3>(uc, gc, param, acc);
+    rhs_elem_simplex<DIM, KIND, 4>(uc, gc, param, acc);
+    rhs_elem_simplex<DIM, KIND, 5>(uc, gc, param, acc);
+  }
+#pragma unroll
+  for (int e = 0; e < NV; ++e) contrib[e * ncells + c] = acc[e];
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_rhs_elem_nodes(Grid g, const double* __restrict__ contrib,
+                                                           double* __restrict__ b, double mw) {
   int i, j, l;
   if (!node_of_thread<DIM>(g, i, j, l)) return;
-  const double* __restrict__ gl = slot->g;
-  const double param = slot->param;
-  double acc = 0.0;
-#pragma unroll 1
-  for (int e = 0; e < NV; ++e) {
-    // the fine cell whose corner e is this node
-    const int ci = i - (e & 1), cj = j - ((e >> 1) & 1), cl = DIM == 3 ? l - ((e >> 2) & 1) : 0;
-    double uc[NV], gc[NV];
+  const long long n = g.n;
+  const long long ncells = DIM == 2 ? n * n : n * n * n;
+  double sum = 0.0;
 #pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      const int x = ci + (c & 1), y = cj + ((c >> 1) & 1), z = DIM == 3 ? cl + ((c >> 2) & 1) : 0;
-      uc[c] = u[gidx<DIM>(g, x, y, z)];
-      gc[c] = gl[fine_load_index(nf1, s, x, y, z)];
-    }
-    acc += rhs_elem_simplex<DIM, KIND, 0>(e, uc, gc, param) + rhs_elem_simplex<DIM, KIND, 1>(e, uc, gc, param);
-    if constexpr (DIM == 3)
-      acc += (rhs_elem_simplex<DIM, KIND, 2>(e, uc, gc, param) + rhs_elem_simplex<DIM, KIND, 3>(e, uc, gc, param)) +
-             (rhs_elem_simplex<DIM, KIND, 4>(e, uc, gc, param) + rhs_elem_simplex<DIM, KIND, 5>(e, uc, gc, param));
+  for (int e = 0; e < (1 << DIM); ++e) {
+    const long long cell = (i - (e & 1)) + n * ((j - ((e >> 1) & 1)) + (DIM == 3 ? n * (l - ((e >> 2) & 1)) : 0));
+    sum += contrib[e * ncells + cell];
   }
-  b[gidx<DIM>(g, i, j, l)] = m * ElemRule<DIM>::W * acc;
+  b[gidx<DIM>(g, i, j, l)] = mw * sum;
 }
 
 // ---------------------------------------------------------------------------

@@ -22,7 +22,7 @@ void launch_aug_small(size_t lds, hipStream_t st, Grid g, AugShape s, double* ut
 
 template <int DIM, int KIND>
 void launch_rhs_elem(dim3 grid, hipStream_t st, Grid g, const ProblemSlot* slot, int nf1, int fs, const double* u,
-                     double* b, double m);
+                     double* contrib, double* b, double m);
 
 template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM = false>
 void launch_aug_pass(int blocks, int threads, size_t lds, hipStream_t st, Grid g, AugShape s, const double* ut,

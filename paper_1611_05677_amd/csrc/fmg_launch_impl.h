@@ -21,10 +21,15 @@ void launch_aug_small(size_t lds, hipStream_t st, Grid g, AugShape s, double* ut
                                                              newton_max, tol, do_update, fold, next);
 }
 
+// grid: the node grid of the level (second launch); the first launch takes
+// one thread per fine cell.  contrib: 2^d n^d doubles.
 template <int DIM, int KIND>
 void launch_rhs_elem(dim3 grid, hipStream_t st, Grid g, const ProblemSlot* slot, int nf1, int fs, const double* u,
-                     double* b, double m) {
-  k_rhs_elem<DIM, KIND><<<grid, kBlock, 0, st>>>(g, slot, nf1, fs, u, b, m);
+                     double* contrib, double* b, double m) {
+  const long long ncells = DIM == 2 ? (long long)g.n * g.n : (long long)g.n * g.n * g.n;
+  k_rhs_elem_cells<DIM, KIND><<<(unsigned)((ncells + kBlock - 1) / kBlock), kBlock, 0, st>>>(g, slot, nf1, fs, u,
+                                                                                             contrib);
+  k_rhs_elem_nodes<DIM><<<grid, kBlock, 0, st>>>(g, contrib, b, m * ElemRule<DIM>::W);
 }
 
 template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM>
@@ -114,7 +119,7 @@ void launch_transition(dim3 grid, hipStream_t st, TransitionArgs a, const Newton
 #define FMG_INSTANTIATE_ELEM(D, K)                                                                   \
   namespace fmg {                                                                                    \
   template void launch_rhs_elem<D, K>(dim3, hipStream_t, Grid, const ProblemSlot*, int, int,          \
-                                      const double*, double*, double);                              \
+                                      const double*, double*, double*, double);                     \
   template void launch_aug_pass<D, K, true, false, true>(int, int, size_t, hipStream_t, Grid, AugShape, \
                                                          const double*, const ProblemSlot*, int, int,  \
                                                          double, double, const double*, NewtonState*,  \
