@@ -153,7 +153,8 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p, bool host_
     {   // every level: level 1 takes the augmented passes in element mode
       const int nodes_log = d * (k - 1);
       // large levels: 1024-thread (2D) or 512-thread (3D) blocks, fewer of them
-      const bool wide = nodes_log >= (d == 2 ? aug_wide_nodes_log<2>() : aug_wide_nodes_log<3>());
+      const bool wide = ro.o.quadrature == FMG_QUAD_VERTEX &&
+                        nodes_log >= (d == 2 ? aug_wide_nodes_log<2>() : aug_wide_nodes_log<3>());
       const int tlog = wide ? ilog2(d == 2 ? aug_threads<2>() : aug_threads<3>()) : 8;
       const int cap_log = ilog2(std::max(1, (ro.o.aug_max_blocks >> (tlog - 8)) / ncell));
       const int bpc_log = std::max(0, std::min(nodes_log - tlog, cap_log));

@@ -61,12 +61,14 @@ __device__ __forceinline__ void elem_point(int p, double (&s)[3]) {
 }
 
 // Value at point p of the P1 interpolant with chain-vertex values v[0..d].
+// The vertex value v[p] is picked by 0/1 weights, not by a select chain: the
+// compiler turns such a chain into an indexed load from a private array.
 template <int DIM>
 __device__ __forceinline__ double elem_interp(const double (&v)[DIM + 1], double vsum, int p) {
   using R = ElemRule<DIM>;
-  double vp = v[0];
+  double vp = 0.0;
 #pragma unroll
-  for (int k = 1; k <= DIM; ++k) vp = p == k ? v[k] : vp;
+  for (int k = 0; k <= DIM; ++k) vp = fma(p == k ? 1.0 : 0.0, v[k], vp);
   return R::B * vsum + (R::A - R::B) * vp;
 }
 

@@ -331,7 +331,7 @@ __device__ __forceinline__ void rhs_elem_simplex(const double* uc, const double*
     const double val = elem_interp<DIM>(gv, gsum, p) - NL<KIND>::f(elem_interp<DIM>(uv, usum, p), param);
     vsum += val;
 #pragma unroll
-    for (int k = 0; k <= DIM; ++k) own[k] += p == k ? val : 0.0;
+    for (int k = 0; k <= DIM; ++k) own[k] = fma(p == k ? 1.0 : 0.0, val, own[k]);
   }
   // chain vertex k: coordinate A at its own point, B at the others
   constexpr double D = R::A - R::B;
@@ -802,7 +802,8 @@ __device__ __forceinline__ void setup_reduce(const AugShape& s, const double* __
 // least 2^aug_wide_nodes_log fine nodes per coarse cell 1024 (2D) / 512 (3D),
 // so fewer blocks: fewer release/ticket operations and fewer partials for the
 // last block to reduce.  The 3D quadrature needs more registers per thread and
-// stops at 512.
+// stops at 512; the element-rule passes (d+1 points on each of d! simplices
+// per fine cell) always take 256, so that they never spill.
 constexpr int kAugMaxThreads = 1024;
 template <int DIM>
 __host__ __device__ constexpr int aug_threads() { return DIM == 2 ? kAugMaxThreads : 512; }
@@ -834,7 +835,7 @@ __device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShap
 // needs more passes is then left to k_newton_finish.
 // LDS: newton_kernel_lds_doubles(ncell, NQ, N1, blockDim).
 template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM = false>
-__global__ void __launch_bounds__(aug_threads<DIM>()) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
+__global__ void __launch_bounds__(ELEM ? kBlock : aug_threads<DIM>()) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
                                                      const ProblemSlot* __restrict__ slot, int nf1, int fs,
                                                      double scale, double m, const double* __restrict__ A1,
                                                      NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
