@@ -193,12 +193,12 @@ def roofline_live(B, H, dim, workload, reps, stream=None):
     return out
 
 
-def alu_roofline(rows, workload, level, dim):
+def alu_roofline(rows, workload, level, dim, kernel=ALU_KERNEL):
     """Float64 rate of the fine quadrature pass at the finest level: executed
     float64 FLOPs per launch from the committed counter run (VALU float64
     instructions x 64 lanes, FMA counted twice) over the mean launch duration
     from the event-bracketed profile of the same solve."""
-    name, fname = ALU_KERNEL
+    name, fname = kernel
     r = [x for x in rows if x["kernel"] == name and x["level"] == level]
     if not r or r[0]["launches"] == 0:
         return None
@@ -207,7 +207,7 @@ def alu_roofline(rows, workload, level, dim):
     flops = e["fp64_flop_per_launch"] if e else None
     out = {"bound": "alu", "kernel": name, "level": level, "avg_launch_us": avg_ms * 1e3,
            "launches": r[0]["launches"], "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-           "achieved": None, "frac": None, "flop_per_launch": flops,
+           "achieved": None, "frac": None, "traffic": None, "flop_per_launch": flops,
            "flop_source": os.path.relpath(FLOPS_FILE, ROOT) if e else None,
            "fine_nodes": r[0]["nodes"], "bytes_per_launch": r[0]["bytes"]}
     if flops:
@@ -509,6 +509,134 @@ def examples_mode(args, B, W, torch):
     }
 
 
+ELEMENT_DESC = ("element rule: the cube256 problem (3D unit cube, Kuhn tetrahedra, coarse 4^3 refined 6 times, "
+                "256^3, 16,581,375 DOFs, -Lap u + u + sin u = g, g manufactured from u = sin sin sin, m = 2, p = 1) "
+                "with the L2 pairings (f(u), v) and (g, v) taken by a degree-2 rule on every fine tetrahedron "
+                "(4 points), u_h, v_h and g as P1 interpolants, in the linearised load, the augmented problem "
+                "and level 1")
+# the element-rule quadrature pass (setup excluded) at the finest level
+ALU_KERNEL_ELEMENT = ("aug_pass", "fmg_elem.h")
+
+
+def element_cpu_baseline(W):
+    """The element-rule oracle O2 on the host, single thread, on a bounded
+    sample: the same manufactured problem two levels coarser (64^3).  One
+    untimed solve builds the per-level element rules (the analogue of the
+    hierarchy creation); the second is timed."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.nonlinear import Nonlinearity
+    from oracle.o2 import Hierarchy as O2H
+    from oracle.o2 import Options as O2Options
+    from oracle.o2 import fmg as o2_fmg
+    S = W.cube_u_plus_sin(4)
+    with threadpool_limits(limits=1):
+        H = O2H(S.dim, S.coarse_cells, S.refinements)
+        opts = O2Options(quadrature="element")
+        nl = Nonlinearity(S.f_kind, S.f_param)
+        o2_fmg(H, S.g_nodes, nl, opts)
+        t0 = time.perf_counter()
+        o2_fmg(H, S.g_nodes, nl, opts)
+        o2_s = time.perf_counter() - t0
+    return {"value": S.interior_dofs / o2_s, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"O2 with the element rule (scipy CSR, the oracle's replica of the FMG scheme): {S.name} "
+                      f"({S.interior_dofs} DOFs, the benchmark's problem two levels coarser), one solve "
+                      f"{o2_s:.2f} s after an untimed one that builds the element rules",
+            "o2_solve_s": o2_s, "o2_dofs": S.interior_dofs, "cpu_model": _cpu_model(),
+            "threads_used": "1 (scipy sparse kernels are single-threaded; BLAS pools limited to 1)"}
+
+
+def element_mode(args, B, W, torch):
+    """The element-rule reading (fmg_options.quadrature = FMG_QUAD_ELEMENT) on
+    the largest configuration: float64 and mixed throughput and latency, the
+    accuracy gate against ubar_h of the same reading (the library's converged
+    mode, which the tests match to the element-rule oracle O1), the distance to
+    the vertex-rule solution, the float64 ALU roofline of the element
+    quadrature pass and the per-kernel profile."""
+    depth = 6
+    P = W.cube_u_plus_sin(depth)
+    g = torch.from_numpy(P.g_nodes).to("cuda:0")
+    EL = B.FMG_QUAD_ELEMENT
+    if args.only:
+        # trace and counter runs: the timed solves of one precision only
+        uc = uv = np.zeros(P.g_nodes.shape)
+        crep = {"status": None, "extra_steps": None, "last_update_rel": None}
+    else:
+        Hc = B.Hierarchy(3, 4, depth, B.default_options(3, mode=B.FMG_CONVERGED, quadrature=EL), device="cuda:0")
+        uct, crep = Hc.solve(g, P.f_kind, P.f_param)
+        Hc.close()
+        uc = uct.cpu().numpy()
+        Hv = B.Hierarchy(3, 4, depth, B.default_options(3), device="cuda:0")
+        uvt, _ = Hv.solve(g, P.f_kind, P.f_param)
+        Hv.close()
+        uv = uvt.cpu().numpy()
+    disc = nodal(P, uc - P.u_exact_nodes)
+    stream = torch.cuda.current_stream()
+    modes, rows = {}, None
+    for name, prec in (("fp64", B.FMG_FP64), ("mixed", B.FMG_MIXED)):
+        if args.only and name != args.only:
+            continue
+        H = B.Hierarchy(3, 4, depth, B.default_options(3, precision=prec, quadrature=EL), device="cuda:0")
+        out = torch.empty(H.nodes(), dtype=torch.float64, device="cuda:0")
+        for _ in range(args.warmup):
+            H.solve_async(g, P.f_kind, P.f_param, out)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            H.solve_async(g, P.f_kind, P.f_param, out)
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = [a.elapsed_time(b) for a, b in ev]
+        rep = H.report()
+        u = out.cpu().numpy()
+        exact_err, alg = nodal(P, u - P.u_exact_nodes), nodal(P, u - uc)
+        res = {"dof_per_s": P.interior_dofs / (wall / args.steps), "ms_per_solve": 1e3 * wall / args.steps,
+               "latency_ms_p50": percentile(lat, 50), "latency_ms_p99": percentile(lat, 99),
+               "status": rep["status"], "newton_iters": rep["newton_iters"], "level1_iters": rep["level1_iters"],
+               "err_vs_exact_nodal_l2": exact_err, "disc_nodal_l2": disc, "alg_nodal_l2": alg,
+               "alg_over_disc": alg / disc,
+               "gate_total_le_1.1disc": bool(exact_err <= 1.1 * disc),
+               "gate_alg_le_0.5disc": bool(alg <= 0.5 * disc),
+               "vertex_rule_distance_over_disc": nodal(P, u - uv) / disc}
+        res["gate_pass"] = bool(res["gate_total_le_1.1disc"] and res["gate_alg_le_0.5disc"] and rep["status"] == 0)
+        if name == "fp64" and not args.no_profile:
+            total_ms, rows = profile_mode(B, H, P, g, torch)
+            res["profile_event_ms_total"] = total_ms
+            res["profile_rows"] = sorted(rows, key=lambda r: -r["ms"])[:30]
+        H.close()
+        modes[name] = res
+        log(f"element {name}: {res['ms_per_solve']:.3f} ms/solve, {res['dof_per_s'] / 1e9:.3f} GDOF/s, "
+            f"alg/disc {res['alg_over_disc']:.3f}, gate {res['gate_pass']}")
+    alu = alu_roofline(rows, "cube256_element", P.n_levels, 3, ALU_KERNEL_ELEMENT) if rows else None
+    if args.only:
+        return {"only": args.only, "modes": {k: {q: v for q, v in m.items() if q != "profile_rows"}
+                                             for k, m in modes.items()}}
+    primary = modes["fp64"]
+    line = {
+        "metric": METRIC, "value": primary["dof_per_s"], "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": primary["ms_per_solve"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": ELEMENT_DESC, "dofs": P.interior_dofs, "levels": P.n_levels,
+                   "precision_of_value": "fp64 (plain)"},
+        "latency_ms_p50": primary["latency_ms_p50"], "latency_ms_p99": primary["latency_ms_p99"],
+        "gate_pass": primary["gate_pass"],
+        "mixed": {k: modes["mixed"][k] for k in ("dof_per_s", "ms_per_solve", "latency_ms_p50",
+                                                 "latency_ms_p99", "gate_pass", "alg_over_disc")},
+        "mixed_speedup_vs_fp64": modes["mixed"]["dof_per_s"] / primary["dof_per_s"],
+        "converged_reference": {"status": crep["status"], "extra_steps": crep["extra_steps"],
+                                "last_update_rel": crep["last_update_rel"],
+                                "source": "the library's converged mode, element rule"},
+        "modes": modes,
+        "roofline": alu,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = element_cpu_baseline(W)
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -518,7 +646,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 2D 2048^2 record")
     ap.add_argument("--workload", default="cube256",
-                    choices=sorted(WORKLOADS) + ["batch64", "serve", "examples"])
+                    choices=sorted(WORKLOADS) + ["batch64", "serve", "examples", "element"])
     ap.add_argument("--max-depth", type=int, default=6, help="examples: deepest refinement")
     ap.add_argument("--requests", type=int, default=4000, help="serve: requests in the trace")
     ap.add_argument("--inflight", type=int, default=8, help="serve: concurrent solves")
@@ -543,8 +671,9 @@ def main():
     from paper_1611_05677_amd import binding as B
     from paper_1611_05677_amd import workloads as W
 
-    if args.workload in ("batch64", "serve", "examples"):
-        mode = {"batch64": batch_mode, "serve": serve_mode, "examples": examples_mode}[args.workload]
+    if args.workload in ("batch64", "serve", "examples", "element"):
+        mode = {"batch64": batch_mode, "serve": serve_mode, "examples": examples_mode,
+                "element": element_mode}[args.workload]
         line = mode(args, B, W, torch)
         print(json.dumps(line), flush=True)
         return
