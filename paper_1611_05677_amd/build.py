@@ -51,6 +51,16 @@ def asan_runtime() -> str:
     return out.stdout.strip()
 
 
+def is_stale(lib: str) -> bool:
+    """True if `lib` is missing or older than a device source or the C header."""
+    if not os.path.exists(lib):
+        return True
+    t = os.path.getmtime(lib)
+    srcs = [os.path.join(CSRC, f) for f in os.listdir(CSRC)]
+    srcs.append(os.path.join(os.path.dirname(os.path.dirname(CSRC)), "include", "fmg.h"))
+    return any(os.path.getmtime(f) > t for f in srcs if os.path.isfile(f))
+
+
 def build_host_sanitized(verbose: bool = False) -> str:
     return build(verbose, lib=LIB_HOSTSAN, extra=HOSTSAN_FLAGS)
 

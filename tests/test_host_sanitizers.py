@@ -17,7 +17,7 @@ from paper_1611_05677_amd import build as build_mod  # noqa: E402
 
 @pytest.mark.slow
 def test_abi_tests_pass_under_host_sanitizers():
-    if not os.path.exists(build_mod.LIB_HOSTSAN):
+    if build_mod.is_stale(build_mod.LIB_HOSTSAN):
         build_mod.build_host_sanitized()
     rt = build_mod.asan_runtime()
     assert os.path.exists(rt), rt
