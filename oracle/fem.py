@@ -14,6 +14,10 @@ Algorithm 3.1.
 
 Everything is assembled element by element from the vertex coordinates; no
 stencil formula is used, so the stencil closed forms are independent checks.
+
+Variable coefficient (the operator A(x) of eq. "semilinear equation", read as
+kappa(x) I with kappa > 0 constant on every cell of the mesh): the local
+stiffness of a simplex is multiplied by the kappa of the cell that contains it.
 """
 from __future__ import annotations
 
@@ -47,11 +51,23 @@ def simplex_geometry(X: np.ndarray):
 ELEMENT_CHUNK = 1 << 24
 
 
-def _assemble_chunk(mesh: Mesh, T: np.ndarray, N: int):
+def cell_of_simplex(mesh: Mesh, T: np.ndarray) -> np.ndarray:
+    """Index (x fastest) of the cell containing each simplex: the cell whose
+    lower corner is the componentwise minimum of the simplex's vertices."""
+    low = mesh.ijk[T].min(axis=1)                      # (E, d)
+    idx = np.zeros(T.shape[0], dtype=np.int64)
+    for a in range(mesh.dim - 1, -1, -1):
+        idx = idx * mesh.n + low[:, a]
+    return idx
+
+
+def _assemble_chunk(mesh: Mesh, T: np.ndarray, N: int, kappa=None):
     X = mesh.coords[T]
     grads, vol, _ = simplex_geometry(X)
     d = mesh.dim
     Kloc = vol[:, None, None] * np.einsum("eia,eja->eij", grads, grads)
+    if kappa is not None:
+        Kloc = Kloc * np.asarray(kappa, dtype=np.float64)[cell_of_simplex(mesh, T)][:, None, None]
     rows = np.repeat(T, d + 1, axis=1).reshape(-1)
     cols = np.tile(T, (1, d + 1)).reshape(-1)
     K = sp.csr_matrix((Kloc.reshape(-1), (rows, cols)), shape=(N, N))
@@ -59,10 +75,11 @@ def _assemble_chunk(mesh: Mesh, T: np.ndarray, N: int):
     return K, vol
 
 
-def assemble_full(mesh: Mesh):
+def assemble_full(mesh: Mesh, kappa=None):
     """Full stiffness matrix (all nodes, CSR) and lumped mass vector.
 
-    K_T[i,j] = |T| grad(lambda_i) . grad(lambda_j)  (local P1 stiffness).
+    K_T[i,j] = kappa_T |T| grad(lambda_i) . grad(lambda_j)  (local P1 stiffness;
+    kappa per cell, x fastest, or None for kappa = 1).
     """
     d = mesh.dim
     N = mesh.coords.shape[0]
@@ -70,19 +87,19 @@ def assemble_full(mesh: Mesh):
     K = None
     for s in range(0, mesh.simplices.shape[0], ELEMENT_CHUNK):
         T = mesh.simplices[s:s + ELEMENT_CHUNK]
-        Kc, vol = _assemble_chunk(mesh, T, N)
+        Kc, vol = _assemble_chunk(mesh, T, N, kappa)
         K = Kc if K is None else (K + Kc).tocsr()
         del Kc
         np.add.at(mass, T.reshape(-1), np.repeat(vol / (d + 1), d + 1))
     return K, mass
 
 
-def assemble_interior(mesh: Mesh):
+def assemble_interior(mesh: Mesh, kappa=None):
     """Stiffness A (interior x interior, CSR) and lumped mass m on interior nodes.
 
     Dirichlet nodes are eliminated (u = 0 on the boundary, Section 2).
     """
-    K, mass = assemble_full(mesh)
+    K, mass = assemble_full(mesh, kappa)
     I = mesh.interior
     A = K[I][:, I].tocsr()
     A.sort_indices()

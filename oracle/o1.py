@@ -14,6 +14,10 @@ Stopping: ||dU||_2 <= tol ||U||_2 or stagnation of ||dU|| (update norms, not
 residual norms, because the relative residual has a rounding floor near
 1e-10 at a few million unknowns).
 
+With kappa (per cell) the operator is -div(kappa grad u); with f_weight (c at
+every node, c >= 0) the nonlinearity is f(x, u) = c(x) f(u), taken by the
+vertex rule as m_j c_j f(U_j).
+
 With quadrature="element" the pairings use the degree-2 element rule of
 oracle/quadrature.py instead: A U + N(U) = G with N_i = (f(u_h), phi_i),
 G_i = (g_I, phi_i), and Newton matrix A + K(f'(u_h)) (the f'-weighted mass
@@ -69,27 +73,31 @@ def _linear_solver(dim, N):
 
 def solve_fine(dim: int, n: int, g_nodes: np.ndarray, nl: Nonlinearity,
                U0=None, tol: float = 1e-14, max_iter: int = 60,
-               mesh: Mesh | None = None, A=None, m=None, quadrature: str = "vertex") -> O1Result:
-    """ubar_h on the (0,1)^dim mesh with n cells per side; g at all nodes."""
+               mesh: Mesh | None = None, A=None, m=None, quadrature: str = "vertex",
+               kappa=None, f_weight=None) -> O1Result:
+    """ubar_h on the (0,1)^dim mesh with n cells per side; g (and c) at all nodes."""
     mesh = mesh if mesh is not None else unit_mesh(dim, n)
     if A is None or m is None:
-        A, m = assemble_interior(mesh)
+        A, m = assemble_interior(mesh, kappa)
     N = mesh.interior.size
     if quadrature == "vertex":
         g = np.asarray(g_nodes, dtype=np.float64)[mesh.interior]
         mg = m * g
+        mc = m if f_weight is None else m * np.asarray(f_weight, dtype=np.float64)[mesh.interior]
 
         def grad_hess(U):
-            R = A @ U + m * nl.f(U) - mg
-            J = (A + sp.diags(m * nl.df(U))).tocsr()
+            R = A @ U + mc * nl.f(U) - mg
+            J = (A + sp.diags(mc * nl.df(U))).tocsr()
             return R, J
 
         def energy(U):
             t1 = 0.5 * float(U @ (A @ U))
-            t2 = float(m @ nl.F(U))
+            t2 = float(mc @ nl.F(U))
             t3 = float(mg @ U)
             return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
     elif quadrature == "element":
+        if f_weight is not None:
+            raise ValueError("the element rule is read with c = 1 only")
         I = mesh.interior
         Qd = ElementQuadrature(mesh)
         mg = Qd.load(g_nodes)[I]

@@ -29,6 +29,11 @@ Readings of what the paper leaves open (shared with the GPU library):
     alpha row of the Newton matrix is <= 1e-12 of its diagonal entry -- the
     alpha component of the step is set to zero and the w block solved alone.
   * Level 1 (Algorithm 3.2, step 1) is solved by the same Newton iteration.
+  * Variable coefficient (A(x) = kappa(x) I, kappa given per cell of the finest
+    mesh): every coarser level's cell takes the mean of its 2^d children's
+    kappa, and A_k is assembled with it (rediscretisation, not P^T A P).  An
+    x-dependent f(x, u) = c(x) f(u) takes c at the level's nodes (nodes of the
+    finest mesh), in the vertex rule m_j c_j f(u_j).
 """
 from __future__ import annotations
 
@@ -86,6 +91,19 @@ class Options:
         return pre, post
 
 
+def level_kappas(dim: int, n: int, refinements: int, kappa):
+    """Cell coefficients of every level, coarsest first: the finest is kappa
+    (n^d values, x fastest); each coarser cell is the mean of its 2^d children."""
+    if kappa is None:
+        return [None] * (refinements + 1)
+    out = [np.asarray(kappa, dtype=np.float64).reshape((n,) * dim)]   # axes (z,) y, x
+    for _ in range(refinements):
+        f = out[-1]
+        c = f.reshape(*sum(([s // 2, 2] for s in f.shape), []))
+        out.append(c.mean(axis=tuple(range(1, 2 * dim, 2))))
+    return [a.reshape(-1) for a in out[::-1]]
+
+
 @dataclass
 class Level:
     mesh: Mesh
@@ -99,13 +117,14 @@ class Level:
 class Hierarchy:
     """Meshes T_{h_1} .. T_{h_n}, matrices A_k, masses m_k, P_k and Q_k."""
 
-    def __init__(self, dim: int, coarse_cells: int, refinements: int):
+    def __init__(self, dim: int, coarse_cells: int, refinements: int, kappa=None):
         self.dim = dim
         self.coarse_cells = coarse_cells
         self.levels: list[Level] = []
+        kap = level_kappas(dim, coarse_cells * 2 ** refinements, refinements, kappa)
         for k in range(refinements + 1):
             mesh = unit_mesh(dim, coarse_cells * 2 ** k)
-            A, m = assemble_interior(mesh)
+            A, m = assemble_interior(mesh, kap[k])
             lev = Level(mesh, A, m, A.diagonal().copy())
             if k == 0:
                 lev.Q = sp.identity(mesh.interior.size, format="csr")
@@ -199,7 +218,7 @@ def _solve_augmented(J, R):
 
 
 def level1_solve(H: Hierarchy, g1: np.ndarray, nl: Nonlinearity, opts: Options,
-                 g1_full: np.ndarray | None = None):
+                 g1_full: np.ndarray | None = None, c1: np.ndarray | None = None):
     """Algorithm 3.2, step 1: a(u, v) + (f(u), v) = (g, v) on V_{h_1}.
     g1: interior nodal load; g1_full: load at all level-1 nodes (element rule)."""
     lev = H.levels[0]
@@ -218,12 +237,13 @@ def level1_solve(H: Hierarchy, g1: np.ndarray, nl: Nonlinearity, opts: Options,
             return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
     else:
         mg = m * g1
+        mc = m if c1 is None else m * c1
 
         def grad_hess(U):
-            return A @ U + m * nl.f(U) - mg, A + np.diag(m * nl.df(U))
+            return A @ U + mc * nl.f(U) - mg, A + np.diag(mc * nl.df(U))
 
         def energy(U):
-            t1, t2, t3 = 0.5 * U @ A @ U, m @ nl.F(U), mg @ U
+            t1, t2, t3 = 0.5 * U @ A @ U, mc @ nl.F(U), mg @ U
             return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
 
     U, it, ok = newton_minimize(np.zeros(A.shape[0]), grad_hess, energy, _solve_dense,
@@ -233,7 +253,8 @@ def level1_solve(H: Hierarchy, g1: np.ndarray, nl: Nonlinearity, opts: Options,
 
 
 def augmented_solve(H: Hierarchy, k: int, ut: np.ndarray, g_k: np.ndarray,
-                    nl: Nonlinearity, opts: Options, g_full: np.ndarray | None = None):
+                    nl: Nonlinearity, opts: Options, g_full: np.ndarray | None = None,
+                    c_k: np.ndarray | None = None):
     """Algorithm 3.1, step 2: solve eq. "coarse problem" on V_H + span{u~}.
 
     Basis B = [Q_k, u~] (columns are fine nodal vectors), z = B y, y = (w, alpha).
@@ -260,17 +281,18 @@ def augmented_solve(H: Hierarchy, k: int, ut: np.ndarray, g_k: np.ndarray,
             return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
     else:
         mg = m * g_k
+        mc = m if c_k is None else m * c_k
         Btmg = B.T @ mg
 
         def grad_hess(y):
             z = B @ y
-            R = BtAB @ y + B.T @ (m * nl.f(z)) - Btmg
-            J = BtAB + (B.T @ sp.diags(m * nl.df(z)) @ B).toarray()
+            R = BtAB @ y + B.T @ (mc * nl.f(z)) - Btmg
+            J = BtAB + (B.T @ sp.diags(mc * nl.df(z)) @ B).toarray()
             return R, J
 
         def energy(y):
             z = B @ y
-            t1, t2, t3 = 0.5 * y @ BtAB @ y, m @ nl.F(z), Btmg @ y
+            t1, t2, t3 = 0.5 * y @ BtAB @ y, mc @ nl.F(z), Btmg @ y
             return t1 + t2 - t3, abs(t1) + abs(t2) + abs(t3)
 
     y0 = np.zeros(Q.shape[1] + 1)
@@ -291,7 +313,7 @@ class StepInfo:
 
 def correction_step(H: Hierarchy, k: int, u: np.ndarray, g_k: np.ndarray,
                     nl: Nonlinearity, opts: Options, info: list | None = None,
-                    g_full: np.ndarray | None = None):
+                    g_full: np.ndarray | None = None, c_k: np.ndarray | None = None):
     """Algorithm 3.1: u^(l+1) = SemilinearMG(V_H, u^(l), V_{h_k}).
     g_k: interior nodal load; g_full: load at all level-k nodes (element rule)."""
     lev = H.levels[k]
@@ -301,12 +323,12 @@ def correction_step(H: Hierarchy, k: int, u: np.ndarray, g_k: np.ndarray,
         Qd, I = H.quad(k), lev.mesh.interior
         b = Qd.load(g_full)[I] - Qd.nonlinear(full_vector(lev.mesh, u), nl)[I]
     else:
-        b = lev.m * (g_k - nl.f(u))
+        b = lev.m * (g_k - (nl.f(u) if c_k is None else c_k * nl.f(u)))
     ut = u.copy()
     for _ in range(opts.m_vcycles):
         ut = vcycle(H, k, ut, b, pre, post)
     # Step 2: semilinear problem on V_H + span{u~}
-    unew, y, it, ok = augmented_solve(H, k, ut, g_k, nl, opts, g_full)
+    unew, y, it, ok = augmented_solve(H, k, ut, g_k, nl, opts, g_full, c_k)
     if info is not None:
         info.append(StepInfo(k + 1, it, ok, float(y[-1])))
     return unew, ut
@@ -330,7 +352,8 @@ class FMGResult:
 
 
 def fmg(H: Hierarchy, g_fine_nodes: np.ndarray, nl: Nonlinearity,
-        opts: Options | None = None, converged: bool = False) -> FMGResult:
+        opts: Options | None = None, converged: bool = False,
+        f_weight: np.ndarray | None = None) -> FMGResult:
     """Algorithm 3.2 on levels 1..n; optionally keep correcting on level n until
     ||du||_2 <= converged_tol ||u||_2 (converged mode, which tends to ubar_h)."""
     opts = opts or Options()
@@ -340,20 +363,26 @@ def fmg(H: Hierarchy, g_fine_nodes: np.ndarray, nl: Nonlinearity,
     def g_full(k):
         return H.g_full_on_level(g_fine_nodes, k) if element else None
 
-    u, it, _ = level1_solve(H, H.g_on_level(g_fine_nodes, 0), nl, opts, g_full(0))
+    if element and f_weight is not None:
+        raise ValueError("the element rule is read with c = 1 only")
+
+    def c_on(k):
+        return None if f_weight is None else H.g_on_level(f_weight, k)
+
+    u, it, _ = level1_solve(H, H.g_on_level(g_fine_nodes, 0), nl, opts, g_full(0), c_on(0))
     res.level1_iters = it
     for k in range(1, H.n_levels):
         u = H.levels[k].P @ u                     # u^(0) = u_{h_{k-1}}
         g_k, gf = H.g_on_level(g_fine_nodes, k), g_full(k)
         for _ in range(opts.p_steps):
-            u, _ = correction_step(H, k, u, g_k, nl, opts, res.steps, gf)
+            u, _ = correction_step(H, k, u, g_k, nl, opts, res.steps, gf, c_on(k))
     if converged:
         k = H.n_levels - 1
         g_k, gf = H.g_on_level(g_fine_nodes, k), g_full(k)
         prev = np.inf
         res.converged_ok = False
         for s in range(opts.converged_max_steps):
-            unew, _ = correction_step(H, k, u, g_k, nl, opts, None, gf)
+            unew, _ = correction_step(H, k, u, g_k, nl, opts, None, gf, c_on(k))
             du = np.linalg.norm(unew - u)
             u = unew
             res.extra_steps = s + 1

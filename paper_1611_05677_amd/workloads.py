@@ -100,6 +100,11 @@ class Problem:
     u_exact: Optional[Callable] = None   # u(*coords) -> array, for element norms
     grad_u_exact: Optional[Callable] = None
     meta: dict = field(default_factory=dict)
+    # variable coefficients: kappa > 0 per cell of the finest mesh (n^d, x fastest
+    # over the cells' lower corners) and the weight c >= 0 of f(x, u) = c(x) f(u)
+    # at the finest nodes ((n+1)^d); None means 1
+    kappa_cells: Optional[np.ndarray] = None
+    f_weight_nodes: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
@@ -359,3 +364,58 @@ SKETCH_ROWS = 16
 def sketch_row(count: int, i: int, seed: int = SKETCH_SEED) -> np.ndarray:
     """Weights of sketch row i for vectors of `count` entries."""
     return np.random.default_rng([seed, i]).standard_normal(count)
+
+
+# ---------------------------------------------------------------------------
+# Variable coefficients: -div(kappa grad u) + c(x) f(u) = g.
+# ---------------------------------------------------------------------------
+
+def _cell_centres(d: int, n: int) -> list[np.ndarray]:
+    """Centre coordinates of the n^d cells (x fastest), one array per axis."""
+    t = (np.arange(n, dtype=np.float64) + 0.5) / n
+    idx = np.indices((n,) * d)
+    return [t[idx[d - 1 - a]].reshape(-1) for a in range(d)]
+
+
+def variable_coefficient(name: str, dim: int, coarse_cells: int, refinements: int,
+                         f_kind: int, f_param: float = 0.0) -> Problem:
+    """u = prod sin(pi x_i), kappa(x) = 1 + s(x)/2 with s = prod sin(pi x_i)
+    (sampled at the cell centres), c(x) = 1 + cos(pi x_1)/2 at the nodes, and
+    g = -div(kappa grad u) + c f(u) = kappa d pi^2 s - |grad s|^2 / 2 + c f(s)
+    at the nodes (closed forms)."""
+    n = coarse_cells * 2 ** refinements
+    X = _mesh(dim, n)
+    s_ = np.ones_like(X[0])
+    for xi in X:
+        s_ = s_ * np.sin(PI * xi)
+    grad2 = np.zeros_like(X[0])
+    for a in range(dim):
+        t = PI * np.cos(PI * X[a])
+        for b in range(dim):
+            if b != a:
+                t = t * np.sin(PI * X[b])
+        grad2 += t * t
+    kap_nodes = 1.0 + 0.5 * s_
+    c = 1.0 + 0.5 * np.cos(PI * X[0])
+    g = kap_nodes * dim * PI ** 2 * s_ - 0.5 * grad2 + c * _f_closed(f_kind, f_param, s_)
+    C = _cell_centres(dim, n)
+    sc = np.ones_like(C[0])
+    for ci in C:
+        sc = sc * np.sin(PI * ci)
+    return Problem(name, dim, coarse_cells, refinements, f_kind, f_param, g_nodes=np.ascontiguousarray(g),
+                   u_exact_nodes=s_, kappa_cells=np.ascontiguousarray(1.0 + 0.5 * sc),
+                   f_weight_nodes=np.ascontiguousarray(c), meta={"solution": "sin", "kappa": "1 + s/2"})
+
+
+def random_coefficient(name: str, dim: int, coarse_cells: int, refinements: int, f_kind: int, seed,
+                       contrast: float = 10.0, f_param: float = 0.0) -> Problem:
+    """kappa piecewise constant on the cells, log-uniform in [1, contrast]
+    (PCG64 seeded); c uniform in [0, 2] at the nodes; a random-Fourier load."""
+    rng = np.random.default_rng(seed)
+    n = coarse_cells * 2 ** refinements
+    P = fourier_problem(name, dim, coarse_cells, refinements, f_kind, [int(x) for x in np.atleast_1d(seed)] + [7],
+                        f_param=f_param)
+    P.kappa_cells = np.exp(rng.uniform(0.0, np.log(contrast), size=n ** dim))
+    P.f_weight_nodes = rng.uniform(0.0, 2.0, size=(n + 1) ** dim)
+    P.meta.update({"kappa": f"log-uniform [1, {contrast:g}] per cell", "c": "uniform [0, 2] per node"})
+    return P
