@@ -15,9 +15,13 @@ Algorithm 3.1.
 Everything is assembled element by element from the vertex coordinates; no
 stencil formula is used, so the stencil closed forms are independent checks.
 
-Variable coefficient (the operator A(x) of eq. "semilinear equation", read as
-kappa(x) I with kappa > 0 constant on every cell of the mesh): the local
-stiffness of a simplex is multiplied by the kappa of the cell that contains it.
+Variable coefficient (the symmetric positive definite matrix A(x) of eq.
+"semilinear equation"), read as constant on every cell of the mesh: the local
+stiffness of a simplex T is |T| grad(lambda_i)^T A_T grad(lambda_j) with A_T
+the matrix of the cell that contains T.  A coefficient array is either
+kappa per cell (A = kappa I) or the d(d+1)/2 upper-triangle components per
+cell, row by row (2D: a11, a12, a22; 3D: a11, a12, a13, a22, a23, a33), as an
+array (components, cells); cells are numbered x fastest by lower corner.
 """
 from __future__ import annotations
 
@@ -61,13 +65,34 @@ def cell_of_simplex(mesh: Mesh, T: np.ndarray) -> np.ndarray:
     return idx
 
 
-def _assemble_chunk(mesh: Mesh, T: np.ndarray, N: int, kappa=None):
+def coefficient_tensors(dim: int, coef) -> np.ndarray:
+    """(cells, d, d) symmetric matrices from a coefficient array (kappa per
+    cell, or upper-triangle components per cell)."""
+    c = np.asarray(coef, dtype=np.float64)
+    if c.ndim == 1:
+        return c[:, None, None] * np.eye(dim)[None]
+    ncomp = dim * (dim + 1) // 2
+    if c.shape[0] != ncomp:
+        raise ValueError(f"expected {ncomp} components per cell, got {c.shape[0]}")
+    out = np.empty((c.shape[1], dim, dim))
+    q = 0
+    for a in range(dim):
+        for b in range(a, dim):
+            out[:, a, b] = c[q]
+            out[:, b, a] = c[q]
+            q += 1
+    return out
+
+
+def _assemble_chunk(mesh: Mesh, T: np.ndarray, N: int, coef=None):
     X = mesh.coords[T]
     grads, vol, _ = simplex_geometry(X)
     d = mesh.dim
-    Kloc = vol[:, None, None] * np.einsum("eia,eja->eij", grads, grads)
-    if kappa is not None:
-        Kloc = Kloc * np.asarray(kappa, dtype=np.float64)[cell_of_simplex(mesh, T)][:, None, None]
+    if coef is None:
+        Kloc = vol[:, None, None] * np.einsum("eia,eja->eij", grads, grads)
+    else:
+        At = coefficient_tensors(d, coef)[cell_of_simplex(mesh, T)]
+        Kloc = vol[:, None, None] * np.einsum("eia,eab,ejb->eij", grads, At, grads)
     rows = np.repeat(T, d + 1, axis=1).reshape(-1)
     cols = np.tile(T, (1, d + 1)).reshape(-1)
     K = sp.csr_matrix((Kloc.reshape(-1), (rows, cols)), shape=(N, N))
@@ -75,11 +100,11 @@ def _assemble_chunk(mesh: Mesh, T: np.ndarray, N: int, kappa=None):
     return K, vol
 
 
-def assemble_full(mesh: Mesh, kappa=None):
+def assemble_full(mesh: Mesh, coef=None):
     """Full stiffness matrix (all nodes, CSR) and lumped mass vector.
 
-    K_T[i,j] = kappa_T |T| grad(lambda_i) . grad(lambda_j)  (local P1 stiffness;
-    kappa per cell, x fastest, or None for kappa = 1).
+    K_T[i,j] = |T| grad(lambda_i)^T A_T grad(lambda_j)  (local P1 stiffness;
+    coef per cell as described above, or None for A = I).
     """
     d = mesh.dim
     N = mesh.coords.shape[0]
@@ -87,19 +112,19 @@ def assemble_full(mesh: Mesh, kappa=None):
     K = None
     for s in range(0, mesh.simplices.shape[0], ELEMENT_CHUNK):
         T = mesh.simplices[s:s + ELEMENT_CHUNK]
-        Kc, vol = _assemble_chunk(mesh, T, N, kappa)
+        Kc, vol = _assemble_chunk(mesh, T, N, coef)
         K = Kc if K is None else (K + Kc).tocsr()
         del Kc
         np.add.at(mass, T.reshape(-1), np.repeat(vol / (d + 1), d + 1))
     return K, mass
 
 
-def assemble_interior(mesh: Mesh, kappa=None):
+def assemble_interior(mesh: Mesh, coef=None):
     """Stiffness A (interior x interior, CSR) and lumped mass m on interior nodes.
 
     Dirichlet nodes are eliminated (u = 0 on the boundary, Section 2).
     """
-    K, mass = assemble_full(mesh, kappa)
+    K, mass = assemble_full(mesh, coef)
     I = mesh.interior
     A = K[I][:, I].tocsr()
     A.sort_indices()

@@ -14,9 +14,9 @@ Stopping: ||dU||_2 <= tol ||U||_2 or stagnation of ||dU|| (update norms, not
 residual norms, because the relative residual has a rounding floor near
 1e-10 at a few million unknowns).
 
-With kappa (per cell) the operator is -div(kappa grad u); with f_weight (c at
-every node, c >= 0) the nonlinearity is f(x, u) = c(x) f(u), taken by the
-vertex rule as m_j c_j f(U_j).
+With coef (the matrix A(x) per cell, oracle/fem.py) the operator is
+-div(A grad u); with f_weight (c at every node, c >= 0) the nonlinearity is
+f(x, u) = c(x) f(u), taken by the vertex rule as m_j c_j f(U_j).
 
 With quadrature="element" the pairings use the degree-2 element rule of
 oracle/quadrature.py instead: A U + N(U) = G with N_i = (f(u_h), phi_i),
@@ -74,11 +74,11 @@ def _linear_solver(dim, N):
 def solve_fine(dim: int, n: int, g_nodes: np.ndarray, nl: Nonlinearity,
                U0=None, tol: float = 1e-14, max_iter: int = 60,
                mesh: Mesh | None = None, A=None, m=None, quadrature: str = "vertex",
-               kappa=None, f_weight=None) -> O1Result:
+               coef=None, f_weight=None) -> O1Result:
     """ubar_h on the (0,1)^dim mesh with n cells per side; g (and c) at all nodes."""
     mesh = mesh if mesh is not None else unit_mesh(dim, n)
     if A is None or m is None:
-        A, m = assemble_interior(mesh, kappa)
+        A, m = assemble_interior(mesh, coef)
     N = mesh.interior.size
     if quadrature == "vertex":
         g = np.asarray(g_nodes, dtype=np.float64)[mesh.interior]

@@ -29,11 +29,13 @@ Readings of what the paper leaves open (shared with the GPU library):
     alpha row of the Newton matrix is <= 1e-12 of its diagonal entry -- the
     alpha component of the step is set to zero and the w block solved alone.
   * Level 1 (Algorithm 3.2, step 1) is solved by the same Newton iteration.
-  * Variable coefficient (A(x) = kappa(x) I, kappa given per cell of the finest
-    mesh): every coarser level's cell takes the mean of its 2^d children's
-    kappa, and A_k is assembled with it (rediscretisation, not P^T A P).  An
-    x-dependent f(x, u) = c(x) f(u) takes c at the level's nodes (nodes of the
-    finest mesh), in the vertex rule m_j c_j f(u_j).
+  * Variable coefficient (A(x) symmetric positive definite, constant on every
+    cell of the finest mesh): a(u, v) is one form on all the nested spaces, so
+    the matrix of level k is that form on V_{h_k}, A_k = P_{k+1}^T A_{k+1}
+    P_{k+1} down from the finest assembly (with A = I this is the plain
+    assembly on every level).  An x-dependent f(x, u) = c(x) f(u) takes c at
+    the level's nodes (nodes of the finest mesh), in the vertex rule
+    m_j c_j f(u_j).
 """
 from __future__ import annotations
 
@@ -91,19 +93,6 @@ class Options:
         return pre, post
 
 
-def level_kappas(dim: int, n: int, refinements: int, kappa):
-    """Cell coefficients of every level, coarsest first: the finest is kappa
-    (n^d values, x fastest); each coarser cell is the mean of its 2^d children."""
-    if kappa is None:
-        return [None] * (refinements + 1)
-    out = [np.asarray(kappa, dtype=np.float64).reshape((n,) * dim)]   # axes (z,) y, x
-    for _ in range(refinements):
-        f = out[-1]
-        c = f.reshape(*sum(([s // 2, 2] for s in f.shape), []))
-        out.append(c.mean(axis=tuple(range(1, 2 * dim, 2))))
-    return [a.reshape(-1) for a in out[::-1]]
-
-
 @dataclass
 class Level:
     mesh: Mesh
@@ -117,14 +106,13 @@ class Level:
 class Hierarchy:
     """Meshes T_{h_1} .. T_{h_n}, matrices A_k, masses m_k, P_k and Q_k."""
 
-    def __init__(self, dim: int, coarse_cells: int, refinements: int, kappa=None):
+    def __init__(self, dim: int, coarse_cells: int, refinements: int, coef=None):
         self.dim = dim
         self.coarse_cells = coarse_cells
         self.levels: list[Level] = []
-        kap = level_kappas(dim, coarse_cells * 2 ** refinements, refinements, kappa)
         for k in range(refinements + 1):
             mesh = unit_mesh(dim, coarse_cells * 2 ** k)
-            A, m = assemble_interior(mesh, kap[k])
+            A, m = assemble_interior(mesh, coef if (coef is None or k == refinements) else None)
             lev = Level(mesh, A, m, A.diagonal().copy())
             if k == 0:
                 lev.Q = sp.identity(mesh.interior.size, format="csr")
@@ -132,6 +120,14 @@ class Hierarchy:
                 lev.P = prolongation(self.levels[-1].mesh, mesh)
                 lev.Q = (lev.P @ self.levels[-1].Q).tocsr()
             self.levels.append(lev)
+        if coef is not None:
+            # the finest form on the coarser spaces (Galerkin)
+            for k in range(refinements - 1, -1, -1):
+                P = self.levels[k + 1].P
+                A = (P.T @ self.levels[k + 1].A @ P).tocsr()
+                A.sort_indices()
+                self.levels[k].A = A
+                self.levels[k].D = A.diagonal().copy()
         self.A1 = self.levels[0].A.toarray()
         self._quad = {}
 

@@ -100,10 +100,12 @@ class Problem:
     u_exact: Optional[Callable] = None   # u(*coords) -> array, for element norms
     grad_u_exact: Optional[Callable] = None
     meta: dict = field(default_factory=dict)
-    # variable coefficients: kappa > 0 per cell of the finest mesh (n^d, x fastest
-    # over the cells' lower corners) and the weight c >= 0 of f(x, u) = c(x) f(u)
-    # at the finest nodes ((n+1)^d); None means 1
-    kappa_cells: Optional[np.ndarray] = None
+    # variable coefficients: the symmetric positive definite matrix A per cell
+    # of the finest mesh as its d(d+1)/2 upper-triangle components row by row
+    # (2D: a11, a12, a22; 3D: a11, a12, a13, a22, a23, a33), shape
+    # (components, n^d), cells x fastest by lower corner; and the weight
+    # c >= 0 of f(x, u) = c(x) f(u) at the finest nodes ((n+1)^d).  None: A = I, c = 1
+    coef_cells: Optional[np.ndarray] = None
     f_weight_nodes: Optional[np.ndarray] = None
 
     @property
@@ -377,45 +379,80 @@ def _cell_centres(d: int, n: int) -> list[np.ndarray]:
     return [t[idx[d - 1 - a]].reshape(-1) for a in range(d)]
 
 
+def _upper_components(M: np.ndarray) -> list[tuple[int, int]]:
+    d = M.shape[0]
+    return [(a, b) for a in range(d) for b in range(a, d)]
+
+
+# Constant anisotropy of the manufactured variable-coefficient problems
+# (symmetric, diagonally dominant, so positive definite).
+ANISO = {2: np.array([[1.0, 0.3], [0.3, 0.8]]),
+         3: np.array([[1.0, 0.3, 0.2], [0.3, 0.9, 0.25], [0.2, 0.25, 1.1]])}
+
+
+def scalar_coefficient(dim: int, kappa: np.ndarray) -> np.ndarray:
+    """Components (d(d+1)/2, cells) of A = kappa I."""
+    kappa = np.asarray(kappa, dtype=np.float64)
+    return np.stack([kappa if a == b else np.zeros_like(kappa)
+                     for a, b in _upper_components(np.eye(dim))])
+
+
 def variable_coefficient(name: str, dim: int, coarse_cells: int, refinements: int,
-                         f_kind: int, f_param: float = 0.0) -> Problem:
-    """u = prod sin(pi x_i), kappa(x) = 1 + s(x)/2 with s = prod sin(pi x_i)
-    (sampled at the cell centres), c(x) = 1 + cos(pi x_1)/2 at the nodes, and
-    g = -div(kappa grad u) + c f(u) = kappa d pi^2 s - |grad s|^2 / 2 + c f(s)
-    at the nodes (closed forms)."""
+                         f_kind: int, f_param: float = 0.0, isotropic: bool = False) -> Problem:
+    """u = s = prod sin(pi x_i), A(x) = kappa(x) B with kappa = 1 + s/2 sampled
+    at the cell centres and B = ANISO[dim] (or I), c(x) = 1 + cos(pi x_1)/2 at
+    the nodes, and g = -div(A grad u) + c f(u) in closed form at the nodes:
+    -kappa tr(B H_s) - (grad kappa)^T B grad s + c f(s), H_s the Hessian of s."""
+    B = np.eye(dim) if isotropic else ANISO[dim]
     n = coarse_cells * 2 ** refinements
     X = _mesh(dim, n)
-    s_ = np.ones_like(X[0])
-    for xi in X:
-        s_ = s_ * np.sin(PI * xi)
-    grad2 = np.zeros_like(X[0])
+    S = [np.sin(PI * x) for x in X]
+    Cs = [np.cos(PI * x) for x in X]
+    s_ = np.prod(S, axis=0)
+
+    def prod_except(*skip):
+        out = np.ones_like(X[0])
+        for k in range(dim):
+            if k not in skip:
+                out = out * S[k]
+        return out
+
+    grad = [PI * Cs[a] * prod_except(a) for a in range(dim)]
+    trBH = np.zeros_like(X[0])
     for a in range(dim):
-        t = PI * np.cos(PI * X[a])
         for b in range(dim):
-            if b != a:
-                t = t * np.sin(PI * X[b])
-        grad2 += t * t
+            Hab = -PI ** 2 * s_ if a == b else PI ** 2 * Cs[a] * Cs[b] * prod_except(a, b)
+            trBH += B[a, b] * Hab
+    gBg = sum(B[a, b] * grad[a] * grad[b] for a in range(dim) for b in range(dim))
     kap_nodes = 1.0 + 0.5 * s_
     c = 1.0 + 0.5 * np.cos(PI * X[0])
-    g = kap_nodes * dim * PI ** 2 * s_ - 0.5 * grad2 + c * _f_closed(f_kind, f_param, s_)
+    g = -kap_nodes * trBH - 0.5 * gBg + c * _f_closed(f_kind, f_param, s_)
     C = _cell_centres(dim, n)
-    sc = np.ones_like(C[0])
-    for ci in C:
-        sc = sc * np.sin(PI * ci)
+    kc = 1.0 + 0.5 * np.prod([np.sin(PI * x) for x in C], axis=0)
+    coef = np.stack([kc * B[a, b] for a, b in _upper_components(B)])
     return Problem(name, dim, coarse_cells, refinements, f_kind, f_param, g_nodes=np.ascontiguousarray(g),
-                   u_exact_nodes=s_, kappa_cells=np.ascontiguousarray(1.0 + 0.5 * sc),
-                   f_weight_nodes=np.ascontiguousarray(c), meta={"solution": "sin", "kappa": "1 + s/2"})
+                   u_exact_nodes=s_, coef_cells=np.ascontiguousarray(coef),
+                   f_weight_nodes=np.ascontiguousarray(c),
+                   meta={"solution": "sin", "A": "(1 + s/2) " + ("I" if isotropic else "B")})
 
 
 def random_coefficient(name: str, dim: int, coarse_cells: int, refinements: int, f_kind: int, seed,
                        contrast: float = 10.0, f_param: float = 0.0) -> Problem:
-    """kappa piecewise constant on the cells, log-uniform in [1, contrast]
-    (PCG64 seeded); c uniform in [0, 2] at the nodes; a random-Fourier load."""
+    """A = kappa (I + 0.4 S) per cell: kappa log-uniform in [1, contrast], S
+    symmetric with zero diagonal and off-diagonal entries uniform in
+    [-1/2, 1/2] (eigenvalues of I + 0.4 S >= 0.6); c uniform in [0, 2] at the
+    nodes; a random-Fourier load (PCG64 seeded)."""
     rng = np.random.default_rng(seed)
     n = coarse_cells * 2 ** refinements
     P = fourier_problem(name, dim, coarse_cells, refinements, f_kind, [int(x) for x in np.atleast_1d(seed)] + [7],
                         f_param=f_param)
-    P.kappa_cells = np.exp(rng.uniform(0.0, np.log(contrast), size=n ** dim))
+    ncell = n ** dim
+    kappa = np.exp(rng.uniform(0.0, np.log(contrast), size=ncell))
+    comps = []
+    for a, b in _upper_components(np.eye(dim)):
+        comps.append(kappa if a == b else kappa * 0.4 * rng.uniform(-0.5, 0.5, size=ncell))
+    P.coef_cells = np.ascontiguousarray(np.stack(comps))
     P.f_weight_nodes = rng.uniform(0.0, 2.0, size=(n + 1) ** dim)
-    P.meta.update({"kappa": f"log-uniform [1, {contrast:g}] per cell", "c": "uniform [0, 2] per node"})
+    P.meta.update({"A": f"kappa (I + 0.4 S), kappa log-uniform [1, {contrast:g}] per cell",
+                   "c": "uniform [0, 2] per node"})
     return P
