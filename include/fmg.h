@@ -72,6 +72,7 @@ enum fmg_precision { FMG_FP64 = 0, FMG_MIXED = 1 };
 enum fmg_smoother { FMG_SMOOTHER_DEFAULT = 0, FMG_JACOBI = 1, FMG_CHEBYSHEV = 2 };
 enum fmg_mode { FMG_PAPER = 0, FMG_CONVERGED = 1 };
 enum fmg_quadrature { FMG_QUAD_VERTEX = 0, FMG_QUAD_ELEMENT = 1 };
+enum fmg_coefficients { FMG_COEF_IDENTITY = 0, FMG_COEF_VARIABLE = 1 };
 
 typedef struct {
     int dim;            /* 2 or 3                                           */
@@ -142,6 +143,22 @@ typedef struct {
                            augmented problem, level 1).  Element mode ignores
                            aug_small_nodes and rejects fuse_small_levels = 1
                            and fmg_solve_noalloc with FMG_E_UNSUPPORTED      */
+    int coefficients;   /* FMG_COEF_IDENTITY (default): a(u,v) = (grad u,
+                           grad v); FMG_COEF_VARIABLE: a(u,v) = (A grad u,
+                           grad v) with the symmetric positive definite matrix
+                           A(x) of eq. "semilinear equation" constant on every
+                           cell of the finest mesh, given by
+                           fmg_set_coefficients before the first solve.  Every
+                           level carries that one form (Galerkin: the level-k
+                           matrix is the finest form on V_{h_k}; on the Kuhn
+                           meshes a 7-point (2D) or 15-point (3D) stencil held
+                           as per-node edge weights).  Problems may then give
+                           f(x,u) = c(x) f(u) (fmg_problem.f_weight).  Needs
+                           precision FMG_FP64 and the vertex rule, runs the
+                           V-cycles with one-sweep kernels down to level 1 and
+                           ignores tail_max_nodes, aug_small_nodes and
+                           sweep_rows; fuse_small_levels = 1 and
+                           fmg_solve_noalloc return FMG_E_UNSUPPORTED        */
 } fmg_options;
 
 typedef struct {
@@ -153,6 +170,11 @@ typedef struct {
                                simplex, boundary vertices included); must stay
                                valid until the solve has completed on the
                                stream                                        */
+    const double *f_weight; /* device or NULL; c(x) >= 0 at the finest nodes,
+                               (n+1)^dim, for f(x,u) = c(x) f(u) (vertex
+                               rule: m_j c_j f(u_j)); NULL means c = 1.  Only
+                               hierarchies with FMG_COEF_VARIABLE take it
+                               (else FMG_E_UNSUPPORTED); lifetime as g_nodes  */
 } fmg_problem;
 
 typedef struct {
@@ -183,8 +205,25 @@ int fmg_create_hierarchy(const fmg_mesh_desc *mesh, const fmg_options *opts,
                          void *d_workspace, size_t workspace_bytes, void *stream,
                          fmg_hierarchy **out);
 
+/* FMG_COEF_VARIABLE hierarchies: set the matrix A(x) of the operator
+ * -div(A grad u) (Section 2, eq. "semilinear equation"; the form a(u,v) of
+ * eq. "weak_form").  d_coef (device, float64) holds the d(d+1)/2 upper-
+ * triangle components of A row by row (2D: a11, a12, a22; 3D: a11, a12, a13,
+ * a22, a23, a33) as component planes of n^dim cells each (x fastest, a cell
+ * named by its lower corner node), A symmetric positive definite per cell;
+ * A = kappa I is (kappa, 0, kappa) or (kappa, 0, 0, kappa, 0, kappa).
+ * Enqueues on `stream` the kernels that form every level's stencil (the
+ * per-simplex means of the finest matrices, the forward edge weights) and
+ * the level-1 matrix A_1 and its inverse; d_coef is read by them only, so it
+ * may be released once they have completed.  Solves enqueued after this call
+ * use the new operator (captured graphs stay valid).  Errors: FMG_E_INVALID
+ * (NULL, or a hierarchy created without FMG_COEF_VARIABLE).  Positive
+ * definiteness is the caller's: the library does not check it. */
+int fmg_set_coefficients(fmg_hierarchy *h, const double *d_coef, void *stream);
+
 /* Solve one problem with Algorithm 3.2.  d_u_out (device, (n+1)^dim float64)
- * receives the finest-level solution with zero boundary.  report may be NULL
+ * receives the finest-level solution with zero boundary.  FMG_COEF_VARIABLE
+ * hierarchies return FMG_E_INVALID until fmg_set_coefficients was called.  report may be NULL
  * or point to memory the device can write (device memory or pinned host
  * memory); it is written at the end of the solve.  Asynchronous in FMG_PAPER
  * mode; FMG_CONVERGED mode synchronises the stream once per extra step. */

@@ -30,11 +30,13 @@ FMG_FP64, FMG_MIXED = 0, 1
 FMG_SMOOTHER_DEFAULT, FMG_JACOBI, FMG_CHEBYSHEV = 0, 1, 2
 FMG_PAPER, FMG_CONVERGED = 0, 1
 FMG_QUAD_VERTEX, FMG_QUAD_ELEMENT = 0, 1
+FMG_COEF_IDENTITY, FMG_COEF_VARIABLE = 0, 1
 FMG_OP_APPLY_A, FMG_OP_SMOOTH, FMG_OP_RESTRICT, FMG_OP_PROLONG, FMG_OP_COARSE = range(5)
 
 EXPORTED = ("fmg_default_options", "fmg_workspace_bytes", "fmg_create_hierarchy", "fmg_solve",
             "fmg_get_report", "fmg_solve_batch", "fmg_destroy", "fmg_status_str", "fmg_level_op",
-            "fmg_profile_solve", "fmg_kernel_name", "fmg_time_level_kernel", "fmg_solve_noalloc")
+            "fmg_profile_solve", "fmg_kernel_name", "fmg_time_level_kernel", "fmg_solve_noalloc",
+            "fmg_set_coefficients")
 
 
 class MeshDesc(ctypes.Structure):
@@ -51,11 +53,17 @@ class Options(ctypes.Structure):
                 ("use_graph", ctypes.c_int), ("tail_max_nodes", ctypes.c_int),
                 ("fuse_small_levels", ctypes.c_int), ("aug_max_blocks", ctypes.c_int),
                 ("aug_small_nodes", ctypes.c_int), ("sweep_rows", ctypes.c_int),
-                ("quadrature", ctypes.c_int)]
+                ("quadrature", ctypes.c_int), ("coefficients", ctypes.c_int)]
 
 
 class ProblemC(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("param", ctypes.c_double), ("g_nodes", ctypes.c_void_p)]
+    _fields_ = [("kind", ctypes.c_int), ("param", ctypes.c_double), ("g_nodes", ctypes.c_void_p),
+                ("f_weight", ctypes.c_void_p)]
+
+
+def _problem(kind, param, g, c=None) -> ProblemC:
+    return ProblemC(int(kind), float(param), ctypes.c_void_p(g.data_ptr()),
+                    ctypes.c_void_p(c.data_ptr() if c is not None else 0))
 
 
 class Report(ctypes.Structure):
@@ -121,6 +129,8 @@ def _load():
     lib.fmg_time_level_kernel.restype = ctypes.c_int
     lib.fmg_solve_noalloc.argtypes = [P(MeshDesc), P(Options), P(ProblemC), vp, vp, vp]
     lib.fmg_solve_noalloc.restype = ctypes.c_int
+    lib.fmg_set_coefficients.argtypes = [vp, vp, vp]
+    lib.fmg_set_coefficients.restype = ctypes.c_int
     return lib
 
 
@@ -203,15 +213,34 @@ class Hierarchy:
         k = self.levels if level is None else level
         return (self.coarse_cells * 2 ** (k - 1) + 1) ** self.dim
 
-    def solve_async(self, g, kind: int, param: float = 0.0, out=None, report_ptr: int = 0, stream=None):
+    def set_coefficients(self, coef, stream=None):
+        """FMG_COEF_VARIABLE hierarchies: the matrix A(x) per finest cell as a
+        contiguous float64 device tensor of d(d+1)/2 component planes of n^d
+        cells (upper triangle row by row).  Stream-ordered; `coef` must stay
+        alive until the setup kernels have run (the call keeps a reference)."""
+        import torch
+        ncomp = self.dim * (self.dim + 1) // 2
+        if coef.dtype != torch.float64 or not coef.is_contiguous() or coef.numel() != ncomp * self.n ** self.dim:
+            raise ValueError("coef must be a contiguous float64 tensor of d(d+1)/2 planes of n^d cells")
+        st = stream if stream is not None else self.stream
+        _check(LIB.fmg_set_coefficients(self.handle, ctypes.c_void_p(coef.data_ptr()),
+                                        ctypes.c_void_p(_stream_ptr(st))), "fmg_set_coefficients")
+        self._coef = coef
+
+    def solve_async(self, g, kind: int, param: float = 0.0, out=None, report_ptr: int = 0, stream=None,
+                    c=None):
         """Enqueue one solve on `stream` (default: the hierarchy's stream, else
-        torch's current one); returns the output tensor."""
+        torch's current one); returns the output tensor.  c: optional weight
+        c(x) of f(x, u) = c(x) f(u) at the finest nodes (variable-coefficient
+        hierarchies)."""
         import torch
         if out is None:
             out = torch.empty(self.nodes(), dtype=torch.float64, device=g.device)
         if g.dtype != torch.float64 or not g.is_contiguous() or g.numel() != self.nodes():
             raise ValueError("g must be a contiguous float64 tensor with (n+1)^d entries")
-        prob = ProblemC(int(kind), float(param), ctypes.c_void_p(g.data_ptr()))
+        if c is not None and (c.dtype != torch.float64 or not c.is_contiguous() or c.numel() != self.nodes()):
+            raise ValueError("c must be a contiguous float64 tensor with (n+1)^d entries")
+        prob = _problem(kind, param, g, c)
         st = stream if stream is not None else self.stream
         _check(LIB.fmg_solve(self.handle, ctypes.byref(prob), ctypes.c_void_p(out.data_ptr()),
                              ctypes.c_void_p(report_ptr), ctypes.c_void_p(_stream_ptr(st))),
@@ -226,8 +255,8 @@ class Hierarchy:
                "fmg_get_report")
         return r.as_dict()
 
-    def solve(self, g, kind: int, param: float = 0.0, out=None):
-        out = self.solve_async(g, kind, param, out)
+    def solve(self, g, kind: int, param: float = 0.0, out=None, c=None):
+        out = self.solve_async(g, kind, param, out, c=c)
         return out, self.report()
 
     def level_op(self, op: int, level: int, in0, in1=None, precision: int = FMG_FP64, omega: float = 0.0):
@@ -258,8 +287,7 @@ def solve_batch(hs: list, gs: list, kinds: list, params: list, outs: list, strea
     one graph launch on `stream`; the solves run side by side on the device."""
     n = len(hs)
     H = (ctypes.c_void_p * n)(*[h.handle for h in hs])
-    P = (ProblemC * n)(*[ProblemC(int(k), float(p), ctypes.c_void_p(g.data_ptr()))
-                         for g, k, p in zip(gs, kinds, params)])
+    P = (ProblemC * n)(*[_problem(k, p, g) for g, k, p in zip(gs, kinds, params)])
     O = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
     _check(LIB.fmg_solve_batch(H, P, O, None, n, ctypes.c_void_p(_stream_ptr(stream))), "fmg_solve_batch")
 
@@ -278,7 +306,7 @@ def solve_noalloc(dim: int, coarse_cells: int, refinements: int, g, kind: int, p
         raise ValueError("g must be a contiguous float64 tensor with (n+1)^d entries")
     mesh = MeshDesc(dim, coarse_cells, refinements)
     o = opts if opts is not None else default_options(dim)
-    prob = ProblemC(int(kind), float(param), ctypes.c_void_p(g.data_ptr()))
+    prob = _problem(kind, param, g)
     _check(LIB.fmg_solve_noalloc(ctypes.byref(mesh), ctypes.byref(o), ctypes.byref(prob),
                                  ctypes.c_void_p(out.data_ptr()),
                                  ctypes.c_void_p(report.data_ptr() if report is not None else 0),

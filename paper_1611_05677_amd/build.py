@@ -24,7 +24,7 @@ LIB_HOSTSAN = os.path.join(HERE, "libfmg_hostsan.so")
 HOSTSAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
                  "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
 SOURCES = ["fmg.hip", "fmg_kind_2d_a.hip", "fmg_kind_2d_b.hip", "fmg_kind_3d_a.hip", "fmg_kind_3d_b.hip",
-           "fmg_kind_2d_e.hip", "fmg_kind_3d_e.hip"]
+           "fmg_kind_2d_e.hip", "fmg_kind_3d_e.hip", "fmg_kind_2d_v.hip", "fmg_kind_3d_v.hip"]
 ARCH = os.environ.get("FMG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

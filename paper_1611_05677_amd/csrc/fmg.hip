@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fmg.h"
@@ -77,6 +78,10 @@ struct Plan {
   size_t off_fmgtail;
   size_t off_ticket;
   size_t off_econtrib;     // element rule: per-corner cell contributions of the right-hand side
+  int var;                 // variable coefficient: the arrays below are in use
+  size_t off_w[FMG_MAX_LEVELS + 1];     // forward-edge weight planes of level k
+  long long wplane[FMG_MAX_LEVELS + 1];  // elements between the planes (the level's array size)
+  size_t off_sm[FMG_MAX_LEVELS + 1];    // per-simplex matrices of level k < n
   size_t norm_blocks;
   size_t total;
 };
@@ -98,6 +103,14 @@ int resolve(int dim, const fmg_options* in, Resolved& r) {
   if (o.sweep_rows < -1 || (o.sweep_rows > 0 && o.sweep_rows < 4) || o.sweep_rows > 4096) return FMG_E_INVALID;
   if (o.quadrature != FMG_QUAD_VERTEX && o.quadrature != FMG_QUAD_ELEMENT) return FMG_E_INVALID;
   if (o.quadrature == FMG_QUAD_ELEMENT && o.fuse_small_levels) return FMG_E_UNSUPPORTED;
+  if (o.coefficients != FMG_COEF_IDENTITY && o.coefficients != FMG_COEF_VARIABLE) return FMG_E_INVALID;
+  if (o.coefficients == FMG_COEF_VARIABLE) {
+    if (o.precision != FMG_FP64 || o.quadrature != FMG_QUAD_VERTEX || o.fuse_small_levels) return FMG_E_UNSUPPORTED;
+    // one-sweep V-cycle kernels down to level 1, multi-workgroup augmented passes
+    o.tail_max_nodes = 0;
+    o.aug_small_nodes = 0;
+    o.sweep_rows = -1;
+  }
   r.o = o;
   r.smoother = o.smoother ? o.smoother : (dim == 2 ? FMG_JACOBI : FMG_CHEBYSHEV);
   if (r.smoother == FMG_JACOBI) {
@@ -153,7 +166,7 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p, bool host_
     {   // every level: level 1 takes the augmented passes in element mode
       const int nodes_log = d * (k - 1);
       // large levels: 1024-thread (2D) or 512-thread (3D) blocks, fewer of them
-      const bool wide = ro.o.quadrature == FMG_QUAD_VERTEX &&
+      const bool wide = ro.o.quadrature == FMG_QUAD_VERTEX && ro.o.coefficients == FMG_COEF_IDENTITY &&
                         nodes_log >= (d == 2 ? aug_wide_nodes_log<2>() : aug_wide_nodes_log<3>());
       const int tlog = wide ? ilog2(d == 2 ? aug_threads<2>() : aug_threads<3>()) : 8;
       const int cap_log = ilog2(std::max(1, (ro.o.aug_max_blocks >> (tlog - 8)) / ncell));
@@ -164,6 +177,7 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p, bool host_
       L.aug.bpc_log = bpc_log;
       L.aug.npb_log = nodes_log - bpc_log;
       L.aug.N1 = p.N1;
+      L.aug.general = ro.o.coefficients == FMG_COEF_VARIABLE ? 1 : 0;
       L.aug_blocks = ncell << bpc_log;
       max_blocks = std::max(max_blocks, L.aug_blocks);
     }
@@ -208,6 +222,18 @@ int make_plan(const fmg_mesh_desc* mesh, const Resolved& ro, Plan& p, bool host_
     const size_t nf = (size_t)F.g.n;
     p.off_econtrib = take(sizeof(double) * (d == 2 ? 4 * nf * nf : 8 * nf * nf * nf));
   }
+  p.var = ro.o.coefficients == FMG_COEF_VARIABLE ? 1 : 0;
+  if (p.var) {
+    const int nfwd = (1 << d) - 1, nsm = d == 2 ? 3 * 2 : 6 * 6;   // components x simplices
+    for (int k = 1; k <= p.nlev; ++k) {
+      p.wplane[k] = (long long)p.lev[k].count;
+      p.off_w[k] = take(sizeof(double) * nfwd * p.lev[k].count);
+      if (k < p.nlev) {
+        const size_t n = p.lev[k].g.n;
+        p.off_sm[k] = take(sizeof(double) * nsm * (d == 2 ? n * n : n * n * n));
+      }
+    }
+  }
   p.total = off;
   return FMG_OK;
 }
@@ -224,6 +250,7 @@ struct fmg_hierarchy {
   hipStream_t cap_stream;
   hipGraphExec_t graph[7];
   Prof* prof;              // set only while fmg_profile_solve records
+  bool coef_ready;         // variable coefficient: fmg_set_coefficients was called
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   NewtonState* ns() const { return at<NewtonState>(plan.off_state); }
   fmg_report* rep() const { return at<fmg_report>(plan.off_report); }
@@ -245,7 +272,8 @@ enum KernelClass {
   KC_NEWTON_FINISH, KC_AUG_UPDATE, KC_LEVEL1, KC_BEGIN, KC_OUTPUT, KC_END, KC_FILL,
   KC_VCYCLE_TAIL64, KC_VCYCLE_TAIL32, KC_FMG_TAIL, KC_AUG_SMALL, KC_PRE2D64, KC_POST2D64, KC_PRE2D32, KC_POST2D32,
   KC_PRE2S64, KC_POST2S64, KC_PRE2S32, KC_POST2S32, KC_SMOOTH3S64, KC_SMOOTH3S32,
-  KC_PRE3P64, KC_POST3P64, KC_PRE3P32, KC_POST3P32, KC_RHS_ELEM, KC_COUNT
+  KC_PRE3P64, KC_POST3P64, KC_PRE3P32, KC_POST3P32, KC_RHS_ELEM,
+  KC_SMOOTHW64, KC_SMOOTHW64_ZERO, KC_RESIDW64, KC_RESTRICT64_R, KC_COUNT
 };
 const char* const kKernelNames[KC_COUNT] = {
   "smooth_f64", "smooth_f64_from_zero", "resid_restrict_f64", "prolong_add_f64", "coarse_solve_f64",
@@ -258,7 +286,7 @@ const char* const kKernelNames[KC_COUNT] = {
   "pre_sweeps_restrict_2d_stream_f32", "prolong_post_sweeps_2d_stream_f32",
   "smooth_3d_stream_f64", "smooth_3d_stream_f32",
   "pre_sweep_pair_3d_f64", "prolong_sweep_pair_3d_f64", "pre_sweep_pair_3d_f32", "prolong_sweep_pair_3d_f32",
-  "rhs_element"};
+  "rhs_element", "smooth_var_f64", "smooth_var_f64_from_zero", "resid_var_f64", "restrict_f64"};
 
 // Event pairs around launches (fmg_profile_solve only).
 struct Prof {
@@ -482,6 +510,52 @@ double launch_sweep(const fmg_hierarchy* h, int k, const T* x, const T* b, T* t,
 }
 
 template <int DIM, typename T>
+void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t st);
+
+// V-cycle level k >= 2 of the variable-coefficient operator (float64): damped
+// Jacobi sweeps with the level's stencil arrays, the residual into the spare
+// array, its restriction P^T r, the coarse cycle, the correction and the
+// post-sweeps.
+template <int DIM>
+void vcycle_var(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t st) {
+  const Plan& p = h->plan;
+  const LevelInfo& L = p.lev[k];
+  const LevelInfo& C = p.lev[k - 1];
+  double*& x = R.x[k];
+  double*& t = R.t[k];
+  double* b = h->at<double>(p.off_b[k]);
+  const double* W = h->at<double>(p.off_w[k]);
+  const long long pl = p.wplane[k];
+  const dim3 grid = grid_of(L.g, DIM);
+  const long long N = interior(L.g, DIM), Nc = interior(C.g, DIM);
+  const double nfw = (1 << DIM) - 1;      // weight planes read per node
+  const int npre = h->ro.o.nu_pre, npost = h->ro.o.nu_post;
+  if (zero_init && npre == 0)
+    FMG_LAUNCH(h, st, KC_FILL, k, N, 8.0 * L.count, k_fill<double><<<256, 256, 0, st>>>(x, L.count, 0.0));
+  for (int i = 0; i < npre; ++i) {
+    if (zero_init && i == 0)
+      FMG_LAUNCH(h, st, KC_SMOOTHW64_ZERO, k, N, 8.0 * (2.0 + nfw) * N,
+                 k_smooth_w<DIM, true><<<grid, kBlock, 0, st>>>(L.g, x, b, t, W, pl, h->ro.pre[i]));
+    else
+      FMG_LAUNCH(h, st, KC_SMOOTHW64, k, N, 8.0 * (3.0 + nfw) * N,
+                 k_smooth_w<DIM, false><<<grid, kBlock, 0, st>>>(L.g, x, b, t, W, pl, h->ro.pre[i]));
+    std::swap(x, t);
+  }
+  FMG_LAUNCH(h, st, KC_RESIDW64, k, N, 8.0 * (3.0 + nfw) * N,
+             k_resid_w<DIM><<<grid, kBlock, 0, st>>>(L.g, x, b, t, W, pl));
+  FMG_LAUNCH(h, st, KC_RESTRICT64_R, k, N, 8.0 * (N + Nc),
+             k_restrict<DIM><<<grid_of(C.g, DIM), kBlock, 0, st>>>(L.g, C.g, t, h->at<double>(p.off_b[k - 1])));
+  vcycle<DIM, double>(h, R, k - 1, true, st);
+  FMG_LAUNCH(h, st, KC_PROLONG64_ADD, k, N, 8.0 * (2 * N + Nc),
+             k_prolong<DIM, double, true><<<grid, kBlock, 0, st>>>(C.g, L.g, R.x[k - 1], x));
+  for (int i = 0; i < npost; ++i) {
+    FMG_LAUNCH(h, st, KC_SMOOTHW64, k, N, 8.0 * (3.0 + nfw) * N,
+               k_smooth_w<DIM, false><<<grid, kBlock, 0, st>>>(L.g, x, b, t, W, pl, h->ro.post[i]));
+    std::swap(x, t);
+  }
+}
+
+template <int DIM, typename T>
 void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t st) {
   const Plan& p = h->plan;
   const LevelInfo& L = p.lev[k];
@@ -495,6 +569,12 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
     FMG_LAUNCH(h, st, KC_COARSE64 + kc, 1, N, 2 * s * N,
                k_coarse_solve<DIM, T><<<1, 64, 0, st>>>(L.g, p.N1, Sel<T>::ainv(h), b, x));
     return;
+  }
+  if constexpr (std::is_same<T, double>::value) {
+    if (p.var) {
+      vcycle_var<DIM>(h, R, k, zero_init, st);
+      return;
+    }
   }
   if (k <= p.tail_top && p.tail_dense) {
     // x_k = x0 + B_k (b_k - A_k x0) (zero start: B_k b_k), written to the
@@ -740,6 +820,42 @@ void aug_solve_elem(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, boo
                k_aug_update<DIM><<<grid_of(L.g, DIM), kBlock, 0, st>>>(L.g, L.aug, h->ns(), R.x[k]));
 }
 
+// Algorithm 3.1, step 2 with the variable-coefficient operator: the setup
+// pass (A u~ from the level's stencil arrays), the quadrature passes of the
+// launch sequence (weighted by c(x) when the problem gives it), the
+// finisher, and the update unless deferred.
+template <int DIM, int KIND>
+void aug_solve_var(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bool defer_update) {
+  const Plan& p = h->plan;
+  const LevelInfo& L = p.lev[k];
+  const fmg_options& o = h->ro.o;
+  const long long N = interior(L.g, DIM);
+  const int nf1 = p.lev[p.nlev].g.n + 1, fs = 1 << (p.nlev - k);
+  double* pq = h->at<double>(p.off_pq);
+  double* ps = h->at<double>(p.off_ps);
+  unsigned* ticket = h->at<unsigned>(p.off_ticket);
+  const double* A1 = h->at<double>(p.off_A1);
+  const size_t lds = aug_pass_lds_bytes(p);
+  const double nfw = (1 << DIM) - 1;
+  FMG_LAUNCH(h, st, KC_AUG_PASS0, k, N, (16.0 + 8.0 * nfw) * N,
+             (launch_aug_pass<DIM, KIND, true, false, false, true>(L.aug_blocks, L.aug_threads, lds, st, L.g, L.aug,
+                                                                   R.x[k], h->slot(), nf1, fs, L.scale, L.m, A1,
+                                                                   h->ns(), h->rep(), pq, ps, ticket, k,
+                                                                   o.newton_max, o.newton_tol)));
+  for (int pass = 1; pass < o.newton_passes; ++pass)
+    FMG_LAUNCH(h, st, KC_AUG_PASS, k, N, 8.0 * N,
+               (launch_aug_pass<DIM, KIND, false, false, false, true>(L.aug_blocks, L.aug_threads, lds, st, L.g,
+                                                                      L.aug, R.x[k], h->slot(), nf1, fs, L.scale,
+                                                                      L.m, A1, h->ns(), h->rep(), pq, ps, ticket, k,
+                                                                      o.newton_max, o.newton_tol)));
+  FMG_LAUNCH(h, st, KC_NEWTON_FINISH, k, N, 0.0,
+             (launch_newton_finish<DIM, KIND, false, true>(lds, st, L.g, L.aug, R.x[k], h->slot(), A1, L.m, h->ns(),
+                                                           h->rep(), o.newton_max, o.newton_tol)));
+  if (!defer_update)
+    FMG_LAUNCH(h, st, KC_AUG_UPDATE, k, N, 16.0 * N,
+               k_aug_update<DIM><<<grid_of(L.g, DIM), kBlock, 0, st>>>(L.g, L.aug, h->ns(), R.x[k]));
+}
+
 template <int DIM, int KIND>
 void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bool rhs_ready,
                      bool defer_update, bool fold_next) {
@@ -758,6 +874,9 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
     FMG_LAUNCH(h, st, KC_RHS_ELEM, k, N, (DIM == 2 ? 88.0 : 152.0) * N,
                (launch_rhs_elem<DIM, KIND>(grid, st, L.g, h->slot(), nf1, fs, R.x[k],
                                            h->at<double>(p.off_econtrib), b, L.m)));
+  else if (!rhs_ready && p.var)
+    FMG_LAUNCH(h, st, KC_RHS, k, N, 24.0 * N,
+               (launch_rhs<DIM, KIND, true>(grid, st, L.g, h->slot(), nf1, fs, R.x[k], b, L.m)));
   else if (!rhs_ready)
     FMG_LAUNCH(h, st, KC_RHS, k, N, 24.0 * N,
                (launch_rhs<DIM, KIND>(grid, st, L.g, h->slot(), nf1, fs, R.x[k], b, L.m)));
@@ -784,6 +903,10 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
   const double* A1 = h->at<double>(p.off_A1);
   if (elem) {
     aug_solve_elem<DIM, KIND>(h, R, k, st, defer_update);
+    return;
+  }
+  if (p.var) {
+    aug_solve_var<DIM, KIND>(h, R, k, st, defer_update);
     return;
   }
   if (N <= o.aug_small_nodes) {
@@ -870,7 +993,8 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     // report reset and Algorithm 3.2, step 1: exact semilinear solve on V_{h_1}
     const LevelInfo& L1 = p.lev[1];
     const size_t lds1 = sizeof(double) * (size_t)level1_lds_doubles(p.N1);
-    folded = p.nlev >= 2 && interior(p.lev[2].g, DIM) <= kFoldTransitionNodes;
+    // (the variable-coefficient transitions, which apply c(x), run as launches of their own)
+    folded = !p.var && p.nlev >= 2 && interior(p.lev[2].g, DIM) <= kFoldTransitionNodes;
     FMG_LAUNCH(h, st, KC_LEVEL1, 1, p.N1, 0.0,
                (launch_level1<DIM, KIND>(lds1, st, L1.g, p.N1, h->at<double>(p.off_A1), L1.m, h->slot(), nf1,
                                          1 << (p.nlev - 1), R.x[1], h->rep(), o.newton_max, o.newton_tol, p.nlev,
@@ -883,7 +1007,15 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     const LevelInfo& L = p.lev[k];
     const LevelInfo& C = p.lev[k - 1];
     const long long N = interior(L.g, DIM);
-    if (!folded && pending_aug)
+    if (!folded && p.var)
+      FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (3 * N + interior(C.g, DIM)),
+                 (pending_aug ? launch_transition<DIM, KIND, true, true>(grid_of(L.g, DIM), st,
+                                                                         transition_args(h, R, k, true), h->ns(),
+                                                                         h->slot())
+                              : launch_transition<DIM, KIND, false, true>(grid_of(L.g, DIM), st,
+                                                                          transition_args(h, R, k, false), h->ns(),
+                                                                          h->slot())));
+    else if (!folded && pending_aug)
       FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (3 * N + interior(C.g, DIM)),
                  (launch_transition<DIM, KIND, true>(grid_of(L.g, DIM), st, transition_args(h, R, k, true), h->ns(),
                                                      h->slot())));
@@ -949,6 +1081,17 @@ int check_problem(const fmg_problem* prob) {
   if (prob->kind < FMG_F_ZERO || prob->kind > FMG_F_NEG_EXP) return FMG_E_INVALID;
   if (prob->kind == FMG_F_LINEAR && !(prob->param >= 0)) return FMG_E_INVALID;
   if (prob->kind == FMG_F_SIGNED_POW && !(prob->param >= 1)) return FMG_E_INVALID;
+  return FMG_OK;
+}
+
+// check_problem plus what the hierarchy needs: the coefficients set (variable
+// coefficient), and a weight c(x) only where the variable-coefficient
+// kernels run.
+int check_problem_for(const fmg_hierarchy* h, const fmg_problem* prob) {
+  const int st = check_problem(prob);
+  if (st != FMG_OK) return st;
+  if (h->plan.var && !h->coef_ready) return FMG_E_INVALID;
+  if (prob->f_weight && !h->plan.var) return FMG_E_UNSUPPORTED;
   return FMG_OK;
 }
 
@@ -1174,6 +1317,141 @@ void build_tail_operators(const Plan& p, const Resolved& ro, const std::vector<d
 
 namespace {
 
+// Axis order of Kuhn simplex s of a cell (as KuhnChain<d, s>).
+void chain_axes(int d, int s, int ax[3]) {
+  if (d == 2) { ax[0] = s; ax[1] = 1 - s; ax[2] = 2; return; }
+  ax[0] = s / 2;
+  const int r0 = ax[0] == 0 ? 1 : 0, r1 = ax[0] == 2 ? 1 : 2;
+  ax[1] = (s & 1) ? r1 : r0;
+  ax[2] = (s & 1) ? r0 : r1;
+}
+
+// Upper-triangle component index of entry (a, b), rows in order.
+int comp_index(int d, int a, int b) {
+  if (a > b) std::swap(a, b);
+  return a * d - a * (a - 1) / 2 + (b - a);
+}
+
+// Barycentric gradient k of a chain (unit cell) as (axis, sign) pairs.
+int chain_gradient(int d, const int ax[3], int k, int axis[2], int sign[2]) {
+  int n = 0;
+  if (k > 0) { axis[n] = ax[k - 1]; sign[n] = 1; ++n; }
+  if (k < d) { axis[n] = ax[k]; sign[n] = -1; ++n; }
+  return n;
+}
+
+// Terms of the forward-edge weights: for every direction delta, every cell
+// (octant o below the node) and simplex whose chain holds both o and o + delta,
+// -g_i^T A g_j as integer multiples of the matrix components.
+void build_coef_terms(int d, CoefTerms& T) {
+  std::memset(&T, 0, sizeof(T));
+  const int NS = d == 2 ? 2 : 6, NO = 1 << d;
+  int n = 0;
+  for (int dl = 1; dl < NO; ++dl) {
+    T.begin[dl - 1] = n;
+    for (int o = 0; o < NO; ++o) {
+      if (o & dl) continue;
+      for (int sx = 0; sx < NS; ++sx) {
+        int ax[3];
+        chain_axes(d, sx, ax);
+        int v[4] = {0, 0, 0, 0};
+        for (int k = 1; k <= d; ++k) v[k] = v[k - 1] | (1 << ax[k - 1]);
+        int i = -1, j = -1;
+        for (int k = 0; k <= d; ++k) {
+          if (v[k] == o) i = k;
+          if (v[k] == (o | dl)) j = k;
+        }
+        if (i < 0 || j < 0) continue;
+        int ai[2], si[2], aj[2], sj[2], coef[6] = {0, 0, 0, 0, 0, 0};
+        const int ni = chain_gradient(d, ax, i, ai, si), nj = chain_gradient(d, ax, j, aj, sj);
+        for (int x = 0; x < ni; ++x)
+          for (int y = 0; y < nj; ++y) coef[comp_index(d, ai[x], aj[y])] -= si[x] * sj[y];
+        for (int q = 0; q < d * (d + 1) / 2; ++q)
+          if (coef[q] != 0 && n < kCoefTermsMax) {
+            T.o[n] = (unsigned char)o;
+            T.s[n] = (unsigned char)sx;
+            T.q[n] = (unsigned char)q;
+            T.c[n] = (signed char)coef[q];
+            ++n;
+          }
+      }
+    }
+  }
+  T.begin[NO - 1] = n;
+}
+
+// Coarse simplex of every child simplex: the fine simplex of octant o with
+// chain order pi holds the points whose coordinates in the parent cell
+// decrease first over the axes with o = 1 (in pi's order), then over the
+// others (in pi's order).
+void build_coarsen_map(int d, CoarsenMap& M) {
+  std::memset(&M, 0, sizeof(M));
+  const int NS = d == 2 ? 2 : 6, NO = 1 << d;
+  for (int o = 0; o < NO; ++o)
+    for (int pi = 0; pi < NS; ++pi) {
+      int ax[3], sig[3] = {0, 0, 0}, m = 0;
+      chain_axes(d, pi, ax);
+      for (int k = 0; k < d; ++k)
+        if ((o >> ax[k]) & 1) sig[m++] = ax[k];
+      for (int k = 0; k < d; ++k)
+        if (!((o >> ax[k]) & 1)) sig[m++] = ax[k];
+      for (int sx = 0; sx < NS; ++sx) {
+        int bx[3];
+        chain_axes(d, sx, bx);
+        bool same = true;
+        for (int k = 0; k < d; ++k) same = same && bx[k] == sig[k];
+        if (same) M.sigma[o][pi] = (unsigned char)sx;
+      }
+    }
+}
+
+// Stencil arrays of every level, then A_1 and its inverse, from the finest
+// cell matrices d_coef.
+template <int DIM>
+void coef_setup(fmg_hierarchy* h, const double* d_coef, hipStream_t s) {
+  const Plan& p = h->plan;
+  CoefTerms terms;
+  build_coef_terms(DIM, terms);
+  CoarsenMap map;
+  build_coarsen_map(DIM, map);
+  constexpr int NS = coef_simplices<DIM>();
+  for (int k = p.nlev - 1; k >= 1; --k) {
+    const int nc = p.lev[k].g.n;
+    const long long work = (DIM == 2 ? (long long)nc * nc : (long long)nc * nc * nc) * NS;
+    const bool from_cells = k + 1 == p.nlev;
+    k_coef_coarsen<DIM><<<(unsigned)((work + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        nc, from_cells ? d_coef : h->at<double>(p.off_sm[k + 1]), from_cells ? 1 : 0, h->at<double>(p.off_sm[k]),
+        map);
+  }
+  const double dfact = DIM == 2 ? 2.0 : 6.0;
+  for (int k = 1; k <= p.nlev; ++k) {
+    const LevelInfo& L = p.lev[k];
+    const long long n1 = L.g.n + 1;
+    const long long nodes = DIM == 2 ? n1 * n1 : n1 * n1 * n1;
+    const bool finest = k == p.nlev;
+    k_coef_weights<DIM><<<(unsigned)((nodes + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        L.g, finest ? d_coef : h->at<double>(p.off_sm[k]), finest ? 1 : 0, L.scale / dfact,
+        h->at<double>(p.off_w[k]), p.wplane[k], terms);
+  }
+  k_coef_level1<DIM><<<1, kBlock, 0, s>>>(p.lev[1].g, h->at<double>(p.off_w[1]), p.wplane[1], p.N1,
+                                          h->at<double>(p.off_A1));
+  k_spd_invert<<<1, kInvertThreads, sizeof(double) * invert_lds_doubles(p.N1), s>>>(
+      h->at<double>(p.off_A1), h->at<double>(p.off_A1inv), h->at<float>(p.off_A1inv_f), p.N1);
+}
+
+// The hierarchy's part of the problem slot.
+CoefLevels coef_levels(const fmg_hierarchy* h) {
+  CoefLevels c;
+  std::memset(&c, 0, sizeof(c));
+  const Plan& p = h->plan;
+  if (p.var)
+    for (int k = 1; k <= p.nlev; ++k) {
+      c.w[k] = h->at<double>(p.off_w[k]);
+      c.plane[k] = p.wplane[k];
+    }
+  return c;
+}
+
 // The LDS-resident V-cycle tail may use up to the whole 160 KB of a workgroup.
 hipError_t set_tail_lds_limit() {
   const int lim = (int)kTailLdsMax;
@@ -1239,6 +1517,7 @@ struct SlotDesc {
   const double* g;
   double* out;
   fmg_report* rep;
+  const double* c;
   double param;
   int kind;
   int pad;
@@ -1248,6 +1527,7 @@ __global__ void k_set_slots(const SlotDesc* __restrict__ d, int count) {
   for (int i = threadIdx.x; i < count; i += blockDim.x) {
     ProblemSlot* s = d[i].slot;
     s->g = d[i].g; s->u_out = d[i].out; s->rep_out = d[i].rep; s->param = d[i].param; s->kind = d[i].kind;
+    s->c = d[i].c;
   }
 }
 
@@ -1368,6 +1648,7 @@ int fmg_create_hierarchy(const fmg_mesh_desc* mesh, const fmg_options* opts, voi
   h->ws_bytes = workspace_bytes;
   for (auto& g : h->graph) g = nullptr;
   h->prof = nullptr;
+  h->coef_ready = false;
   if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete h; return FMG_E_HIP; }
   if (set_tail_lds_limit() != hipSuccess) {
     (void)hipStreamDestroy(h->cap_stream);
@@ -1387,6 +1668,7 @@ int fmg_create_hierarchy(const fmg_mesh_desc* mesh, const fmg_options* opts, voi
   }
   if (p.off_uprev) k_fill<double><<<1024, 256, 0, s>>>(h->at<double>(p.off_uprev), p.lev[p.nlev].count, 0.0);
   k_fill<unsigned><<<1, 64, 0, s>>>(h->at<unsigned>(p.off_ticket), 1, 0u);
+  k_init_slot<<<1, 64, 0, s>>>(h->slot(), p.lev[p.nlev].g.n + 1, coef_levels(h));
   if (p.tail_top >= 2 && ro.o.fuse_small_levels) {
     // parameters of the single-workgroup FMG launch over levels 1..T (canonical roles)
     FmgTailParams P;
@@ -1444,14 +1726,24 @@ int fmg_create_hierarchy(const fmg_mesh_desc* mesh, const fmg_options* opts, voi
   return FMG_OK;
 }
 
+int fmg_set_coefficients(fmg_hierarchy* h, const double* d_coef, void* stream) {
+  if (!h || !d_coef || !h->plan.var) return FMG_E_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (h->plan.dim == 2) coef_setup<2>(h, d_coef, s);
+  else coef_setup<3>(h, d_coef, s);
+  if (hipGetLastError() != hipSuccess) return FMG_E_HIP;
+  h->coef_ready = true;
+  return FMG_OK;
+}
+
 int fmg_solve(fmg_hierarchy* h, const fmg_problem* prob, double* d_u_out, fmg_report* report, void* stream) {
   if (!h || !d_u_out) return FMG_E_INVALID;
-  int st = check_problem(prob);
+  int st = check_problem_for(h, prob);
   if (st != FMG_OK) return st;
   const Plan& p = h->plan;
   const fmg_options& o = h->ro.o;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  k_set_slot<<<1, 64, 0, s>>>(h->slot(), prob->g_nodes, d_u_out, report, prob->param, prob->kind);
+  k_set_slot<<<1, 64, 0, s>>>(h->slot(), prob->g_nodes, d_u_out, report, prob->param, prob->kind, prob->f_weight);
   record_fn rec = p.dim == 2 ? pick_record<2>(prob->kind) : pick_record<3>(prob->kind);
   Roles R;
   canonical_roles(h, R);
@@ -1522,7 +1814,8 @@ int fmg_solve_noalloc(const fmg_mesh_desc* mesh, const fmg_options* opts, const 
   if (st != FMG_OK) return st;
   Resolved ro;
   if ((st = resolve(mesh->dim, opts, ro)) != FMG_OK) return st;
-  if (ro.o.mode != FMG_PAPER || ro.o.fuse_small_levels || ro.o.quadrature != FMG_QUAD_VERTEX)
+  if (ro.o.mode != FMG_PAPER || ro.o.fuse_small_levels || ro.o.quadrature != FMG_QUAD_VERTEX ||
+      ro.o.coefficients != FMG_COEF_IDENTITY || prob->f_weight)
     return FMG_E_UNSUPPORTED;
   fmg_hierarchy h;   // on the stack: plan, options and the scratch as workspace
   if ((st = make_plan(mesh, ro, h.plan, false)) != FMG_OK) return st;
@@ -1544,7 +1837,8 @@ int fmg_solve_noalloc(const fmg_mesh_desc* mesh, const fmg_options* opts, const 
   k_fill<double><<<1024, 256, 0, s>>>(h.at<double>(p.off_x[1]), words, 0.0);
   k_level1_tables<<<1, 64, sizeof(double) * 2 * p.N1 * p.N1, s>>>(
       p.dim, p.nH, p.lev[1].scale, h.at<double>(p.off_A1), h.at<double>(p.off_A1inv), h.at<float>(p.off_A1inv_f));
-  k_set_slot<<<1, 64, 0, s>>>(h.slot(), prob->g_nodes, d_u_out, report, prob->param, prob->kind);
+  k_init_slot<<<1, 64, 0, s>>>(h.slot(), p.lev[p.nlev].g.n + 1, CoefLevels{});
+  k_set_slot<<<1, 64, 0, s>>>(h.slot(), prob->g_nodes, d_u_out, report, prob->param, prob->kind, nullptr);
   record_fn rec = p.dim == 2 ? pick_record<2>(prob->kind) : pick_record<3>(prob->kind);
   Roles R;
   canonical_roles(&h, R);
@@ -1555,11 +1849,11 @@ int fmg_solve_noalloc(const fmg_mesh_desc* mesh, const fmg_options* opts, const 
 int fmg_profile_solve(fmg_hierarchy* h, const fmg_problem* prob, double* d_u_out, void* stream,
                       fmg_profile* out) {
   if (!h || !d_u_out || !out) return FMG_E_INVALID;
-  int st = check_problem(prob);
+  int st = check_problem_for(h, prob);
   if (st != FMG_OK) return st;
   const Plan& p = h->plan;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  k_set_slot<<<1, 64, 0, s>>>(h->slot(), prob->g_nodes, d_u_out, nullptr, prob->param, prob->kind);
+  k_set_slot<<<1, 64, 0, s>>>(h->slot(), prob->g_nodes, d_u_out, nullptr, prob->param, prob->kind, prob->f_weight);
   record_fn rec = p.dim == 2 ? pick_record<2>(prob->kind) : pick_record<3>(prob->kind);
   Prof pf;
   Roles R;
@@ -1613,7 +1907,7 @@ int fmg_solve_batch(fmg_hierarchy* const* hs, const fmg_problem* probs, double* 
   bool graphs = true;
   for (int i = 0; i < count; ++i) {
     if (!hs[i] || !outs[i]) return FMG_E_INVALID;
-    const int st = check_problem(&probs[i]);
+    const int st = check_problem_for(hs[i], &probs[i]);
     if (st != FMG_OK) return st;
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i] || outs[j] == outs[i]) return FMG_E_INVALID;
@@ -1658,6 +1952,7 @@ int fmg_solve_batch(fmg_hierarchy* const* hs, const fmg_problem* probs, double* 
     SlotDesc& d = b->host[i];
     d.slot = hs[i]->slot(); d.g = probs[i].g_nodes; d.out = outs[i];
     d.rep = reports ? reports[i] : nullptr; d.param = probs[i].param; d.kind = probs[i].kind; d.pad = 0;
+    d.c = probs[i].f_weight;
   }
   if (hipMemcpyAsync(b->table, b->host.data(), sizeof(SlotDesc) * count, hipMemcpyHostToDevice, s) != hipSuccess)
     return FMG_E_HIP;
@@ -1731,6 +2026,39 @@ int level_op_impl(fmg_hierarchy* h, int op, int k, int prec, const double* in0, 
     if (prec == FMG_FP64) k_pack<DIM, double, double><<<pk, 256, 0, s>>>(g, s64, out, 1);
     else k_pack<DIM, double, float><<<pk, 256, 0, s>>>(g, s32, out, 1);
   };
+  if (p.var && op != FMG_OP_PROLONG && op != FMG_OP_COARSE) {
+    // the variable-coefficient operator (float64 only)
+    if (prec != FMG_FP64 || !h->coef_ready) return FMG_E_INVALID;
+    const double* W = h->at<double>(p.off_w[k]);
+    const long long pl = p.wplane[k];
+    switch (op) {
+      case FMG_OP_APPLY_A:
+        in(in0, x, xs, L.g);
+        k_apply_Aw<DIM><<<grid, kBlock, 0, s>>>(L.g, x, t, W, pl);
+        outp(t, ts, L.g);
+        break;
+      case FMG_OP_SMOOTH:
+        in(in0, x, xs, L.g);
+        in(in1, b, bs, L.g);
+        k_smooth_w<DIM, false><<<grid, kBlock, 0, s>>>(L.g, x, b, t, W, pl, omega);
+        outp(t, ts, L.g);
+        break;
+      case FMG_OP_RESTRICT: {
+        if (k < 2) return FMG_E_INVALID;
+        const LevelInfo& C = p.lev[k - 1];
+        in(in0, x, xs, L.g);
+        in(in1, b, bs, L.g);
+        double* bc = h->at<double>(p.off_b[k - 1]);
+        k_resid_w<DIM><<<grid, kBlock, 0, s>>>(L.g, x, b, t, W, pl);
+        k_restrict<DIM><<<grid_of(C.g, DIM), kBlock, 0, s>>>(L.g, C.g, t, bc);
+        outp(bc, nullptr, C.g);
+        break;
+      }
+      default:
+        return FMG_E_INVALID;
+    }
+    return hipGetLastError() == hipSuccess ? FMG_OK : FMG_E_HIP;
+  }
   switch (op) {
     case FMG_OP_APPLY_A:
       in(in0, x, xs, L.g);
@@ -1876,6 +2204,7 @@ extern "C" int fmg_time_level_kernel(fmg_hierarchy* h, int kernel, int level, in
   if (!h || !ms_per_launch || !bytes_per_launch || reps < 1 || reps > 100000 || level < 2 ||
       level > h->plan.nlev)
     return FMG_E_INVALID;
+  if (h->plan.var) return FMG_E_UNSUPPORTED;
   hipStream_t s = static_cast<hipStream_t>(stream);
   double bytes = 0.0;
   auto once = [&]() {

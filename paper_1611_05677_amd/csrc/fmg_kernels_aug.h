@@ -17,6 +17,7 @@
 #pragma once
 
 #include "fmg_device.h"
+#include "fmg_kernels_coef.h"
 #include "fmg_kernels_mg.h"
 
 namespace fmg {
@@ -25,8 +26,12 @@ struct ProblemSlot {
   const double* g;        // finest nodal load, packed (nf+1)^d
   double* u_out;          // packed (nf+1)^d output
   fmg_report* rep_out;    // optional device-writable report copy
+  const double* c;        // weight c(x) of f(x, u) = c f(u) at the finest nodes (packed), or nullptr (c = 1)
   double param;           // nonlinearity parameter
   int kind;
+  // set when the hierarchy is created (not per problem)
+  int nf1;                // finest nodes per side
+  CoefLevels coef;        // stencil arrays of the variable-coefficient operator (w[k] = nullptr: A = I)
 };
 
 struct NewtonState {
@@ -46,6 +51,7 @@ struct AugShape {
   int bpc_log;   // blocks per coarse cell = 2^bpc_log
   int npb_log;   // fine node slots per block = 2^npb_log
   int N1;        // interior coarse nodes
+  int general;   // 1: A_1 is a general matrix (variable coefficient), not the constant stencil
 };
 
 constexpr double kArmijo = 1e-4;
@@ -125,14 +131,23 @@ __device__ __forceinline__ long long fine_load_index(int nf1, int s, int i, int 
 // ---------------------------------------------------------------------------
 // Linearised right-hand side: b_j = m (g_j - f(u_j)) at level-k interior nodes.
 // ---------------------------------------------------------------------------
-template <int DIM, int KIND>
+// CW: f(x, u) = c(x) f(u) with c at the finest nodes (slot->c; nullptr means
+// c = 1).  A separate instance, so that the c = 1 kernel keeps its own
+// arithmetic (the compiler fuses g - f(u) differently once a weight may enter).
+template <int DIM, int KIND, bool CW = false>
 __global__ void __launch_bounds__(kBlock) k_rhs(Grid g, const ProblemSlot* __restrict__ slot, int nf1, int s,
                                                 const double* __restrict__ u, double* __restrict__ b, double m) {
   int i, j, l;
   if (!node_of_thread<DIM>(g, i, j, l)) return;
   const int c = gidx<DIM>(g, i, j, l);
-  const double gv = slot->g[fine_load_index(nf1, s, i, j, l)];
-  b[c] = m * (gv - NL<KIND>::f(u[c], slot->param));
+  const long long fi = fine_load_index(nf1, s, i, j, l);
+  const double gv = slot->g[fi];
+  if constexpr (CW) {
+    const double* __restrict__ cw = slot->c;
+    b[c] = m * (gv - (cw ? cw[fi] : 1.0) * NL<KIND>::f(u[c], slot->param));
+  } else {
+    b[c] = m * (gv - NL<KIND>::f(u[c], slot->param));
+  }
 }
 
 // Per-cell setup sums for one block's node range:
@@ -153,12 +168,15 @@ __device__ __forceinline__ void setup_node(const double* phi, double u, double a
 
 // Quadrature sums of one fine node at z (the nonlinear terms and their
 // derivatives): f phi_a, f' phi_a u~, f' phi_a phi_b, f u~, f' u~^2, F.
-template <int DIM, int KIND>
-__device__ __forceinline__ void quad_node(const double* phi, double z, double u, double param, double* acc) {
+// CW: the sums are weighted by c(x_j) (cj) of f(x, u) = c(x) f(u).
+template <int DIM, int KIND, bool CW = false>
+__device__ __forceinline__ void quad_node(const double* phi, double z, double u, double param, double* acc,
+                                          double cj = 1.0) {
   using AC = Acc<DIM>;
   using PR = Pairs<DIM>;
   double f, df, F;
   NL<KIND>::all(z, param, f, df, F);
+  if (CW) { f *= cj; df *= cj; F *= cj; }
   double dphi[AC::NV];
 #pragma unroll
   for (int a = 0; a < AC::NV; ++a) {
@@ -184,6 +202,29 @@ __device__ __forceinline__ void setup_accumulate(const Grid& g, const AugShape& 
     double phi[Acc<DIM>::NV];
     kuhn_phi<DIM>(tl, phi);
     setup_node<DIM>(phi, u, apply_A_at<DIM>(ut, c, g, scale), gl[fine_load_index(nf1, fs, i, j, l)], acc);
+  });
+}
+
+// The same with the variable-coefficient stencil (W, plane) and, when cw is
+// set, the weight c(x) in the quadrature sums at z = u~.
+template <int DIM, int KIND>
+__device__ __forceinline__ void setup_quad_accumulate_var(const Grid& g, const AugShape& s,
+                                                          const double* __restrict__ ut,
+                                                          const double* __restrict__ gl,
+                                                          const double* __restrict__ cw, int nf1, int fs,
+                                                          const double* __restrict__ W, long long plane,
+                                                          double param, int cell, int t0, int t1, int tid,
+                                                          int nthreads, double* acc_s, double* acc_q) {
+  int cx, cy, cz;
+  cell_of<DIM>(cell, s.nH, cx, cy, cz);
+  for_cell_nodes<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, ut,
+                      [&](int c, const double* tl, int i, int j, int l, double u) {
+    double phi[Acc<DIM>::NV];
+    kuhn_phi<DIM>(tl, phi);
+    const long long fi = fine_load_index(nf1, fs, i, j, l);
+    double diag;
+    setup_node<DIM>(phi, u, apply_Aw_at<DIM>(ut, c, g, W, plane, diag), gl[fi], acc_s);
+    quad_node<DIM, KIND, true>(phi, u, u, param, acc_q, cw ? cw[fi] : 1.0);
   });
 }
 
@@ -239,6 +280,45 @@ __device__ __forceinline__ void quad_accumulate(const Grid& g, const AugShape& s
     for (int a = 0; a < AC::NV; ++a) z += wv[a] * phi[a];
     quad_node<DIM, KIND>(phi, z, u, param, acc);
   });
+}
+
+// quad_accumulate with the weight c(x) of f(x, u) = c(x) f(u) (cw: finest
+// nodal c, nf1 / fs as for the load).
+template <int DIM, int KIND>
+__device__ __forceinline__ void quad_accumulate_cw(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                                   const double* ytry, double param, const double* __restrict__ cw,
+                                                   int nf1, int fs, int cell, int t0, int t1, int tid, int nthreads,
+                                                   double* acc) {
+  using AC = Acc<DIM>;
+  int cx, cy, cz;
+  cell_of<DIM>(cell, s.nH, cx, cy, cz);
+  double wv[AC::NV];
+#pragma unroll
+  for (int a = 0; a < AC::NV; ++a) {
+    const int gi = coarse_vertex<DIM>(s.nH, cx, cy, cz, a);
+    wv[a] = gi >= 0 ? ytry[gi] : 0.0;
+  }
+  const double alpha = ytry[s.N1];
+  for_cell_nodes<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, ut,
+                      [&](int, const double* tl, int i, int j, int l, double u) {
+    double phi[AC::NV];
+    kuhn_phi<DIM>(tl, phi);
+    double z = alpha * u;
+#pragma unroll
+    for (int a = 0; a < AC::NV; ++a) z += wv[a] * phi[a];
+    quad_node<DIM, KIND, true>(phi, z, u, param, acc, cw[fine_load_index(nf1, fs, i, j, l)]);
+  });
+}
+
+// Quadrature sums of the variable-coefficient solves: weighted when c is given.
+template <int DIM, int KIND>
+__device__ __forceinline__ void quad_accumulate_var(const Grid& g, const AugShape& s, const double* __restrict__ ut,
+                                                    const double* ytry, double param, const double* __restrict__ cw,
+                                                    int nf1, int cell, int t0, int t1, int tid, int nthreads,
+                                                    double* acc) {
+  if (cw) quad_accumulate_cw<DIM, KIND>(g, s, ut, ytry, param, cw, nf1, (nf1 - 1) / g.n, cell, t0, t1, tid,
+                                        nthreads, acc);
+  else quad_accumulate<DIM, KIND>(g, s, ut, ytry, param, cell, t0, t1, tid, nthreads, acc);
 }
 
 }  // namespace fmg
@@ -820,9 +900,10 @@ __device__ __forceinline__ void newton_step_dev(const AugShape& s, const double*
                                                 double m, NewtonState* ns, fmg_report* rep, int newton_max,
                                                 double tol, double* sm);
 
-template <int DIM, int KIND, bool ELEM = false>
+template <int DIM, int KIND, bool ELEM = false, bool VAR = false>
 __device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShape& s, const double* __restrict__ ut,
-                                           const double* ytry, double param, double* cs);
+                                           const double* ytry, double param, double* cs,
+                                           const ProblemSlot* __restrict__ slot = nullptr);
 
 // One pass of the augmented Newton iteration in one launch.  Every block
 // accumulates its share of the fine quadrature sums at ns->ytry (SETUP: the
@@ -832,10 +913,13 @@ __device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShap
 // fixed block order, into the cell sums and performs the Newton step.
 // tickets[0]: zero between launches.  ELEM: the element rule (the block's
 // node range is a range of fine cells); the completion of a Newton solve that
-// needs more passes is then left to k_newton_finish.
+// needs more passes is then left to k_newton_finish.  VAR: the variable-
+// coefficient operator (the setup pass applies the level's stencil arrays)
+// and the weight c(x) of f(x, u) = c(x) f(u) when the problem gives one; the
+// completion is left to k_newton_finish as well.
 // LDS: newton_kernel_lds_doubles(ncell, NQ, N1, blockDim).
-template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM = false>
-__global__ void __launch_bounds__(ELEM ? kBlock : aug_threads<DIM>()) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
+template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM = false, bool VAR = false>
+__global__ void __launch_bounds__(ELEM || VAR ? kBlock : aug_threads<DIM>()) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
                                                      const ProblemSlot* __restrict__ slot, int nf1, int fs,
                                                      double scale, double m, const double* __restrict__ A1,
                                                      NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,
@@ -843,6 +927,7 @@ __global__ void __launch_bounds__(ELEM ? kBlock : aug_threads<DIM>()) k_aug_pass
                                                      unsigned* __restrict__ tickets, int level, int newton_max,
                                                      double tol) {
   static_assert(!(ELEM && FINISH), "element-rule passes leave the completion to k_newton_finish");
+  static_assert(!(VAR && (FINISH || ELEM)), "variable-coefficient passes: vertex rule, separate completion");
   using AC = Acc<DIM>;
   extern __shared__ double smem[];
   __shared__ int is_last;
@@ -861,6 +946,10 @@ __global__ void __launch_bounds__(ELEM ? kBlock : aug_threads<DIM>()) k_aug_pass
     if (ELEM)
       setup_quad_accumulate_elem<DIM, KIND>(g, s, ut, slot->g, nf1, fs, scale, param, cell, t0, t1, threadIdx.x,
                                             blockDim.x, acc, acc + AC::NS);
+    else if (VAR)
+      setup_quad_accumulate_var<DIM, KIND>(g, s, ut, slot->g, slot->c, nf1, fs, slot->coef.w[level],
+                                           slot->coef.plane[level], param, cell, t0, t1, threadIdx.x, blockDim.x,
+                                           acc, acc + AC::NS);
     else
       setup_quad_accumulate<DIM, KIND>(g, s, ut, slot->g, nf1, fs, scale, param, cell, t0, t1, threadIdx.x,
                                        blockDim.x, acc, acc + AC::NS);
@@ -874,6 +963,9 @@ __global__ void __launch_bounds__(ELEM ? kBlock : aug_threads<DIM>()) k_aug_pass
     for (int q = 0; q < AC::NQ; ++q) acc[q] = 0.0;
     if (ELEM)
       quad_accumulate_elem<DIM, KIND>(g, s, ut, ns->ytry, param, cell, t0, t1, threadIdx.x, blockDim.x, acc);
+    else if (VAR)
+      quad_accumulate_var<DIM, KIND>(g, s, ut, ns->ytry, param, slot->c, nf1, cell, t0, t1, threadIdx.x,
+                                     blockDim.x, acc);
     else
       quad_accumulate<DIM, KIND>(g, s, ut, ns->ytry, param, cell, t0, t1, threadIdx.x, blockDim.x, acc);
     double tot = block_sum_many<AC::NQ>(acc, smem);
@@ -915,9 +1007,10 @@ __global__ void __launch_bounds__(ELEM ? kBlock : aug_threads<DIM>()) k_aug_pass
 // spread over a segment of LPC = min(64, r^d) lanes, so a wavefront holds
 // 64 / LPC cells and reduces each accumulator over its segment only; the last
 // lane of a segment writes the cell's sums.  No block barrier inside.
-template <int DIM, int KIND, int LPC, bool ELEM>
+template <int DIM, int KIND, int LPC, bool ELEM, bool VAR>
 __device__ __forceinline__ void quad_cells_seg(const Grid& g, const AugShape& s, const double* __restrict__ ut,
-                                               const double* ytry, double param, double* cs) {
+                                               const double* ytry, double param, double* cs,
+                                               const ProblemSlot* __restrict__ slot) {
   using AC = Acc<DIM>;
   constexpr int CPW = 64 / LPC;
   const int ncell = DIM == 2 ? s.nH * s.nH : s.nH * s.nH * s.nH;
@@ -931,6 +1024,8 @@ __device__ __forceinline__ void quad_cells_seg(const Grid& g, const AugShape& s,
     for (int q = 0; q < AC::NQ; ++q) acc[q] = 0.0;
     if (cell < ncell) {
       if (ELEM) quad_accumulate_elem<DIM, KIND>(g, s, ut, ytry, param, cell, 0, nodes, sub, LPC, acc);
+      else if (VAR)
+        quad_accumulate_var<DIM, KIND>(g, s, ut, ytry, param, slot->c, slot->nf1, cell, 0, nodes, sub, LPC, acc);
       else quad_accumulate<DIM, KIND>(g, s, ut, ytry, param, cell, 0, nodes, sub, LPC, acc);
     }
 #pragma unroll
@@ -942,15 +1037,16 @@ __device__ __forceinline__ void quad_cells_seg(const Grid& g, const AugShape& s,
   __syncthreads();
 }
 
-template <int DIM, int KIND, bool ELEM>
+template <int DIM, int KIND, bool ELEM, bool VAR>
 __device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShape& s, const double* __restrict__ ut,
-                                           const double* ytry, double param, double* cs) {
+                                           const double* ytry, double param, double* cs,
+                                           const ProblemSlot* __restrict__ slot) {
   const int nodes_log = DIM * s.log2r;
-  if (nodes_log <= 2) quad_cells_seg<DIM, KIND, 4, ELEM>(g, s, ut, ytry, param, cs);
-  else if (nodes_log == 3) quad_cells_seg<DIM, KIND, 8, ELEM>(g, s, ut, ytry, param, cs);
-  else if (nodes_log == 4) quad_cells_seg<DIM, KIND, 16, ELEM>(g, s, ut, ytry, param, cs);
-  else if (nodes_log == 5) quad_cells_seg<DIM, KIND, 32, ELEM>(g, s, ut, ytry, param, cs);
-  else quad_cells_seg<DIM, KIND, 64, ELEM>(g, s, ut, ytry, param, cs);
+  if (nodes_log <= 2) quad_cells_seg<DIM, KIND, 4, ELEM, VAR>(g, s, ut, ytry, param, cs, slot);
+  else if (nodes_log == 3) quad_cells_seg<DIM, KIND, 8, ELEM, VAR>(g, s, ut, ytry, param, cs, slot);
+  else if (nodes_log == 4) quad_cells_seg<DIM, KIND, 16, ELEM, VAR>(g, s, ut, ytry, param, cs, slot);
+  else if (nodes_log == 5) quad_cells_seg<DIM, KIND, 32, ELEM, VAR>(g, s, ut, ytry, param, cs, slot);
+  else quad_cells_seg<DIM, KIND, 64, ELEM, VAR>(g, s, ut, ytry, param, cs, slot);
 }
 
 template <int DIM, int LPC>
@@ -1038,7 +1134,7 @@ __device__ __forceinline__ void setup_quad_cells_by_waves(const Grid& g, const A
 // Completes a Newton solve that the passes of the launch sequence did not
 // finish: one block evaluates the fine quadrature itself (3D, and the element
 // rule in 2D).
-template <int DIM, int KIND, bool ELEM = false>
+template <int DIM, int KIND, bool ELEM = false, bool VAR = false>
 __global__ void __launch_bounds__(kBlock) k_newton_finish(Grid g, AugShape s, const double* __restrict__ ut,
                                                           const ProblemSlot* __restrict__ slot,
                                                           const double* __restrict__ A1, double m,
@@ -1052,7 +1148,7 @@ __global__ void __launch_bounds__(kBlock) k_newton_finish(Grid g, AugShape s, co
   while (true) {
     __syncthreads();
     if (ns->done) return;
-    quad_cells_by_waves<DIM, KIND, ELEM>(g, s, ut, ns->ytry, slot->param, cs);
+    quad_cells_by_waves<DIM, KIND, ELEM, VAR>(g, s, ut, ns->ytry, slot->param, cs, slot);
     newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   }
 }
@@ -1159,13 +1255,15 @@ struct TransitionArgs {
 };
 
 // AUG: a.use_aug, as a template argument so that the node's code has no
-// branch and every load is issued before the first use.
-template <int DIM, int KIND, bool AUG>
+// branch and every load is issued before the first use.  CW: the weight c(x)
+// of f(x, u) = c(x) f(u) (slot->c, nullptr means c = 1), as for k_rhs.
+template <int DIM, int KIND, bool AUG, bool CW = false>
 __device__ __forceinline__ void transition_node(const TransitionArgs& a, const double* __restrict__ y,
                                                 const ProblemSlot* __restrict__ slot, int i, int j, int l) {
   const int si = i & 1, sj = j & 1, sl = DIM == 3 ? (l & 1) : 0;
   const int pi = i >> 1, pj = j >> 1, pl = l >> 1;
-  const double gv = slot->g[fine_load_index(a.nf1, a.fs, i, j, l)];
+  const long long fi = fine_load_index(a.nf1, a.fs, i, j, l);
+  const double gv = slot->g[fi];
   AugTerms<DIM> t;
   if constexpr (AUG) t = aug_gather<DIM>(a.sf, y, i, j, l);
   // both coarse values are loaded; at a coarse node they are the same value,
@@ -1176,15 +1274,20 @@ __device__ __forceinline__ void transition_node(const TransitionArgs& a, const d
   if constexpr (AUG) v = aug_apply<DIM>(t, v);
   const int q = gidx<DIM>(a.gf, i, j, l);
   a.uf[q] = v;
-  a.bf[q] = a.m * (gv - NL<KIND>::f(v, slot->param));
+  if constexpr (CW) {
+    const double* __restrict__ cw = slot->c;
+    a.bf[q] = a.m * (gv - (cw ? cw[fi] : 1.0) * NL<KIND>::f(v, slot->param));
+  } else {
+    a.bf[q] = a.m * (gv - NL<KIND>::f(v, slot->param));
+  }
 }
 
-template <int DIM, int KIND, bool AUG>
+template <int DIM, int KIND, bool AUG, bool CW = false>
 __global__ void __launch_bounds__(kBlock) k_transition(TransitionArgs a, const NewtonState* __restrict__ ns,
                                                        const ProblemSlot* __restrict__ slot) {
   int i, j, l;
   if (!node_of_thread<DIM>(a.gf, i, j, l)) return;
-  transition_node<DIM, KIND, AUG>(a, ns->y, slot, i, j, l);
+  transition_node<DIM, KIND, AUG, CW>(a, ns->y, slot, i, j, l);
 }
 
 // The same transition by the threads of one block (small fine levels, at the
@@ -1238,12 +1341,16 @@ __device__ __forceinline__ void level1_newton_dev(const Grid& g1, int N1, const 
   double* col = T + N1;             // N1 Cholesky column
   double* rdiag = col + N1;         // N1 reciprocal pivots
   double* sc = rdiag + N1;          // scalars: [0]=E [1]=scale [2]=done
+  double* MC = sc + 4;              // N1: m c(x) at the nodes (c = 1 unless the problem gives c)
   const double q = slot->param;
+  const double* __restrict__ cw = slot->c;
   for (int idx = threadIdx.x; idx < N1 * N1; idx += blockDim.x) A1[idx] = A1g[idx];
   for (int r = threadIdx.x; r < N1; r += blockDim.x) {
     const int mm = g1.n - 1;
     const int i = 1 + r % mm, j = 1 + (r / mm) % mm, l = DIM == 3 ? 1 + r / (mm * mm) : 0;
-    G[r] = m1 * slot->g[fine_load_index(nf1, fs, i, j, l)];
+    const long long fi = fine_load_index(nf1, fs, i, j, l);
+    G[r] = m1 * slot->g[fi];
+    MC[r] = cw ? m1 * cw[fi] : m1;
     U[r] = 0.0;
   }
   __syncthreads();
@@ -1255,7 +1362,7 @@ __device__ __forceinline__ void level1_newton_dev(const Grid& g1, int N1, const 
       t1 += V[a] * t;
       double f, df, F;
       NL<KIND>::all(V[a], q, f, df, F);
-      t2 += m1 * F;
+      t2 += MC[a] * F;
       t3 += G[a] * V[a];
     }
     t1 *= 0.5;
@@ -1277,8 +1384,8 @@ __device__ __forceinline__ void level1_newton_dev(const Grid& g1, int N1, const 
       for (int b = 0; b < N1; ++b) t += A1[a * N1 + b] * U[b];
       double f, df, F;
       NL<KIND>::all(U[a], q, f, df, F);
-      R[a] = t + m1 * f - G[a];
-      J[a * N1 + a] += m1 * df;
+      R[a] = t + MC[a] * f - G[a];
+      J[a * N1 + a] += MC[a] * df;
       D[a] = -R[a];
     }
     __syncthreads();
@@ -1334,9 +1441,20 @@ __device__ __forceinline__ void level1_newton_dev(const Grid& g1, int N1, const 
 // Solve bookkeeping
 // ---------------------------------------------------------------------------
 static __global__ void k_set_slot(ProblemSlot* slot, const double* g, double* u_out, fmg_report* rep_out, double param,
-                           int kind) {
+                           int kind, const double* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     slot->g = g; slot->u_out = u_out; slot->rep_out = rep_out; slot->param = param; slot->kind = kind;
+    slot->c = c;
+  }
+}
+
+// The hierarchy's part of the slot: finest nodes per side and the stencil
+// arrays of the variable-coefficient operator (all nullptr for A = I).
+static __global__ void k_init_slot(ProblemSlot* slot, int nf1, CoefLevels coef) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    slot->nf1 = nf1;
+    slot->coef = coef;
+    slot->c = nullptr;
   }
 }
 

@@ -11,7 +11,7 @@
 
 namespace fmg {
 
-template <int DIM, int KIND>
+template <int DIM, int KIND, bool CW = false>
 void launch_rhs(dim3 grid, hipStream_t st, Grid g, const ProblemSlot* slot, int nf1, int fs, const double* u,
                 double* b, double m);
 
@@ -24,13 +24,13 @@ template <int DIM, int KIND>
 void launch_rhs_elem(dim3 grid, hipStream_t st, Grid g, const ProblemSlot* slot, int nf1, int fs, const double* u,
                      double* contrib, double* b, double m);
 
-template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM = false>
+template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM = false, bool VAR = false>
 void launch_aug_pass(int blocks, int threads, size_t lds, hipStream_t st, Grid g, AugShape s, const double* ut,
                      const ProblemSlot* slot, int nf1, int fs, double scale, double m, const double* A1,
                      NewtonState* ns, fmg_report* rep, double* pq, double* ps, unsigned* tickets, int level,
                      int newton_max, double tol);
 
-template <int DIM, int KIND, bool ELEM = false>
+template <int DIM, int KIND, bool ELEM = false, bool VAR = false>
 void launch_newton_finish(size_t lds, hipStream_t st, Grid g, AugShape s, const double* ut,
                           const ProblemSlot* slot, const double* A1, double m, NewtonState* ns, fmg_report* rep,
                           int newton_max, double tol);
@@ -43,7 +43,7 @@ void launch_level1(size_t lds, hipStream_t st, Grid g1, int N1, const double* A1
                    const ProblemSlot* slot, int nf1, int fs, double* x1, fmg_report* rep, int newton_max,
                    double tol, int levels, int* flag, int fold, TransitionArgs next);
 
-template <int DIM, int KIND, bool AUG>
+template <int DIM, int KIND, bool AUG, bool CW = false>
 void launch_transition(dim3 grid, hipStream_t st, TransitionArgs a, const NewtonState* ns,
                        const ProblemSlot* slot);
 

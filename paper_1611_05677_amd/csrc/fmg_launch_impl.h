@@ -7,10 +7,10 @@
 
 namespace fmg {
 
-template <int DIM, int KIND>
+template <int DIM, int KIND, bool CW>
 void launch_rhs(dim3 grid, hipStream_t st, Grid g, const ProblemSlot* slot, int nf1, int fs, const double* u,
                 double* b, double m) {
-  k_rhs<DIM, KIND><<<grid, kBlock, 0, st>>>(g, slot, nf1, fs, u, b, m);
+  k_rhs<DIM, KIND, CW><<<grid, kBlock, 0, st>>>(g, slot, nf1, fs, u, b, m);
 }
 
 template <int DIM, int KIND>
@@ -32,21 +32,21 @@ void launch_rhs_elem(dim3 grid, hipStream_t st, Grid g, const ProblemSlot* slot,
   k_rhs_elem_nodes<DIM><<<grid, kBlock, 0, st>>>(g, contrib, b, m * ElemRule<DIM>::W);
 }
 
-template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM>
+template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM, bool VAR>
 void launch_aug_pass(int blocks, int threads, size_t lds, hipStream_t st, Grid g, AugShape s, const double* ut,
                      const ProblemSlot* slot, int nf1, int fs, double scale, double m, const double* A1,
                      NewtonState* ns, fmg_report* rep, double* pq, double* ps, unsigned* tickets, int level,
                      int newton_max, double tol) {
-  k_aug_pass<DIM, KIND, SETUP, FINISH, ELEM><<<blocks, threads, lds, st>>>(g, s, ut, slot, nf1, fs, scale, m, A1, ns,
+  k_aug_pass<DIM, KIND, SETUP, FINISH, ELEM, VAR><<<blocks, threads, lds, st>>>(g, s, ut, slot, nf1, fs, scale, m, A1, ns,
                                                                            rep, pq, ps, tickets, level, newton_max,
                                                                            tol);
 }
 
-template <int DIM, int KIND, bool ELEM>
+template <int DIM, int KIND, bool ELEM, bool VAR>
 void launch_newton_finish(size_t lds, hipStream_t st, Grid g, AugShape s, const double* ut,
                           const ProblemSlot* slot, const double* A1, double m, NewtonState* ns, fmg_report* rep,
                           int newton_max, double tol) {
-  k_newton_finish<DIM, KIND, ELEM><<<1, kBlock, lds, st>>>(g, s, ut, slot, A1, m, ns, rep, newton_max, tol);
+  k_newton_finish<DIM, KIND, ELEM, VAR><<<1, kBlock, lds, st>>>(g, s, ut, slot, A1, m, ns, rep, newton_max, tol);
 }
 
 template <int DIM, int KIND, bool MIXED>
@@ -62,10 +62,10 @@ void launch_level1(size_t lds, hipStream_t st, Grid g1, int N1, const double* A1
                                                   flag, fold, next);
 }
 
-template <int DIM, int KIND, bool AUG>
+template <int DIM, int KIND, bool AUG, bool CW>
 void launch_transition(dim3 grid, hipStream_t st, TransitionArgs a, const NewtonState* ns,
                        const ProblemSlot* slot) {
-  k_transition<DIM, KIND, AUG><<<grid, kBlock, 0, st>>>(a, ns, slot);
+  k_transition<DIM, KIND, AUG, CW><<<grid, kBlock, 0, st>>>(a, ns, slot);
 }
 
 }  // namespace fmg
@@ -133,4 +133,33 @@ void launch_transition(dim3 grid, hipStream_t st, TransitionArgs a, const Newton
   template void launch_newton_finish<D, K, true>(size_t, hipStream_t, Grid, AugShape, const double*,   \
                                                  const ProblemSlot*, const double*, double, NewtonState*, \
                                                  fmg_report*, int, double);                           \
+  }
+
+// The variable-coefficient kernels for dimension D and nonlinearity K: the
+// weighted right-hand side and transitions, setup and quadrature passes and
+// the Newton finisher.  Instantiated in fmg_kind_{2d,3d}_v.hip.
+#define FMG_INSTANTIATE_VAR(D, K)                                                                    \
+  namespace fmg {                                                                                    \
+  template void launch_rhs<D, K, true>(dim3, hipStream_t, Grid, const ProblemSlot*, int, int,        \
+                                       const double*, double*, double);                              \
+  template void launch_transition<D, K, true, true>(dim3, hipStream_t, TransitionArgs,               \
+                                                    const NewtonState*, const ProblemSlot*);         \
+  template void launch_transition<D, K, false, true>(dim3, hipStream_t, TransitionArgs,              \
+                                                     const NewtonState*, const ProblemSlot*);        \
+  template void launch_aug_pass<D, K, true, false, false, true>(int, int, size_t, hipStream_t, Grid,  \
+                                                                AugShape, const double*,             \
+                                                                const ProblemSlot*, int, int, double, \
+                                                                double, const double*, NewtonState*,  \
+                                                                fmg_report*, double*, double*,        \
+                                                                unsigned*, int, int, double);         \
+  template void launch_aug_pass<D, K, false, false, false, true>(int, int, size_t, hipStream_t, Grid, \
+                                                                 AugShape, const double*,            \
+                                                                 const ProblemSlot*, int, int, double, \
+                                                                 double, const double*, NewtonState*, \
+                                                                 fmg_report*, double*, double*,       \
+                                                                 unsigned*, int, int, double);        \
+  template void launch_newton_finish<D, K, false, true>(size_t, hipStream_t, Grid, AugShape,           \
+                                                        const double*, const ProblemSlot*,             \
+                                                        const double*, double, NewtonState*,           \
+                                                        fmg_report*, int, double);                    \
   }

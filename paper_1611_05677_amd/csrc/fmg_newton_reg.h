@@ -333,8 +333,11 @@ __device__ __forceinline__ void level1_dispatch(const Grid& g1, int N1, const do
                                                 const ProblemSlot* __restrict__ slot, int nf1, int fs,
                                                 double* __restrict__ x1, fmg_report* __restrict__ rep,
                                                 int newton_max, double tol, double* smem) {
-  if (DIM == 2 && N1 == 9) level1_newton_reg<DIM, KIND, 9>(g1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
-  else if (DIM == 3 && N1 == 27)
+  // the register path assumes A = I (constant stencil, c = 1)
+  const bool plain = slot->coef.w[1] == nullptr && slot->c == nullptr;
+  if (DIM == 2 && N1 == 9 && plain)
+    level1_newton_reg<DIM, KIND, 9>(g1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
+  else if (DIM == 3 && N1 == 27 && plain)
     level1_newton_reg<DIM, KIND, 27>(g1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
   else level1_newton_dev<DIM, KIND>(g1, N1, A1g, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
   __syncthreads();
@@ -345,8 +348,8 @@ template <int DIM>
 __device__ __forceinline__ void newton_step_dev(const AugShape& s, const double* cs, const double* __restrict__ A1,
                                                 double m, NewtonState* ns, fmg_report* rep, int newton_max,
                                                 double tol, double* sm) {
-  if (DIM == 2 && s.N1 == 9) newton_core_reg<DIM, 10>(s, cs, m, ns, rep, newton_max, tol, sm);
-  else if (DIM == 3 && s.N1 == 27) newton_core_reg<DIM, 28>(s, cs, m, ns, rep, newton_max, tol, sm);
+  if (DIM == 2 && s.N1 == 9 && !s.general) newton_core_reg<DIM, 10>(s, cs, m, ns, rep, newton_max, tol, sm);
+  else if (DIM == 3 && s.N1 == 27 && !s.general) newton_core_reg<DIM, 28>(s, cs, m, ns, rep, newton_max, tol, sm);
   else newton_core<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
 }
 

@@ -45,7 +45,8 @@ int main(void) {{
   P(fmg_options, omega); P(fmg_options, newton_tol); P(fmg_options, newton_passes);
   P(fmg_options, converged_tol); P(fmg_options, use_graph);
   P(fmg_report, newton_iters); P(fmg_report, newton_total); P(fmg_report, alpha);
-  P(fmg_report, last_update_rel); P(fmg_problem, g_nodes);
+  P(fmg_report, last_update_rel); P(fmg_problem, g_nodes); P(fmg_problem, f_weight);
+  P(fmg_options, quadrature); P(fmg_options, coefficients);
   return 0;
 }}""")
     exe = tmp_path / "layout"
@@ -189,3 +190,30 @@ def test_element_rule_option_is_validated_on_the_host():
     assert B.workspace_bytes(2, 4, 3, B.default_options(2, quadrature=2)) == 0
     assert B.workspace_bytes(2, 4, 3, B.default_options(2, quadrature=B.FMG_QUAD_ELEMENT,
                                                          fuse_small_levels=1)) == 0
+
+
+def test_variable_coefficient_option_is_validated_on_the_host():
+    """fmg_options.coefficients: identity (default) or variable; the variable
+    operator needs float64, the vertex rule and no fused small levels; its
+    workspace holds the stencil arrays of every level; fmg_set_coefficients
+    and fmg_solve_noalloc refuse before any HIP call."""
+    o = B.default_options(3)
+    assert o.coefficients == B.FMG_COEF_IDENTITY
+    var = B.default_options(3, coefficients=B.FMG_COEF_VARIABLE)
+    base, big = B.workspace_bytes(3, 4, 4, o), B.workspace_bytes(3, 4, 4, var)
+    nodes = 65 ** 3
+    assert big - base >= 8 * 7 * nodes                   # seven forward-edge planes on the finest level
+    assert B.workspace_bytes(2, 4, 3, B.default_options(2, coefficients=2)) == 0
+    for bad in (dict(precision=B.FMG_MIXED), dict(quadrature=B.FMG_QUAD_ELEMENT), dict(fuse_small_levels=1)):
+        assert B.workspace_bytes(2, 4, 3, B.default_options(2, coefficients=B.FMG_COEF_VARIABLE, **bad)) == 0
+    fake = ctypes.c_void_p(0x1000)                       # never dereferenced
+    assert B.LIB.fmg_set_coefficients(None, fake, None) == B.FMG_E_INVALID
+    small = B.MeshDesc(2, 4, 3)
+    prob = B.ProblemC(2, 0.0, fake)
+    v2 = B.default_options(2, coefficients=B.FMG_COEF_VARIABLE)
+    assert B.LIB.fmg_solve_noalloc(ctypes.byref(small), ctypes.byref(v2), ctypes.byref(prob), fake, None,
+                                   None) == B.FMG_E_UNSUPPORTED
+    weighted = B.ProblemC(2, 0.0, fake, fake)
+    o2 = B.default_options(2)
+    assert B.LIB.fmg_solve_noalloc(ctypes.byref(small), ctypes.byref(o2), ctypes.byref(weighted), fake, None,
+                                   None) == B.FMG_E_UNSUPPORTED

@@ -1,0 +1,274 @@
+"""GPU parity of the variable-coefficient operator -div(A(x) grad u) and of
+f(x, u) = c(x) f(u) (fmg_options.coefficients = FMG_COEF_VARIABLE) through
+the C ABI.
+
+* the level operators against the oracle's Galerkin hierarchy (A_k = P^T
+  A_{k+1} P from the element-by-element finest assembly): stiffness,
+  Jacobi sweep, residual restriction and the level-1 solve, relative 1e-13;
+* paper mode against O2 with the same coefficients, element by element:
+  relative L2 <= 1e-10, Newton counts within one, alpha to 1e-9;
+* converged mode against O1 (the exact discrete solution): 1e-10;
+* the Theorem 3.2 gate on the manufactured problem, A = I reproducing the
+  constant-coefficient solve, graph replay, batches and the error paths.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from oracle.nonlinear import Nonlinearity  # noqa: E402
+from oracle.norms import nodal_l2  # noqa: E402
+from oracle.o1 import solve_fine  # noqa: E402
+from oracle.o2 import Hierarchy as O2H  # noqa: E402
+from oracle.o2 import Options as O2Options  # noqa: E402
+from oracle.o2 import fmg as o2_fmg  # noqa: E402
+from paper_1611_05677_amd import binding as B  # noqa: E402
+from paper_1611_05677_amd import workloads as W  # noqa: E402
+
+DEV = "cuda:0"
+PARITY = 1e-10
+OP_TOL = 1e-13
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def gpu_hierarchy(P, **opt):
+    H = B.Hierarchy(P.dim, P.coarse_cells, P.refinements,
+                    B.default_options(P.dim, coefficients=B.FMG_COEF_VARIABLE, **opt), device=DEV)
+    H.set_coefficients(dev(P.coef_cells))
+    return H
+
+
+def gpu_solve(P, **opt):
+    H = gpu_hierarchy(P, **opt)
+    c = dev(P.f_weight_nodes) if P.f_weight_nodes is not None else None
+    u, rep = H.solve(dev(P.g_nodes), P.f_kind, P.f_param, c=c)
+    out = u.cpu().numpy()
+    H.close()
+    return out, rep
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# level operators
+# ---------------------------------------------------------------------------
+OP_CASES = [(2, 3, 3), (2, 4, 4), (3, 2, 3), (3, 4, 2)]
+
+
+def _op_setup(dim, nH, L):
+    P = W.random_coefficient("ops", dim, nH, L, W.F_CUBIC, [21, dim, nH])
+    G = gpu_hierarchy(P)
+    O = O2H(dim, nH, L, coef=P.coef_cells)
+    return P, G, O
+
+
+def _rand_full(mesh, seed):
+    v = np.random.default_rng(seed).standard_normal(mesh.coords.shape[0])
+    v[mesh.boundary] = 0.0
+    return v
+
+
+@pytest.mark.parametrize("dim,nH,L", OP_CASES)
+def test_stiffness_sweep_and_restriction_match_the_galerkin_hierarchy(dim, nH, L):
+    P, G, O = _op_setup(dim, nH, L)
+    for k in range(1, L + 2):
+        lev = O.levels[k - 1]
+        mesh, I = lev.mesh, lev.mesh.interior
+        x, b = _rand_full(mesh, 10 * k), _rand_full(mesh, 10 * k + 1)
+        # stiffness
+        expect = np.zeros_like(x)
+        expect[I] = lev.A @ x[I]
+        got = G.level_op(B.FMG_OP_APPLY_A, k, dev(x)).cpu().numpy()
+        assert np.max(np.abs(got - expect)) <= OP_TOL * np.max(np.abs(expect)), ("A", k)
+        # one damped Jacobi sweep with D = diag(A_k)
+        w = 0.7
+        expect = np.zeros_like(x)
+        expect[I] = x[I] + w * (b[I] - lev.A @ x[I]) / lev.A.diagonal()
+        got = G.level_op(B.FMG_OP_SMOOTH, k, dev(x), dev(b), omega=w).cpu().numpy()
+        assert np.max(np.abs(got - expect)) <= OP_TOL * np.max(np.abs(expect)), ("smooth", k)
+        if k >= 2:
+            cm = O.levels[k - 2].mesh
+            expect = np.zeros(cm.coords.shape[0])
+            expect[cm.interior] = lev.P.T @ (b[I] - lev.A @ x[I])
+            got = G.level_op(B.FMG_OP_RESTRICT, k, dev(x), dev(b)).cpu().numpy()
+            assert np.max(np.abs(got - expect)) <= OP_TOL * np.max(np.abs(expect)), ("restrict", k)
+    m1 = O.levels[0].mesh
+    b1 = _rand_full(m1, 99)
+    expect = np.zeros_like(b1)
+    expect[m1.interior] = np.linalg.solve(O.A1, b1[m1.interior])
+    got = G.level_op(B.FMG_OP_COARSE, 1, dev(b1)).cpu().numpy()
+    assert np.max(np.abs(got - expect)) <= 1e-12 * np.max(np.abs(expect))
+    G.close()
+
+
+def test_isotropic_unit_matrix_gives_the_constant_stencil():
+    """A = I through the variable-coefficient path: the stencil arrays must
+    reproduce the constant 5-/7-point operator."""
+    for dim, nH, L in [(2, 4, 3), (3, 4, 2)]:
+        n = nH * 2 ** L
+        P = W.random_coefficient("unit", dim, nH, L, W.F_CUBIC, [22])
+        P.coef_cells = W.scalar_coefficient(dim, np.ones(n ** dim))
+        G = gpu_hierarchy(P)
+        C = B.Hierarchy(dim, nH, L, B.default_options(dim), device=DEV)
+        for k in range(1, L + 2):
+            mesh = O2H(dim, nH, k - 1).levels[-1].mesh
+            x = _rand_full(mesh, k)
+            a = G.level_op(B.FMG_OP_APPLY_A, k, dev(x)).cpu().numpy()
+            c = C.level_op(B.FMG_OP_APPLY_A, k, dev(x)).cpu().numpy()
+            assert np.max(np.abs(a - c)) <= 1e-14 * np.max(np.abs(c)), k
+        G.close()
+        C.close()
+
+
+# ---------------------------------------------------------------------------
+# full solves
+# ---------------------------------------------------------------------------
+CASES = [
+    W.variable_coefficient("v2_L3", 2, 4, 3, W.F_CUBIC),
+    W.variable_coefficient("v2_L5", 2, 4, 5, W.F_U_PLUS_SIN),
+    W.variable_coefficient("v2_iso", 2, 4, 4, W.F_NEG_EXP, isotropic=True),
+    W.variable_coefficient("v3_L2", 3, 4, 2, W.F_U_PLUS_SIN),
+    W.variable_coefficient("v3_L3", 3, 4, 3, W.F_CUBIC),
+    W.random_coefficient("r2", 2, 4, 4, W.F_U_PLUS_SIN, [23, 1]),
+    W.random_coefficient("r2_abs", 2, 4, 3, W.F_ABS_U_U, [23, 2]),
+    W.random_coefficient("r2_pow", 2, 4, 3, W.F_SIGNED_POW, [23, 3], f_param=1.5),
+    W.random_coefficient("r3", 3, 4, 2, W.F_CUBIC, [23, 4]),
+    W.random_coefficient("r3_lin", 3, 4, 2, W.F_LINEAR, [23, 5], f_param=2.0),
+    # general level-1 and Newton paths (N_1 not 9 or 27), ragged coarse grids
+    W.random_coefficient("r2_nH3", 2, 3, 4, W.F_U_PLUS_SIN, [23, 6]),
+    W.random_coefficient("r3_nH2", 3, 2, 3, W.F_CUBIC, [23, 7]),
+    W.random_coefficient("r2_nH5", 2, 5, 3, W.F_CUBIC, [23, 8]),
+]
+
+
+def _o2(P, converged=False):
+    H = O2H(P.dim, P.coarse_cells, P.refinements, coef=P.coef_cells)
+    return o2_fmg(H, P.g_nodes, Nonlinearity(P.f_kind, P.f_param), O2Options(), converged=converged,
+                  f_weight=P.f_weight_nodes)
+
+
+@pytest.mark.parametrize("P", CASES, ids=[p.name for p in CASES])
+def test_paper_mode_matches_cpu_replica(P):
+    u, rep = gpu_solve(P)
+    assert rep["status"] == 0, rep
+    res = _o2(P)
+    expect = res.full()
+    assert rel(u, expect) <= PARITY, rel(u, expect)
+    assert abs(rep["level1_iters"] - res.level1_iters) <= 1, (rep["level1_iters"], res.level1_iters)
+    for s in res.steps:
+        assert abs(rep["newton_iters"][s.level - 1] - s.newton_iters) <= 1
+        assert abs(rep["alpha"][s.level - 1] - s.alpha) <= 1e-9 * max(1.0, abs(s.alpha))
+
+
+def test_without_weight_matches_the_replica_with_c_one():
+    P = W.random_coefficient("r2_c1", 2, 4, 4, W.F_U_PLUS_SIN, [24])
+    P.f_weight_nodes = None
+    u, rep = gpu_solve(P)
+    assert rep["status"] == 0, rep
+    assert rel(u, _o2(P).full()) <= PARITY
+
+
+@pytest.mark.parametrize("P", [W.variable_coefficient("cv2", 2, 4, 4, W.F_CUBIC),
+                               W.random_coefficient("cv3", 3, 4, 2, W.F_U_PLUS_SIN, [25])], ids=["2d", "3d"])
+def test_converged_mode_matches_fine_newton(P):
+    u, rep = gpu_solve(P, mode=B.FMG_CONVERGED)
+    assert rep["status"] == 0 and rep["extra_steps"] >= 1, rep
+    ref = solve_fine(P.dim, P.n, P.g_nodes, Nonlinearity(P.f_kind, P.f_param), coef=P.coef_cells,
+                     f_weight=P.f_weight_nodes).full()
+    assert rel(u, ref) <= PARITY, rel(u, ref)
+
+
+@pytest.mark.parametrize("dim,L", [(2, 6), (3, 4)])
+def test_solution_meets_the_gate(dim, L):
+    """Theorem 3.2's gate on the manufactured problem: algebraic error at
+    most half the discretisation error (O1 gives ubar_h)."""
+    P = W.variable_coefficient("gate", dim, 4, L, W.F_CUBIC if dim == 2 else W.F_U_PLUS_SIN)
+    u, rep = gpu_solve(P)
+    assert rep["status"] == 0, rep
+    o1 = solve_fine(P.dim, P.n, P.g_nodes, Nonlinearity(P.f_kind), coef=P.coef_cells, f_weight=P.f_weight_nodes)
+    I = o1.mesh.interior
+    disc = nodal_l2(o1.m, o1.U - P.u_exact_nodes[I])
+    assert nodal_l2(o1.m, u[I] - o1.U) <= 0.5 * disc
+    assert nodal_l2(o1.m, u[I] - P.u_exact_nodes[I]) <= 1.1 * disc
+
+
+def test_unit_matrix_reproduces_the_constant_coefficient_solve():
+    P = W.square_cubic_sin(4)
+    n = P.n
+    P.coef_cells = W.scalar_coefficient(2, np.ones(n * n))
+    u, rep = gpu_solve(P)
+    C = B.Hierarchy(2, 4, 4, B.default_options(2), device=DEV)
+    uc, _ = C.solve(dev(P.g_nodes), P.f_kind, P.f_param)
+    C.close()
+    assert rel(u, uc.cpu().numpy()) <= 1e-12
+
+
+def test_graph_and_direct_launches_agree_bitwise():
+    P = W.random_coefficient("gr", 3, 4, 2, W.F_U_PLUS_SIN, [26])
+    a, _ = gpu_solve(P)
+    b, _ = gpu_solve(P, use_graph=0)
+    assert np.array_equal(a, b)
+
+
+def test_new_coefficients_take_effect_in_a_captured_graph():
+    P = W.random_coefficient("re", 2, 4, 4, W.F_CUBIC, [27])
+    Q = W.random_coefficient("re2", 2, 4, 4, W.F_CUBIC, [28])
+    H = gpu_hierarchy(P)
+    g, c = dev(P.g_nodes), dev(P.f_weight_nodes)
+    u1, _ = H.solve(g, P.f_kind, c=c)
+    H.set_coefficients(dev(Q.coef_cells))
+    u2, _ = H.solve(g, P.f_kind, c=c)
+    H.close()
+    Q.g_nodes, Q.f_weight_nodes = P.g_nodes, P.f_weight_nodes
+    assert rel(u1.cpu().numpy(), _o2(P).full()) <= PARITY
+    assert rel(u2.cpu().numpy(), _o2(Q).full()) <= PARITY
+
+
+def test_batch_with_weights_matches_single_solves():
+    Ps = [W.random_coefficient(f"b{i}", 2, 4, 3 + i % 2, W.F_U_PLUS_SIN, [29, i]) for i in range(3)]
+    Hs = [gpu_hierarchy(P) for P in Ps]
+    gs = [dev(P.g_nodes) for P in Ps]
+    cs = [dev(P.f_weight_nodes) for P in Ps]
+    outs = [torch.empty_like(g) for g in gs]
+    n = len(Ps)
+    import ctypes
+    Hc = (ctypes.c_void_p * n)(*[h.handle for h in Hs])
+    Pc = (B.ProblemC * n)(*[B._problem(P.f_kind, P.f_param, g, c) for P, g, c in zip(Ps, gs, cs)])
+    Oc = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    assert B.LIB.fmg_solve_batch(Hc, Pc, Oc, None, n, ctypes.c_void_p(B._stream_ptr())) == B.FMG_OK
+    torch.cuda.synchronize()
+    for P, H, g, c, o in zip(Ps, Hs, gs, cs, outs):
+        single, _ = H.solve(g, P.f_kind, c=c)
+        assert np.array_equal(o.cpu().numpy(), single.cpu().numpy())
+        assert rel(o.cpu().numpy(), _o2(P).full()) <= PARITY
+        H.close()
+
+
+def test_error_paths():
+    P = W.random_coefficient("err", 2, 4, 3, W.F_CUBIC, [30])
+    H = B.Hierarchy(2, 4, 3, B.default_options(2, coefficients=B.FMG_COEF_VARIABLE), device=DEV)
+    g, c = dev(P.g_nodes), dev(P.f_weight_nodes)
+    with pytest.raises(B.FMGError) as e:          # no coefficients yet
+        H.solve_async(g, P.f_kind)
+    assert e.value.code == B.FMG_E_INVALID
+    H.close()
+    C = B.Hierarchy(2, 4, 3, B.default_options(2), device=DEV)
+    with pytest.raises(B.FMGError) as e:          # c(x) needs the variable-coefficient kernels
+        C.solve_async(g, P.f_kind, c=c)
+    assert e.value.code == B.FMG_E_UNSUPPORTED
+    with pytest.raises(B.FMGError) as e:
+        C.set_coefficients(dev(P.coef_cells))
+    assert e.value.code == B.FMG_E_INVALID
+    C.close()
+    with pytest.raises(B.FMGError) as e:
+        B.solve_noalloc(2, 4, 3, g, P.f_kind, opts=B.default_options(2, coefficients=B.FMG_COEF_VARIABLE))
+    assert e.value.code == B.FMG_E_UNSUPPORTED
