@@ -123,12 +123,12 @@ def run_mode(B, torch, P, g, precision, steps, warmup, golden, uc):
     return H, res
 
 
-def profile_mode(B, H, P, g, torch):
+def profile_mode(B, H, P, g, torch, c=None):
     """Per-kernel HIP-event timing of one direct-launch solve (same stream)."""
     import ctypes
     prof = B.Profile()
     out = torch.empty(H.nodes(), dtype=torch.float64, device="cuda:0")
-    prob = B.ProblemC(int(P.f_kind), float(P.f_param), ctypes.c_void_p(g.data_ptr()))
+    prob = B._problem(P.f_kind, P.f_param, g, c)
     B._check(B.LIB.fmg_profile_solve(H.handle, ctypes.byref(prob), ctypes.c_void_p(out.data_ptr()),
                                      ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
                                      ctypes.byref(prof)), "fmg_profile_solve")
@@ -637,6 +637,163 @@ def element_mode(args, B, W, torch):
     return line
 
 
+VARIABLE_DESC = ("variable coefficient: 3D unit cube, Kuhn tetrahedra, coarse 4^3 refined 6 times (256^3, "
+                 "16,581,375 DOFs); -div(A grad u) + c(x) (u + sin u) = g with A(x) = (1 + s/2) B constant per cell "
+                 "(s = sin(pi x) sin(pi y) sin(pi z) at the cell centre, B a fixed symmetric positive definite "
+                 "matrix with off-diagonal entries: the 15-point Kuhn stencil), c = 1 + cos(pi x)/2 at the nodes, "
+                 "g manufactured from u = s; every level the Galerkin restriction of the finest form; m = 2 V(2,2) "
+                 "Chebyshev-weighted cycles, p = 1, float64")
+# the weighted Jacobi sweep at the finest level (HBM bound: x, b, the seven
+# forward-edge weight planes in, the new iterate out)
+VAR_ROOF_KERNEL = ("smooth_var_f64", "fmg_kernels_coef.h")
+
+
+def variable_cpu_baseline(W):
+    """The variable-coefficient oracle O2 on the host, single thread, on a
+    bounded sample: the same manufactured problem two levels coarser (64^3).
+    The Galerkin hierarchy (the analogue of fmg_create_hierarchy plus
+    fmg_set_coefficients) is built untimed; the median of ten solves is
+    reported."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.nonlinear import Nonlinearity
+    from oracle.o2 import Hierarchy as O2H
+    from oracle.o2 import fmg as o2_fmg
+    S = W.variable_coefficient("cube64_var", 3, 4, 4, W.F_U_PLUS_SIN)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        H = O2H(S.dim, S.coarse_cells, S.refinements, coef=S.coef_cells)
+        build_s = time.perf_counter() - t0
+        nl = Nonlinearity(S.f_kind, S.f_param)
+        times = []
+        for _ in range(10):
+            t0 = time.perf_counter()
+            o2_fmg(H, S.g_nodes, nl, f_weight=S.f_weight_nodes)
+            times.append(time.perf_counter() - t0)
+        o2_s = float(np.median(times))
+    return {"value": S.interior_dofs / o2_s, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"O2 with the coefficients (scipy CSR, the oracle's replica of the FMG scheme): {S.name} "
+                      f"({S.interior_dofs} DOFs, the benchmark's problem two levels coarser), median of 10 "
+                      f"solves {o2_s:.3f} s; Galerkin hierarchy {build_s:.1f} s not timed",
+            "o2_solve_s": o2_s, "o2_dofs": S.interior_dofs, "hierarchy_s": build_s, "cpu_model": _cpu_model(),
+            "threads_used": "1 (scipy sparse kernels are single-threaded; BLAS pools limited to 1)"}
+
+
+def variable_mode(args, B, W, torch):
+    """The variable-coefficient operator (fmg_options.coefficients =
+    FMG_COEF_VARIABLE) on the largest configuration: float64 throughput and
+    latency of the solve (the operator set once beforehand, its setup timed
+    on its own), the accuracy gate against ubar_h of the same operator (the
+    library's converged mode, which the tests match to the oracle O1), the
+    HBM roofline of the weighted sweep and the per-kernel profile."""
+    depth = 6
+    P = W.variable_coefficient("cube256_var", 3, 4, depth, W.F_U_PLUS_SIN)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")   # noqa: E731
+    g, c, coef = dev(P.g_nodes), dev(P.f_weight_nodes), dev(P.coef_cells)
+    VAR = B.FMG_COEF_VARIABLE
+    if args.roofline_only:
+        # counter runs: the weighted sweep alone (as timed below) and a plain
+        # 256 MiB device copy that calibrates FETCH_SIZE / WRITE_SIZE
+        H = B.Hierarchy(3, 4, depth, B.default_options(3, coefficients=VAR), device="cuda:0")
+        H.set_coefficients(coef)
+        ms, nbytes = B.time_level_kernel(H, VAR_ROOF_KERNEL[0], H.levels, args.roof_reps)
+        n = 1 << 25
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        H.close()
+        return {"roofline_only": VAR_ROOF_KERNEL[0], "avg_launch_us": ms * 1e3, "bytes_per_launch": nbytes,
+                "copy_bytes_each_way": 8 * n, "copies": 3}
+    if args.only:
+        uc = np.zeros(P.g_nodes.shape)
+        crep = {"status": None, "extra_steps": None, "last_update_rel": None}
+    else:
+        Hc = B.Hierarchy(3, 4, depth, B.default_options(3, mode=B.FMG_CONVERGED, coefficients=VAR), device="cuda:0")
+        Hc.set_coefficients(coef)
+        uct, crep = Hc.solve(g, P.f_kind, P.f_param, c=c)
+        Hc.close()
+        uc = uct.cpu().numpy()
+    disc = nodal(P, uc - P.u_exact_nodes)
+    stream = torch.cuda.current_stream()
+    H = B.Hierarchy(3, 4, depth, B.default_options(3, coefficients=VAR), device="cuda:0")
+    setup_ms = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        H.set_coefficients(coef)
+        b.record(stream)
+        torch.cuda.synchronize()
+        setup_ms.append(a.elapsed_time(b))
+    out = torch.empty(H.nodes(), dtype=torch.float64, device="cuda:0")
+    for _ in range(args.warmup):
+        H.solve_async(g, P.f_kind, P.f_param, out, c=c)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        H.solve_async(g, P.f_kind, P.f_param, out, c=c)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = [a.elapsed_time(b) for a, b in ev]
+    rep = H.report()
+    u = out.cpu().numpy()
+    exact_err, alg = nodal(P, u - P.u_exact_nodes), nodal(P, u - uc)
+    res = {"dof_per_s": P.interior_dofs / (wall / args.steps), "ms_per_solve": 1e3 * wall / args.steps,
+           "latency_ms_p50": percentile(lat, 50), "latency_ms_p99": percentile(lat, 99),
+           "status": rep["status"], "newton_iters": rep["newton_iters"], "level1_iters": rep["level1_iters"],
+           "err_vs_exact_nodal_l2": exact_err, "disc_nodal_l2": disc, "alg_nodal_l2": alg,
+           "alg_over_disc": alg / disc if disc > 0 else None,
+           "gate_total_le_1.1disc": bool(exact_err <= 1.1 * disc),
+           "gate_alg_le_0.5disc": bool(alg <= 0.5 * disc)}
+    res["gate_pass"] = bool(res["gate_total_le_1.1disc"] and res["gate_alg_le_0.5disc"] and rep["status"] == 0)
+    log(f"variable fp64: {res['ms_per_solve']:.3f} ms/solve, {res['dof_per_s'] / 1e9:.3f} GDOF/s, "
+        f"setup {min(setup_ms):.2f} ms, alg/disc {res['alg_over_disc']}, gate {res['gate_pass']}")
+    rows = None
+    if not args.no_profile:
+        total_ms, rows = profile_mode(B, H, P, g, torch, c)
+        res["profile_event_ms_total"] = total_ms
+        res["profile_rows"] = sorted(rows, key=lambda r: -r["ms"])[:30]
+    name, fname = VAR_ROOF_KERNEL
+    ms, nbytes = B.time_level_kernel(H, name, H.levels, args.roof_reps)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    e = _counter_entry(TRAFFIC_FILE, name, "cube256_var", fname)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": e["hbm_bytes_per_launch"] if e else None,
+            "kernel": name, "level": H.levels, "launches_timed": args.roof_reps, "avg_launch_us": ms * 1e3,
+            "bytes_per_launch": nbytes,
+            "bytes_model": "8 B x 10 N: read x, b and the seven forward-edge weight planes, write the new "
+                           "iterate, N interior nodes of the level",
+            "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT) if e else None}
+    H.close()
+    if args.only:
+        return {"only": args.only, "modes": {"fp64": {q: v for q, v in res.items() if q != "profile_rows"}},
+                "roofline": roof}
+    line = {
+        "metric": METRIC, "value": res["dof_per_s"], "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms_per_solve"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": VARIABLE_DESC, "dofs": P.interior_dofs, "levels": P.n_levels,
+                   "precision_of_value": "fp64 (plain; the variable operator runs in float64 only)"},
+        "latency_ms_p50": res["latency_ms_p50"], "latency_ms_p99": res["latency_ms_p99"],
+        "gate_pass": res["gate_pass"],
+        "coef_setup_ms": {"min": min(setup_ms), "all": setup_ms,
+                          "what": "fmg_set_coefficients: per-simplex means on every level, forward-edge "
+                                  "weights, A_1 and its inverse (once per coefficient field, outside the solve)"},
+        "converged_reference": {"status": crep["status"], "extra_steps": crep["extra_steps"],
+                                "last_update_rel": crep["last_update_rel"],
+                                "source": "the library's converged mode, same operator"},
+        "modes": {"fp64": res},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = variable_cpu_baseline(W)
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -646,7 +803,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 2D 2048^2 record")
     ap.add_argument("--workload", default="cube256",
-                    choices=sorted(WORKLOADS) + ["batch64", "serve", "examples", "element"])
+                    choices=sorted(WORKLOADS) + ["batch64", "serve", "examples", "element", "variable"])
     ap.add_argument("--max-depth", type=int, default=6, help="examples: deepest refinement")
     ap.add_argument("--requests", type=int, default=4000, help="serve: requests in the trace")
     ap.add_argument("--inflight", type=int, default=8, help="serve: concurrent solves")
@@ -671,9 +828,9 @@ def main():
     from paper_1611_05677_amd import binding as B
     from paper_1611_05677_amd import workloads as W
 
-    if args.workload in ("batch64", "serve", "examples", "element"):
+    if args.workload in ("batch64", "serve", "examples", "element", "variable"):
         mode = {"batch64": batch_mode, "serve": serve_mode, "examples": examples_mode,
-                "element": element_mode}[args.workload]
+                "element": element_mode, "variable": variable_mode}[args.workload]
         line = mode(args, B, W, torch)
         print(json.dumps(line), flush=True)
         return

@@ -306,7 +306,10 @@ int fmg_level_op(fmg_hierarchy *h, int op, int level, int precision,
  * ("pre_sweep_pair_3d_f64/f32", "prolong_sweep_pair_3d_f64/f32"), the 3D
  * plane-marching sweep ("smooth_3d_stream_f64/f32") and the separate sweep
  * ("smooth_f64/f32"), residual-restriction and prolongation-correction
- * kernels, in float64 or (mixed-mode hierarchies) float32.  The kernel is
+ * kernels, in float64 or (mixed-mode hierarchies) float32; in
+ * FMG_COEF_VARIABLE hierarchies the stencil-array sweep and residual
+ * ("smooth_var_f64", "resid_var_f64", after fmg_set_coefficients) and the
+ * prolongation.  The kernel is
  * launched with the solve's launch shape on level `level` (2..levels) of the
  * hierarchy's own buffers, which it overwrites (no solve may be in flight on
  * `h`): once untimed, then `reps` times back to back on `stream` between two

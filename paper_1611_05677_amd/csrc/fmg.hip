@@ -2171,8 +2171,39 @@ int time_launch(fmg_hierarchy* h, int base, int k, hipStream_t st, double& bytes
   }
 }
 
+// Variable-coefficient hierarchies: the weighted sweep and residual on level
+// k's buffers (and the shared prolongation).
+template <int DIM>
+int time_launch_var(fmg_hierarchy* h, int kernel, int k, hipStream_t st, double& bytes) {
+  const Plan& p = h->plan;
+  if (!h->coef_ready) return FMG_E_INVALID;
+  Roles R;
+  canonical_roles(h, R);
+  const LevelInfo& L = p.lev[k];
+  const long long N = interior(L.g, DIM);
+  const double nfw = (1 << DIM) - 1;
+  const double* W = h->at<double>(p.off_w[k]);
+  double* b = h->at<double>(p.off_b[k]);
+  switch (kernel) {
+    case KC_SMOOTHW64:
+      bytes = 8.0 * (3.0 + nfw) * N;
+      k_smooth_w<DIM, false><<<grid_of(L.g, DIM), kBlock, 0, st>>>(L.g, R.x[k], b, R.t[k], W, p.wplane[k],
+                                                                   h->ro.pre[0]);
+      return FMG_OK;
+    case KC_RESIDW64:
+      bytes = 8.0 * (3.0 + nfw) * N;
+      k_resid_w<DIM><<<grid_of(L.g, DIM), kBlock, 0, st>>>(L.g, R.x[k], b, R.t[k], W, p.wplane[k]);
+      return FMG_OK;
+    case KC_PROLONG64_ADD:
+      return time_launch<DIM, double>(h, kernel, k, st, bytes);
+    default:
+      return FMG_E_UNSUPPORTED;
+  }
+}
+
 template <int DIM>
 int time_launch_any(fmg_hierarchy* h, int kernel, int k, hipStream_t st, double& bytes) {
+  if (h->plan.var) return time_launch_var<DIM>(h, kernel, k, st, bytes);
   // classes come in float64 / float32 pairs at a fixed distance
   const int d_mg = KC_SMOOTH32 - KC_SMOOTH64, d_2d = KC_PRE2D32 - KC_PRE2D64;
   switch (kernel) {
@@ -2204,7 +2235,6 @@ extern "C" int fmg_time_level_kernel(fmg_hierarchy* h, int kernel, int level, in
   if (!h || !ms_per_launch || !bytes_per_launch || reps < 1 || reps > 100000 || level < 2 ||
       level > h->plan.nlev)
     return FMG_E_INVALID;
-  if (h->plan.var) return FMG_E_UNSUPPORTED;
   hipStream_t s = static_cast<hipStream_t>(stream);
   double bytes = 0.0;
   auto once = [&]() {

@@ -895,7 +895,7 @@ __host__ __device__ constexpr int newton_kernel_lds_doubles(int ncell, int NQ, i
   return ncell * NQ + newton_scratch_doubles(N1) + threads;
 }
 
-template <int DIM>
+template <int DIM, bool GEN = false>
 __device__ __forceinline__ void newton_step_dev(const AugShape& s, const double* cs, const double* __restrict__ A1,
                                                 double m, NewtonState* ns, fmg_report* rep, int newton_max,
                                                 double tol, double* sm);
@@ -989,7 +989,7 @@ __global__ void __launch_bounds__(ELEM || VAR ? kBlock : aug_threads<DIM>()) k_a
     setup_reduce<DIM>(s, ps, m, ns, cs, tmp);
   }
   cell_sums_from_partials<AC::NQ, sum_units<DIM>()>(pq, ncell, bpc, cs, tmp);
-  newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
+  newton_step_dev<DIM, VAR>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   if (FINISH) {
     // last pass of the launch sequence: this block completes the Newton solve
     // if it needs more passes, evaluating the fine quadrature by itself
@@ -1149,7 +1149,7 @@ __global__ void __launch_bounds__(kBlock) k_newton_finish(Grid g, AugShape s, co
     __syncthreads();
     if (ns->done) return;
     quad_cells_by_waves<DIM, KIND, ELEM, VAR>(g, s, ut, ns->ytry, slot->param, cs, slot);
-    newton_step_dev<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
+    newton_step_dev<DIM, VAR>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
   }
 }
 

@@ -195,7 +195,10 @@ static __global__ void __launch_bounds__(kInvertThreads) k_spd_invert(const doub
 }
 
 // ---------------------------------------------------------------------------
-// Multigrid operators with the stencil arrays (float64).
+// Multigrid operators with the stencil arrays (float64).  Each node reads its
+// own seven (3D) weights and those of its backward neighbours, three of which
+// lie in the previous plane: the blocks take rows in bands that march through
+// the planes (node_of_thread_banded), so that plane is still in the XCD's L2.
 // ---------------------------------------------------------------------------
 
 // (A x)_c and diag(A)_c at interior node c.
@@ -227,7 +230,7 @@ template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_apply_Aw(Grid g, const double* __restrict__ x, double* __restrict__ y,
                                                      const double* __restrict__ W, long long plane) {
   int i, j, l;
-  if (!node_of_thread<DIM>(g, i, j, l)) return;
+  if (!node_of_thread_banded<DIM>(g, i, j, l)) return;
   const int c = gidx<DIM>(g, i, j, l);
   double diag;
   y[c] = apply_Aw_at<DIM>(x, c, g, W, plane, diag);
@@ -239,7 +242,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_w(Grid g, const double* __res
                                                      const double* __restrict__ b, double* __restrict__ out,
                                                      const double* __restrict__ W, long long plane, double w) {
   int i, j, l;
-  if (!node_of_thread<DIM>(g, i, j, l)) return;
+  if (!node_of_thread_banded<DIM>(g, i, j, l)) return;
   const int c = gidx<DIM>(g, i, j, l);
   if (ZERO) {
     constexpr int NF = coef_fwd<DIM>();
@@ -260,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_w(Grid g, const double* __rest
                                                     const double* __restrict__ b, double* __restrict__ r,
                                                     const double* __restrict__ W, long long plane) {
   int i, j, l;
-  if (!node_of_thread<DIM>(g, i, j, l)) return;
+  if (!node_of_thread_banded<DIM>(g, i, j, l)) return;
   const int c = gidx<DIM>(g, i, j, l);
   double d;
   r[c] = b[c] - apply_Aw_at<DIM>(x, c, g, W, plane, d);

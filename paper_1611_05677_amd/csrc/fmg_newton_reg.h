@@ -26,6 +26,39 @@ __device__ __forceinline__ double stencil_shfl(double v, int A, int ax, int ay, 
   return node ? s1 * (2.0 * DIM * v - nb) : 0.0;
 }
 
+// A general A_1 (variable coefficient): on the Kuhn meshes row A couples only
+// nodes at offsets in {-1,0,1}^d, so the lane keeps those entries, a1q[q] at
+// box offset q = (dx+1) + 3 (dy+1) (+ 9 (dz+1)), zero outside the grid.
+template <int DIM> constexpr int box_size() { return DIM == 2 ? 9 : 27; }
+
+template <int DIM>
+__device__ __forceinline__ void box_row(const double* __restrict__ A1g, int N1, int A, int ax, int ay, int az,
+                                        int mm, bool node, double (&a1q)[box_size<DIM>()]) {
+#pragma unroll
+  for (int q = 0; q < box_size<DIM>(); ++q) {
+    const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = DIM == 3 ? q / 9 - 1 : 0;
+    const int bx = ax + dx, by = ay + dy, bz = az + dz;
+    const bool in = node && bx >= 1 && bx <= mm && by >= 1 && by <= mm && (DIM == 2 || (bz >= 1 && bz <= mm));
+    const int B = A + dx + mm * dy + mm * mm * dz;
+    a1q[q] = in ? A1g[(size_t)A * N1 + B] : 0.0;
+  }
+}
+
+// (A_1 v)_A from the lane's box row (lanes without a node return 0).
+template <int DIM>
+__device__ __forceinline__ double box_apply_shfl(double v, int A, int mm, const double (&a1q)[box_size<DIM>()]) {
+  const int lane = threadIdx.x;
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < box_size<DIM>(); ++q) {
+    const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = DIM == 3 ? q / 9 - 1 : 0;
+    const int B = A + dx + mm * dy + mm * mm * dz;
+    const double r = __shfl(v, (B >= 0 && B < 64) ? B : lane, 64);
+    s += a1q[q] * r;
+  }
+  return s;
+}
+
 // Gauss-Jordan elimination without pivoting of the symmetric positive definite
 // NY x NY system J x = b whose row `lane` is jr[] (full rows; lanes >= NY
 // hold zero rows) and whose right-hand side entry `lane` is v.  Steps
@@ -77,9 +110,11 @@ __host__ __device__ constexpr int pair_of(int a, int b) {
 }
 
 // Newton step (see newton_core) with the state in registers.  LDS: J ((NY + 1) rows of NY | 1).
-template <int DIM, int NY>
+// GEN: A_1 is the general matrix A1g (variable coefficient), not the stencil.
+template <int DIM, int NY, bool GEN = false>
 __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double* cs, double m, NewtonState* nsg,
-                                                fmg_report* rep, int newton_max, double tol, double* sm) {
+                                                fmg_report* rep, int newton_max, double tol, double* sm,
+                                                const double* __restrict__ A1g = nullptr) {
   if (threadIdx.x >= 64) return;
   using AC = Acc<DIM>;
   constexpr int N1 = NY - 1;
@@ -105,7 +140,9 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
   int ax, ay, az;
   coarse_coords<DIM>(nH, A, ax, ay, az);
   // ---- residual and the J column of u~ ----
-  const double Aw = stencil_shfl<DIM>(w, A, ax, ay, az, mm, node, s1);
+  double a1q[box_size<DIM>()];
+  if constexpr (GEN) box_row<DIM>(A1g, N1, A, ax, ay, az, mm, node, a1q);
+  const double Aw = GEN ? box_apply_shfl<DIM>(w, A, mm, a1q) : stencil_shfl<DIM>(w, A, ax, ay, az, mm, node, s1);
   double nh = 0.0, khu = 0.0;
   double st[DIM == 2 ? 9 : 27];   // m f' phi_A phi_B by offset B - A in {-1,0,1}^d
 #pragma unroll
@@ -189,7 +226,7 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
         if (bx < 1 || bx > mm || by < 1 || by > mm || (DIM == 3 && (bz < 1 || bz > mm))) continue;
         const int B = A + dx + mm * dy + mm * mm * dz;
         const int nz = (dx != 0) + (dy != 0) + (dz != 0);
-        const double a1 = nz == 0 ? 2.0 * DIM * s1 : (nz == 1 ? -s1 : 0.0);
+        const double a1 = GEN ? a1q[q] : (nz == 0 ? 2.0 * DIM * s1 : (nz == 1 ? -s1 : 0.0));
         J[A * JS + B] = a1 + m * st[q];
       }
       J[A * JS + N1] = jAu;
@@ -250,11 +287,12 @@ __device__ __forceinline__ void newton_core_reg(const AugShape& s, const double*
 
 // Algorithm 3.2, step 1 with the state in registers (see level1_newton_dev):
 // lane A owns U_A; N1 = 9 (2D) or 27 (3D), i.e. 4 coarse cells per side.
-template <int DIM, int KIND, int N1>
+// GEN: A_1 is the general matrix A1g and f is weighted by c(x) (slot->c).
+template <int DIM, int KIND, int N1, bool GEN = false>
 __device__ __forceinline__ void level1_newton_reg(const Grid& g1, double m1, const ProblemSlot* __restrict__ slot,
                                                   int nf1, int fs, double* __restrict__ x1,
                                                   fmg_report* __restrict__ rep, int newton_max, double tol,
-                                                  double* sm) {
+                                                  double* sm, const double* __restrict__ A1g = nullptr) {
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
   const bool node = lane < N1;
@@ -264,12 +302,30 @@ __device__ __forceinline__ void level1_newton_reg(const Grid& g1, double m1, con
   const int A = node ? lane : 0;
   int ax, ay, az;
   coarse_coords<DIM>(nH, A, ax, ay, az);
-  const double G = node ? m1 * slot->g[fine_load_index(nf1, fs, ax, ay, az)] : 0.0;
+  const long long fi = fine_load_index(nf1, fs, ax, ay, az);
+  const double G = node ? m1 * slot->g[fi] : 0.0;
+  double arow[GEN ? N1 : 1];        // row A of the general A_1 (GEN)
+  double cA = 1.0;                 // c(x_A) (GEN)
+  if constexpr (GEN) {
+#pragma unroll
+    for (int B = 0; B < N1; ++B) arow[B] = node ? A1g[(size_t)A * N1 + B] : 0.0;
+    if (slot->c && node) cA = slot->c[fi];
+  }
+  auto apply = [&](double V) {
+    if constexpr (GEN) {
+      double sum = 0.0;
+#pragma unroll
+      for (int B = 0; B < N1; ++B) sum += arow[B] * lane_value(V, B);
+      return node ? sum : 0.0;
+    } else {
+      return stencil_shfl<DIM>(V, A, ax, ay, az, mm, node, s1);
+    }
+  };
   auto energy = [&](double V, double& Eo, double& So) {
-    const double AV = stencil_shfl<DIM>(V, A, ax, ay, az, mm, node, s1);
+    const double AV = apply(V);
     double f, df, F;
     NL<KIND>::all(V, q, f, df, F);
-    double sums[3] = {node ? V * AV : 0.0, node ? F : 0.0, G * V};
+    double sums[3] = {node ? V * AV : 0.0, node ? (GEN ? cA * F : F) : 0.0, G * V};
     wave_sum_n<3>(sums);
     const double t1 = 0.5 * sums[0];
     const double t2 = m1 * sums[1];
@@ -283,13 +339,18 @@ __device__ __forceinline__ void level1_newton_reg(const Grid& g1, double m1, con
   for (it = 1; it <= newton_max; ++it) {
     double f, df, F;
     NL<KIND>::all(U, q, f, df, F);
-    const double R = node ? stencil_shfl<DIM>(U, A, ax, ay, az, mm, node, s1) + m1 * f - G : 0.0;
+    if (GEN) { f *= cA; df *= cA; }
+    const double R = node ? apply(U) + m1 * f - G : 0.0;
     double jr[N1];
 #pragma unroll
     for (int B = 0; B < N1; ++B) {
       const int bx = 1 + B % 3, by = 1 + (B / 3) % 3, bz = DIM == 3 ? 1 + B / 9 : 0;
       const int nz = abs(bx - ax) + abs(by - ay) + abs(bz - az);
-      jr[B] = !node ? 0.0 : (nz == 0 ? 2.0 * DIM * s1 + m1 * df : (nz == 1 ? -s1 : 0.0));
+      if constexpr (GEN) {
+        jr[B] = !node ? 0.0 : arow[B] + (nz == 0 ? m1 * df : 0.0);
+      } else {
+        jr[B] = !node ? 0.0 : (nz == 0 ? 2.0 * DIM * s1 + m1 * df : (nz == 1 ? -s1 : 0.0));
+      }
     }
     double piv = 1.0, v = node ? -R : 0.0;
     gj_elim_reg<N1>(jr, piv, v);
@@ -333,23 +394,31 @@ __device__ __forceinline__ void level1_dispatch(const Grid& g1, int N1, const do
                                                 const ProblemSlot* __restrict__ slot, int nf1, int fs,
                                                 double* __restrict__ x1, fmg_report* __restrict__ rep,
                                                 int newton_max, double tol, double* smem) {
-  // the register path assumes A = I (constant stencil, c = 1)
+  // A = I and c = 1: the stencil; otherwise the general A_1 (and c(x))
   const bool plain = slot->coef.w[1] == nullptr && slot->c == nullptr;
   if (DIM == 2 && N1 == 9 && plain)
     level1_newton_reg<DIM, KIND, 9>(g1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
   else if (DIM == 3 && N1 == 27 && plain)
     level1_newton_reg<DIM, KIND, 27>(g1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
+  else if (DIM == 2 && N1 == 9)
+    level1_newton_reg<DIM, KIND, 9, true>(g1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem, A1g);
+  else if (DIM == 3 && N1 == 27)
+    level1_newton_reg<DIM, KIND, 27, true>(g1, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem, A1g);
   else level1_newton_dev<DIM, KIND>(g1, N1, A1g, m1, slot, nf1, fs, x1, rep, newton_max, tol, smem);
   __syncthreads();
 }
 
-// Dispatch: register-resident step for the 4-cell coarse grids, LDS step otherwise.
-template <int DIM>
+// Dispatch: register-resident step for the 4-cell coarse grids, LDS step
+// otherwise.  GEN (the variable-coefficient kernels): the register step with
+// the general A_1.
+template <int DIM, bool GEN>
 __device__ __forceinline__ void newton_step_dev(const AugShape& s, const double* cs, const double* __restrict__ A1,
                                                 double m, NewtonState* ns, fmg_report* rep, int newton_max,
                                                 double tol, double* sm) {
-  if (DIM == 2 && s.N1 == 9 && !s.general) newton_core_reg<DIM, 10>(s, cs, m, ns, rep, newton_max, tol, sm);
-  else if (DIM == 3 && s.N1 == 27 && !s.general) newton_core_reg<DIM, 28>(s, cs, m, ns, rep, newton_max, tol, sm);
+  if (DIM == 2 && s.N1 == 9 && (GEN || !s.general))
+    newton_core_reg<DIM, 10, GEN>(s, cs, m, ns, rep, newton_max, tol, sm, A1);
+  else if (DIM == 3 && s.N1 == 27 && (GEN || !s.general))
+    newton_core_reg<DIM, 28, GEN>(s, cs, m, ns, rep, newton_max, tol, sm, A1);
   else newton_core<DIM>(s, cs, A1, m, ns, rep, newton_max, tol, sm);
 }
 

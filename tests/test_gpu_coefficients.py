@@ -253,6 +253,18 @@ def test_batch_with_weights_matches_single_solves():
         H.close()
 
 
+def test_level_kernel_timer_times_the_weighted_sweep():
+    P = W.random_coefficient("tm", 3, 4, 3, W.F_CUBIC, [31])
+    H = gpu_hierarchy(P)
+    ms, nb = B.time_level_kernel(H, "smooth_var_f64", H.levels, 5)
+    assert ms > 0 and nb == 8.0 * (3 + 7) * 31 ** 3
+    ms, nb = B.time_level_kernel(H, "resid_var_f64", H.levels, 5)
+    assert ms > 0 and nb == 8.0 * (3 + 7) * 31 ** 3
+    with pytest.raises(B.FMGError):
+        B.time_level_kernel(H, "pre_sweep_pair_3d_f64", H.levels, 5)
+    H.close()
+
+
 def test_error_paths():
     P = W.random_coefficient("err", 2, 4, 3, W.F_CUBIC, [30])
     H = B.Hierarchy(2, 4, 3, B.default_options(2, coefficients=B.FMG_COEF_VARIABLE), device=DEV)
