@@ -650,30 +650,30 @@ VAR_ROOF_KERNEL = ("smooth_var_f64", "fmg_kernels_coef.h")
 
 def variable_cpu_baseline(W):
     """The variable-coefficient oracle O2 on the host, single thread, on a
-    bounded sample: the same manufactured problem two levels coarser (64^3).
+    bounded sample: the same manufactured problem one level coarser (128^3).
     The Galerkin hierarchy (the analogue of fmg_create_hierarchy plus
-    fmg_set_coefficients) is built untimed; the median of ten solves is
-    reported."""
+    fmg_set_coefficients; about a minute and 14 GB) is built untimed; the
+    median of three solves is reported."""
     from threadpoolctl import threadpool_limits
 
     from oracle.nonlinear import Nonlinearity
     from oracle.o2 import Hierarchy as O2H
     from oracle.o2 import fmg as o2_fmg
-    S = W.variable_coefficient("cube64_var", 3, 4, 4, W.F_U_PLUS_SIN)
+    S = W.variable_coefficient("cube128_var", 3, 4, 5, W.F_U_PLUS_SIN)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         H = O2H(S.dim, S.coarse_cells, S.refinements, coef=S.coef_cells)
         build_s = time.perf_counter() - t0
         nl = Nonlinearity(S.f_kind, S.f_param)
         times = []
-        for _ in range(10):
+        for _ in range(3):
             t0 = time.perf_counter()
             o2_fmg(H, S.g_nodes, nl, f_weight=S.f_weight_nodes)
             times.append(time.perf_counter() - t0)
         o2_s = float(np.median(times))
     return {"value": S.interior_dofs / o2_s, "unit": "DOF/s", "cores": 1, "kind": "oracle",
             "sample": f"O2 with the coefficients (scipy CSR, the oracle's replica of the FMG scheme): {S.name} "
-                      f"({S.interior_dofs} DOFs, the benchmark's problem two levels coarser), median of 10 "
+                      f"({S.interior_dofs} DOFs, the benchmark's problem one level coarser), median of 3 "
                       f"solves {o2_s:.3f} s; Galerkin hierarchy {build_s:.1f} s not timed",
             "o2_solve_s": o2_s, "o2_dofs": S.interior_dofs, "hierarchy_s": build_s, "cpu_model": _cpu_model(),
             "threads_used": "1 (scipy sparse kernels are single-threaded; BLAS pools limited to 1)"}
