@@ -131,6 +131,62 @@ def assemble_interior(mesh: Mesh, coef=None):
     return A, mass[I]
 
 
+def local_rows(dim: int, n: int, nodes_ijk: np.ndarray, coef=None):
+    """Rows of the full stiffness matrix and lumped masses at a few nodes of
+    the (0,1)^dim mesh with n cells per side, without building the mesh: the
+    simplices around each node are generated from their definition (cells
+    whose closure holds the node, split along every axis order into the chain
+    of vertices corner, corner + e_a0, ..), and assembled with the same local
+    formula as assemble_full.  Returns, per node, (column node ids x fastest,
+    values) and the masses.  For checks at sizes whose full assembly does not
+    fit in memory."""
+    import itertools
+    h = 1.0 / n
+    nodes_ijk = np.asarray(nodes_ijk, dtype=np.int64)
+    At = None if coef is None else coefficient_tensors(dim, coef)
+    cols_out, vals_out, mass_out = [], [], []
+    for p in nodes_ijk:
+        simp = []
+        for o in itertools.product((0, 1), repeat=dim):
+            corner = p - np.array(o)
+            if np.any(corner < 0) or np.any(corner >= n):
+                continue
+            for perm in itertools.permutations(range(dim)):
+                v = [corner.copy()]
+                for a in perm:
+                    w = v[-1].copy()
+                    w[a] += 1
+                    v.append(w)
+                simp.append((np.stack(v), corner))
+        row = {}
+        mass = 0.0
+        for V, corner in simp:
+            if not any(np.array_equal(x, p) for x in V):
+                continue
+            X = V.astype(np.float64) * h
+            grads, vol, _ = simplex_geometry(X[None])
+            G = grads[0]
+            if At is None:
+                K = vol[0] * G @ G.T
+            else:
+                cell = 0
+                for a in range(dim - 1, -1, -1):
+                    cell = cell * n + int(corner[a])
+                K = vol[0] * G @ At[cell] @ G.T
+            ip = next(k for k in range(dim + 1) if np.array_equal(V[k], p))
+            for k in range(dim + 1):
+                nid = 0
+                for a in range(dim - 1, -1, -1):
+                    nid = nid * (n + 1) + int(V[k][a])
+                row[nid] = row.get(nid, 0.0) + K[ip, k]
+            mass += vol[0] / (dim + 1)
+        ids = np.array(sorted(row), dtype=np.int64)
+        cols_out.append(ids)
+        vals_out.append(np.array([row[i] for i in ids]))
+        mass_out.append(mass)
+    return cols_out, vals_out, np.array(mass_out)
+
+
 def locate_in_coarse(coarse: Mesh, points: np.ndarray, tol: float = 1e-12):
     """Point location: for each point, a coarse simplex containing it and the
     point's barycentric coordinates in that simplex.

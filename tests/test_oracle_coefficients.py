@@ -36,7 +36,7 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from oracle.fem import assemble_full, assemble_interior, coefficient_tensors
+from oracle.fem import assemble_full, assemble_interior, coefficient_tensors, local_rows
 from oracle.mesh import unit_mesh
 from oracle.nonlinear import Nonlinearity
 from oracle.norms import nodal_l2
@@ -329,3 +329,21 @@ def test_element_rule_with_weight_is_rejected():
     P = W.variable_coefficient("vc", 2, 4, 2, W.F_CUBIC)
     with pytest.raises(ValueError):
         solve_fine(2, P.n, P.g_nodes, Nonlinearity(P.f_kind), quadrature="element", f_weight=P.f_weight_nodes)
+
+
+@pytest.mark.parametrize("d,n,with_coef", [(2, 6, True), (3, 4, True), (3, 3, False)])
+def test_local_rows_equal_the_assembled_rows(d, n, with_coef):
+    """local_rows (the rows of a few nodes, for sizes whose whole assembly does
+    not fit in memory) against the element-by-element assembly, boundary and
+    corner nodes included."""
+    mesh = unit_mesh(d, n)
+    comps = W.random_coefficient("r", d, n, 0, W.F_CUBIC, [18]).coef_cells if with_coef else None
+    K, m = assemble_full(mesh, comps)
+    pick = np.concatenate([np.random.default_rng(19).choice(mesh.coords.shape[0], 12, replace=False), [0, mesh.coords.shape[0] - 1]])
+    cols, vals, mass = local_rows(d, n, mesh.ijk[pick], comps)
+    for k, i in enumerate(pick):
+        row = K.getrow(i).toarray().ravel()
+        got = np.zeros_like(row)
+        got[cols[k]] = vals[k]
+        assert np.max(np.abs(got - row)) < 1e-13 * max(1.0, np.max(np.abs(row)))
+    assert np.max(np.abs(mass - m[pick])) < 1e-15
