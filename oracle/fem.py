@@ -131,6 +131,36 @@ def assemble_interior(mesh: Mesh, coef=None):
     return A, mass[I]
 
 
+def simplices_around(dim: int, n: int, p: np.ndarray):
+    """The simplices of the (0,1)^dim mesh with n cells per side that hold
+    grid node p, generated from their definition: every cell whose closure
+    holds p, split along every axis order into the vertex chain corner,
+    corner + e_a0, ...  Yields (vertices (d+1, d) grid indices, cell corner)."""
+    import itertools
+    p = np.asarray(p, dtype=np.int64)
+    for o in itertools.product((0, 1), repeat=dim):
+        corner = p - np.array(o)
+        if np.any(corner < 0) or np.any(corner >= n):
+            continue
+        for perm in itertools.permutations(range(dim)):
+            v = [corner.copy()]
+            for a in perm:
+                w = v[-1].copy()
+                w[a] += 1
+                v.append(w)
+            V = np.stack(v)
+            if any(np.array_equal(x, p) for x in V):
+                yield V, corner
+
+
+def grid_node_id(n: int, ijk) -> int:
+    """Node id (x fastest) of grid indices ijk on a mesh with n cells per side."""
+    nid = 0
+    for a in range(len(ijk) - 1, -1, -1):
+        nid = nid * (n + 1) + int(ijk[a])
+    return nid
+
+
 def local_rows(dim: int, n: int, nodes_ijk: np.ndarray, coef=None):
     """Rows of the full stiffness matrix and lumped masses at a few nodes of
     the (0,1)^dim mesh with n cells per side, without building the mesh: the
@@ -140,44 +170,24 @@ def local_rows(dim: int, n: int, nodes_ijk: np.ndarray, coef=None):
     formula as assemble_full.  Returns, per node, (column node ids x fastest,
     values) and the masses.  For checks at sizes whose full assembly does not
     fit in memory."""
-    import itertools
     h = 1.0 / n
     nodes_ijk = np.asarray(nodes_ijk, dtype=np.int64)
     At = None if coef is None else coefficient_tensors(dim, coef)
     cols_out, vals_out, mass_out = [], [], []
     for p in nodes_ijk:
-        simp = []
-        for o in itertools.product((0, 1), repeat=dim):
-            corner = p - np.array(o)
-            if np.any(corner < 0) or np.any(corner >= n):
-                continue
-            for perm in itertools.permutations(range(dim)):
-                v = [corner.copy()]
-                for a in perm:
-                    w = v[-1].copy()
-                    w[a] += 1
-                    v.append(w)
-                simp.append((np.stack(v), corner))
         row = {}
         mass = 0.0
-        for V, corner in simp:
-            if not any(np.array_equal(x, p) for x in V):
-                continue
+        for V, corner in simplices_around(dim, n, p):
             X = V.astype(np.float64) * h
             grads, vol, _ = simplex_geometry(X[None])
             G = grads[0]
             if At is None:
                 K = vol[0] * G @ G.T
             else:
-                cell = 0
-                for a in range(dim - 1, -1, -1):
-                    cell = cell * n + int(corner[a])
-                K = vol[0] * G @ At[cell] @ G.T
+                K = vol[0] * G @ At[_cell_index(n, corner)] @ G.T
             ip = next(k for k in range(dim + 1) if np.array_equal(V[k], p))
             for k in range(dim + 1):
-                nid = 0
-                for a in range(dim - 1, -1, -1):
-                    nid = nid * (n + 1) + int(V[k][a])
+                nid = grid_node_id(n, V[k])
                 row[nid] = row.get(nid, 0.0) + K[ip, k]
             mass += vol[0] / (dim + 1)
         ids = np.array(sorted(row), dtype=np.int64)
@@ -185,6 +195,14 @@ def local_rows(dim: int, n: int, nodes_ijk: np.ndarray, coef=None):
         vals_out.append(np.array([row[i] for i in ids]))
         mass_out.append(mass)
     return cols_out, vals_out, np.array(mass_out)
+
+
+def _cell_index(n: int, corner) -> int:
+    """Cell id (x fastest) of the cell with lower corner `corner`."""
+    cell = 0
+    for a in range(len(corner) - 1, -1, -1):
+        cell = cell * n + int(corner[a])
+    return cell
 
 
 def locate_in_coarse(coarse: Mesh, points: np.ndarray, tol: float = 1e-12):

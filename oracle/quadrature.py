@@ -28,7 +28,7 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
-from .fem import ELEMENT_CHUNK, simplex_geometry
+from .fem import ELEMENT_CHUNK, grid_node_id, simplex_geometry, simplices_around
 from .mesh import Mesh
 from .nonlinear import Nonlinearity
 
@@ -105,3 +105,26 @@ def full_vector(mesh: Mesh, U_interior: np.ndarray) -> np.ndarray:
     out = np.zeros(mesh.coords.shape[0])
     out[mesh.interior] = U_interior
     return out
+
+
+def local_element_terms(dim: int, n: int, nodes_ijk, u_nodes: np.ndarray, g_nodes: np.ndarray, nl: Nonlinearity):
+    """(f(u_h), phi_i) and (g_I, phi_i) at a few grid nodes i of the (0,1)^dim
+    mesh with n cells per side, by the element rule on the simplices around
+    each node only (fem.simplices_around): the same per-simplex formula as
+    ElementQuadrature, for sizes whose whole mesh does not fit in memory."""
+    lam, omega = simplex_rule(dim)
+    h = 1.0 / n
+    N, G = [], []
+    for p in np.asarray(nodes_ijk, dtype=np.int64):
+        nv = gv = 0.0
+        for V, _ in simplices_around(dim, n, p):
+            _, vol, _ = simplex_geometry((V.astype(np.float64) * h)[None])
+            ids = [grid_node_id(n, v) for v in V]
+            ip = next(k for k in range(dim + 1) if np.array_equal(V[k], p))
+            uq = lam @ np.asarray(u_nodes)[ids]
+            gq = lam @ np.asarray(g_nodes)[ids]
+            nv += vol[0] * np.sum(omega * nl.f(uq) * lam[:, ip])
+            gv += vol[0] * np.sum(omega * gq * lam[:, ip])
+        N.append(nv)
+        G.append(gv)
+    return np.array(N), np.array(G)

@@ -31,7 +31,7 @@ from oracle.nonlinear import Nonlinearity
 from oracle.norms import nodal_l2
 from oracle.o1 import solve_fine
 from oracle.o2 import Hierarchy, Options, augmented_solve, correction_step, fmg
-from oracle.quadrature import ElementQuadrature, full_vector, simplex_rule
+from oracle.quadrature import ElementQuadrature, full_vector, local_element_terms, simplex_rule
 from paper_1611_05677_amd import workloads as W
 
 
@@ -198,3 +198,20 @@ def test_o2_element_meets_the_theorem_3_2_gate(dim, L):
     alg = nodal_l2(o1.m, res.U - o1.U)
     assert alg <= 0.5 * disc, (alg, disc)
     assert nodal_l2(o1.m, res.U - P.u_exact_nodes[I]) <= 1.1 * disc
+
+
+@pytest.mark.parametrize("d,n", [(2, 6), (3, 4)])
+def test_local_element_terms_equal_the_whole_mesh_quadrature(d, n):
+    """local_element_terms (the element rule at a few nodes, for sizes whose
+    whole mesh does not fit in memory) against ElementQuadrature, boundary
+    nodes included."""
+    mesh = unit_mesh(d, n)
+    Qd = ElementQuadrature(mesh)
+    nl = Nonlinearity(W.F_U_PLUS_SIN)
+    rng = np.random.default_rng(6)
+    u = full_vector(mesh, rng.standard_normal(mesh.interior.size))
+    g = rng.standard_normal(mesh.coords.shape[0])
+    pick = np.concatenate([rng.choice(mesh.coords.shape[0], 12, replace=False), [0]])
+    N, G = local_element_terms(d, n, mesh.ijk[pick], u, g, nl)
+    assert np.max(np.abs(N - Qd.nonlinear(u, nl)[pick])) < 1e-15 * 100
+    assert np.max(np.abs(G - Qd.load(g)[pick])) < 1e-15 * 100
