@@ -141,10 +141,16 @@ __global__ void __launch_bounds__(kP3Threads) k_sweep_pair3(Pair3Args A) {
   const int Z0 = 1 + zc * A.zc_planes, Zend = min(Z0 + A.zc_planes, n);   // owned planes [Z0, Zend)
   const int zs = Z0 - kP3Halo, steps = Zend - Z0 + 2 * kP3Halo;         // planes Z0-2 .. Zend+1
   auto plane = [&](int z) { return (z < 0 ? 0 : (z > n ? n : z)); };
-  // ring of two plane slots per row: x0 (with the coarse pair), b, and u (kP3ProlongAdd)
+  // ring of two plane slots per row: x0, b, one coarse value, and u (kP3ProlongAdd).
+  // Coarse values: fine plane z = 2 p_z + e_z takes the mean of coarse node c0
+  // on coarse plane p_z and c1 on plane p_z + e_z.  An even plane's c1 value is
+  // the previous (odd) plane's, and an odd plane's c0 value the previous
+  // (even) plane's, so each plane loads one coarse value (even: c0 on z/2;
+  // odd: c1 on (z+1)/2) and takes the other from the plane before (pc0, pc1).
   TX qx[2][RW], qb[2][RW];
-  T qc0[2][RW], qc1[2][RW];
+  T qc[2][RW];
   double qu[2][RW];
+  auto cplane = [&](int zc) { return zc < 0 ? 0 : (zc > cg.n ? cg.n : zc); };
   auto fetch = [&](int d, int zl) {
     const int z = plane(zl);
 #pragma unroll
@@ -152,14 +158,24 @@ __global__ void __launch_bounds__(kP3Threads) k_sweep_pair3(Pair3Args A) {
       const size_t o = (size_t)z * g.pz + off[k];
       if (MODE != kP3Zero) qx[d][k] = x[o];
       qb[d][k] = b[o];
-      if (PROLONG) {
-        const int zc0 = z >> 1, zc1 = min((z >> 1) + (z & 1), cg.n);
-        qc0[d][k] = xc[(size_t)zc0 * cg.pz + c0[k]];
-        qc1[d][k] = xc[(size_t)zc1 * cg.pz + c1[k]];
+      if (PROLONG) {   // integer arithmetic, not a select between c0 and c1
+        const int odd = zl & 1;
+        qc[d][k] = xc[(size_t)cplane((zl + odd) >> 1) * cg.pz + c0[k] + odd * (c1[k] - c0[k])];
       }
       if (MODE == kP3ProlongAdd) qu[d][k] = A.u64[o];
     }
   };
+  T pc0[RW], pc1[RW];                 // the previous plane's coarse pair
+#pragma unroll
+  for (int k = 0; k < RW; ++k) {
+    pc0[k] = pc1[k] = T(0);
+    if (PROLONG) {   // what the first plane takes from the plane before it
+      const int odd = zs & 1;
+      const T v = xc[(size_t)cplane((zs - odd) >> 1) * cg.pz + c1[k] + odd * (c0[k] - c1[k])];
+      pc0[k] = odd ? v : T(0);
+      pc1[k] = odd ? T(0) : v;
+    }
+  }
   fetch(0, zs);
   fetch(1, zs + 1);
   // windows per row: x0 planes z-2, z-1; b planes z-1, z-2; s1 planes z-3, z-2;
@@ -189,10 +205,16 @@ __global__ void __launch_bounds__(kP3Threads) k_sweep_pair3(Pair3Args A) {
         xn[k] = (MODE != kP3Zero && ok) ? qx[d][k] : TX(0);
         bn[k] = ok ? qb[d][k] : TX(0);
         un[k] = (MODE == kP3ProlongAdd && ok) ? qu[d][k] : 0.0;
-        if (PROLONG && ok && in_xy[k] && z_in) {
-          T v = qc0[d][k];
-          if (cs[k] | (zl & 1)) v = T(0.5) * (v + qc1[d][k]);
-          xn[k] = xn[k] + v;
+        if (PROLONG) {
+          const T v0 = (zl & 1) ? pc0[k] : qc[d][k];
+          const T v1 = (zl & 1) ? qc[d][k] : pc1[k];
+          pc0[k] = v0;
+          pc1[k] = v1;
+          if (ok && in_xy[k] && z_in) {
+            T v = v0;
+            if (cs[k] | (zl & 1)) v = T(0.5) * (v + v1);
+            xn[k] = xn[k] + v;
+          }
         }
       }
       fetch(d, zl + 2);   // refill the slot (clamped past the end; unused)
