@@ -205,22 +205,35 @@ __device__ __forceinline__ void post2s_wave(const Grid& cg, const Grid& f, const
   const int ylo = Y0 - kPostHalo, yhi = Yend + kPostHalo - 1;
   const int ystart = UP ? ylo : yhi;
   const int steps = yhi - ylo + 1;
-  // queue entries: x, b and the two coarse values of row y; groups of rows as
-  // in the pre-smoothing kernel (next group's loads issued at group start)
-  struct Q4 { T x[kPostQueue], b[kPostQueue], c0[kPostQueue], c1[kPostQueue]; double u[kPostQueue]; };
-  // (coarse reads clamped into the coarse grid: ci + si <= n/2 for every column)
+  // queue entries: x, b, one coarse value and (ADDU) u of row y; groups of
+  // rows as in the pre-smoothing kernel (next group's loads issued at group
+  // start).  Row y = 2 c_j + s_j takes the mean of coarse nodes c0 = (ci, y >> 1)
+  // and c1 = (ci + si, (y + s_j) >> 1); consecutive rows share one of them
+  // (marching up: an even row's c1 is the odd row's before it, an odd row's
+  // c0 the even row's; marching down the other way round), so each row loads
+  // one coarse value (w1: its c1) and takes the other from the row before.
+  struct Q4 { T x[kPostQueue], b[kPostQueue], c[kPostQueue]; double u[kPostQueue]; };
+  const int ci1 = min(ci + si, cg.n);   // (coarse rows and columns clamped into the coarse grid)
+  auto crow = [&](int r) { return r < 0 ? 0 : (r > cg.n ? cg.n : r); };
+  auto loads_c1 = [&](int y) { return UP ? (y & 1) : 1 - (y & 1); };
   auto fetch = [&](Q4& qq, int q, int y) {
     const int yc = clamp_row(y, n);
     qq.x[q] = x[yc * f.px + Xc];
     qq.b[q] = b[yc * f.px + Xc];
-    const int cj = yc >> 1, sj = yc & 1;
-    qq.c0[q] = xc[cj * cg.px + ci];
-    qq.c1[q] = xc[min(cj + sj, cg.n) * cg.px + min(ci + si, cg.n)];
+    const int odd = y & 1, w1 = loads_c1(y);   // integer arithmetic, not a select between c0 and c1
+    qq.c[q] = xc[crow((y + w1 * odd) >> 1) * cg.px + ci + w1 * (ci1 - ci)];
     if (ADDU) qq.u[q] = u64[yc * f.px + Xc];
   };
   Q4 cur;
 #pragma unroll
   for (int q = 0; q < kPostQueue; ++q) fetch(cur, q, ystart + D * q);
+  T pc0 = T(0), pc1 = T(0);             // the previous row's coarse pair
+  {   // what the first row takes from the row before it
+    const int odd = ystart & 1, w1 = loads_c1(ystart);
+    const T v = xc[crow((ystart + (1 - w1) * odd) >> 1) * cg.px + ci + (1 - w1) * (ci1 - ci)];
+    pc0 = w1 ? v : T(0);
+    pc1 = w1 ? T(0) : v;
+  }
   // windows: corrected x rows y-2D, y-D; b rows y-D, y-2D; sweep-1 rows y-3D, y-2D
   T xa = 0, xb = 0, b1 = 0, b2 = 0, s1a = 0, s1b = 0;
   double ua = 0.0, ub = 0.0;      // ADDU: u rows y-2D, y-D
@@ -233,8 +246,13 @@ __device__ __forceinline__ void post2s_wave(const Grid& cg, const Grid& f, const
       const int i = i0 + q;
       const int y = ystart + D * i;
       const bool in0 = col_in && y >= 1 && y <= n - 1;
-      T v = cur.c0[q];
-      if (si | (y & 1)) v = T(0.5) * (v + cur.c1[q]);
+      const int w1 = loads_c1(y);
+      const T v0 = w1 ? pc0 : cur.c[q];
+      const T v1 = w1 ? cur.c[q] : pc1;
+      pc0 = v0;
+      pc1 = v1;
+      T v = v0;
+      if (si | (y & 1)) v = T(0.5) * (v + v1);
       const T xr = stream_mask(cur.x[q], col_ok, y, n);
       const T xcor = in0 ? xr + v : xr;
       const T b0 = stream_mask(cur.b[q], col_ok, y, n);
