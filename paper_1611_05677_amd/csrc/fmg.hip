@@ -22,6 +22,7 @@
 #include "fmg_kernels_stream2d.h"
 #include "fmg_kernels_stream3d.h"
 #include "fmg_kernels_pair3d.h"
+#include "fmg_kernels_restrict3d.h"
 #include "fmg_launch.h"
 
 using namespace fmg;
@@ -460,6 +461,23 @@ void launch_pair3_kernel(const Pair3Args& a, hipStream_t st) {
   k_sweep_pair3<T, MODE><<<pair3_blocks(sh), kP3Threads, 0, st>>>(a);
 }
 
+// bc = P^T (b - A x) from level f to level cg: in 3D on levels with at least
+// kR3MinN cells per side the plane-marching kernel, else (and in 2D) one
+// thread per coarse node.  Both give the same bits.  Measured at 128^3 and
+// 64^3: the plane-marching kernel has too few tiles there (15 against 13 us,
+// 13 against 3.6 us); at 256^3 it takes 69 against 89 us.
+constexpr int kR3MinN = 256;
+
+template <int DIM, typename T>
+void launch_resid_restrict(const Grid& f, const Grid& cg, const T* x, const T* b, T* bc, T scale, hipStream_t st) {
+  if (DIM == 3 && f.n >= kR3MinN) {
+    const Restrict3Shape sh = restrict3_shape(cg.n);
+    k_resid_restrict3m<T><<<restrict3_blocks(sh), kR3Threads, 0, st>>>(f, cg, x, b, bc, scale, sh);
+  } else {
+    k_resid_restrict<DIM, T><<<grid_of(cg, DIM), kBlock, 0, st>>>(f, cg, x, b, bc, scale);
+  }
+}
+
 template <typename T>
 double launch_pre3(const fmg_hierarchy* h, int k, const T* x, const T* b, T* t, bool zero_init, hipStream_t st) {
   const LevelInfo& L = h->plan.lev[k];
@@ -630,8 +648,7 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
     const LevelInfo& C = p.lev[k - 1];
     const long long Nc = interior(C.g, DIM);
     FMG_LAUNCH(h, st, KC_RESTRICT64 + kc, k, N, s * (2 * N + Nc),
-               k_resid_restrict<DIM, T><<<grid_of(C.g, DIM), kBlock, 0, st>>>(L.g, C.g, x, b, Sel<T>::b(h, k - 1),
-                                                                             scale));
+               (launch_resid_restrict<DIM, T>(L.g, C.g, x, b, Sel<T>::b(h, k - 1), scale, st)));
     vcycle<DIM, T>(h, R, k - 1, true, st);
     launch_post3<T>(h, k, x, Sel<T>::x(R, k - 1), b, t, st);
     std::swap(x, t);
@@ -651,8 +668,7 @@ void vcycle(const fmg_hierarchy* h, Roles& R, int k, bool zero_init, hipStream_t
   const LevelInfo& C = p.lev[k - 1];
   const long long Nc = interior(C.g, DIM);
   FMG_LAUNCH(h, st, KC_RESTRICT64 + kc, k, N, s * (2 * N + Nc),
-             k_resid_restrict<DIM, T><<<grid_of(C.g, DIM), kBlock, 0, st>>>(L.g, C.g, x, b, Sel<T>::b(h, k - 1),
-                                                                           scale));
+             (launch_resid_restrict<DIM, T>(L.g, C.g, x, b, Sel<T>::b(h, k - 1), scale, st)));
   vcycle<DIM, T>(h, R, k - 1, true, st);
   FMG_LAUNCH(h, st, KC_PROLONG64_ADD + kc, k, N, s * (2 * N + Nc),
              k_prolong<DIM, T, true><<<grid, kBlock, 0, st>>>(C.g, L.g, Sel<T>::x(R, k - 1), x));
@@ -710,9 +726,8 @@ bool mixed_cycle_fused(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, 
     }
     std::swap(R.xs[k], R.ts[k]);
     FMG_LAUNCH(h, st, KC_RESTRICT32, k, N, 4.0 * (2 * N + Nc),
-               k_resid_restrict<3, float><<<grid_of(C.g, 3), kBlock, 0, st>>>(L.g, C.g, R.xs[k], r32,
-                                                                            h->at<float>(p.off_bs[k - 1]),
-                                                                            (float)L.scale));
+               (launch_resid_restrict<3, float>(L.g, C.g, R.xs[k], r32, h->at<float>(p.off_bs[k - 1]),
+                                                (float)L.scale, st)));
     vcycle<DIM, float>(h, R, k - 1, true, st);
     if (last) {
       Pair3Args q = pair3_args(h, k, h->ro.post);
@@ -2081,9 +2096,9 @@ int level_op_impl(fmg_hierarchy* h, int op, int k, int prec, const double* in0, 
       double* bc = h->at<double>(p.off_b[k - 1]);
       float* bcs = prec == FMG_MIXED ? h->at<float>(p.off_bs[k - 1]) : nullptr;
       if (prec == FMG_FP64)
-        k_resid_restrict<DIM, double><<<grid_of(C.g, DIM), kBlock, 0, s>>>(L.g, C.g, x, b, bc, L.scale);
+        launch_resid_restrict<DIM, double>(L.g, C.g, x, b, bc, L.scale, s);
       else
-        k_resid_restrict<DIM, float><<<grid_of(C.g, DIM), kBlock, 0, s>>>(L.g, C.g, xs, bs, bcs, (float)L.scale);
+        launch_resid_restrict<DIM, float>(L.g, C.g, xs, bs, bcs, (float)L.scale, s);
       outp(bc, bcs, C.g);
       break;
     }
@@ -2160,7 +2175,7 @@ int time_launch(fmg_hierarchy* h, int base, int k, hipStream_t st, double& bytes
     }
     case KC_RESTRICT64:
       bytes = s * (2 * N + Nc);
-      k_resid_restrict<DIM, T><<<grid_of(C.g, DIM), kBlock, 0, st>>>(L.g, C.g, x, b, Sel<T>::b(h, k - 1), scale);
+      launch_resid_restrict<DIM, T>(L.g, C.g, x, b, Sel<T>::b(h, k - 1), scale, st);
       return FMG_OK;
     case KC_PROLONG64_ADD:
       bytes = s * (2 * N + Nc);

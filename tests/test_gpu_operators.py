@@ -96,6 +96,64 @@ def test_residual_restriction_is_Pt(dim, nH, L, prec):
         assert err < 4 * TOL[prec], (k, err)
 
 
+def _restriction_weights():
+    """P^T stencil of an interior coarse node: the oracle's prolongation on
+    the 8^3 / 4^3 pair, column of the coarse node (2, 2, 2), as (fine offset,
+    weight) pairs (the stencil is the same at every interior coarse node)."""
+    coarse, fine = unit_mesh(3, 4), unit_mesh(3, 8)
+    P = prolongation(coarse, fine).tocsc()
+    col = int(np.nonzero(coarse.interior == 2 + 5 * (2 + 5 * 2))[0][0])
+    rows = P.indices[P.indptr[col]:P.indptr[col + 1]]
+    vals = P.data[P.indptr[col]:P.indptr[col + 1]]
+    return [(fine.ijk[fine.interior[r]] - 4, v) for r, v in zip(rows, vals)]
+
+
+@pytest.mark.parametrize("prec", [B.FMG_FP64, B.FMG_MIXED])
+def test_residual_restriction_full_size_sampled(prec):
+    """3D 384^3 (3 coarse cells, 7 refinements), the size class of the
+    plane-marching residual + restriction, with 191 interior coarse nodes per
+    axis that fill none of its 30-column strips, 14-row chunks or 39-plane
+    chunks evenly: P^T (b - A x) at sampled coarse nodes (the strip, chunk and domain
+    edges among them) against the oracle's stiffness rows at the 15 fine nodes
+    under each (assembled from the simplices around each node) and its
+    prolongation weights."""
+    from oracle.fem import local_rows
+    nH, L = 3, 7
+    n = nH * 2 ** L
+    nc = n // 2
+    H = hier(3, nH, L)
+    k = L + 1
+    rng = np.random.default_rng(80 + prec)
+    bnd = np.zeros((n + 1,) * 3, dtype=bool)
+    bnd[[0, -1]] = bnd[:, [0, -1]] = bnd[:, :, [0, -1]] = True
+    bnd = bnd.ravel()
+    x = rng.standard_normal((n + 1) ** 3)
+    b = rng.standard_normal((n + 1) ** 3)
+    x[bnd] = 0.0
+    b[bnd] = 0.0
+    got = H.level_op(B.FMG_OP_RESTRICT, k, to_dev(x), to_dev(b), precision=prec).cpu().numpy()
+    assert np.all(got.reshape((nc + 1,) * 3)[[0, -1]] == 0.0)
+    edges = [1, 2, 14, 15, 29, 30, 31, 39, 40, 60, 61, 78, 79, 181, 182, 190, 191]
+    pick = np.random.default_rng(3).integers(1, nc, size=(40, 3))
+    m = len(edges)
+    pick = np.concatenate([pick, np.array([(e, edges[(3 * i) % m], edges[(5 * i + 2) % m])
+                                           for i, e in enumerate(edges)])])
+    W = _restriction_weights()
+    idx = lambda q: int(q[0] + (n + 1) * (q[1] + (n + 1) * q[2]))
+    expect, gotv = [], []
+    for c in pick:
+        total = 0.0
+        for off, w in W:
+            q = 2 * c + off
+            cols, vals, _ = local_rows(3, n, q[None])
+            total += w * (b[idx(q)] - vals[0] @ x[cols[0]])
+        expect.append(total)
+        gotv.append(got[int(c[0] + (nc + 1) * (c[1] + (nc + 1) * c[2]))])
+    expect, gotv = np.array(expect), np.array(gotv)
+    err = np.max(np.abs(gotv - expect)) / np.max(np.abs(expect))
+    assert err < 4 * TOL[prec], err
+
+
 @pytest.mark.parametrize("dim,nH,L", CASES)
 @pytest.mark.parametrize("prec", [B.FMG_FP64, B.FMG_MIXED])
 def test_prolongation_is_natural_inclusion(dim, nH, L, prec):
