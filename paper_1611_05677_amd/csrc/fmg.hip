@@ -871,9 +871,35 @@ void aug_solve_var(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bool
                k_aug_update<DIM><<<grid_of(L.g, DIM), kBlock, 0, st>>>(L.g, L.aug, h->ns(), R.x[k]));
 }
 
+// The first float64 V-cycle of level k's first correction step on a 3D
+// sweep-pair level whose transition wrote only b_k: the pre-smoothing pair
+// starts from x0 = P u_{k-1} (the previous level's result, up to date), formed
+// as the pair's planes arrive.  The rest is the cycle of vcycle's sweep-pair
+// branch.
+inline void vcycle_from_prolongation3(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st) {
+  const Plan& p = h->plan;
+  const LevelInfo& L = p.lev[k];
+  const LevelInfo& C = p.lev[k - 1];
+  const long long N = interior(L.g, 3), Nc = interior(C.g, 3);
+  double* b = h->at<double>(p.off_b[k]);
+  Pair3Args a = pair3_args(h, k, h->ro.pre);
+  a.xc = R.x[k - 1];
+  a.b = b;
+  a.out = R.t[k];
+  FMG_LAUNCH(h, st, KC_PRE3P64, k, N, 8.0 * (2 * N + Nc), (launch_pair3_kernel<double, kP3ProlongFresh>(a, st)));
+  std::swap(R.x[k], R.t[k]);
+  FMG_LAUNCH(h, st, KC_RESTRICT64, k, N, 8.0 * (2 * N + Nc),
+             (launch_resid_restrict<3, double>(L.g, C.g, R.x[k], b, h->at<double>(p.off_b[k - 1]), L.scale, st)));
+  vcycle<3, double>(h, R, k - 1, true, st);
+  launch_post3<double>(h, k, R.x[k], R.x[k - 1], b, R.t[k], st);
+  std::swap(R.x[k], R.t[k]);
+}
+
+// fused_transition: the level transition into k wrote only b_k; the first
+// cycle starts from P u_{k-1} (vcycle_from_prolongation3).
 template <int DIM, int KIND>
-void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bool rhs_ready,
-                     bool defer_update, bool fold_next) {
+void correction_step_with(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bool rhs_ready,
+                          bool defer_update, bool fold_next, bool fused_transition) {
   const Plan& p = h->plan;
   const LevelInfo& L = p.lev[k];
   const fmg_options& o = h->ro.o;
@@ -897,6 +923,12 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
                (launch_rhs<DIM, KIND>(grid, st, L.g, h->slot(), nf1, fs, R.x[k], b, L.m)));
   for (int c = 0; c < o.m_vcycles; ++c) {
     if (o.precision == FMG_FP64) {
+      if constexpr (DIM == 3) {
+        if (c == 0 && fused_transition) {
+          vcycle_from_prolongation3(h, R, k, st);
+          continue;
+        }
+      }
       vcycle<DIM, double>(h, R, k, false, st);
     } else if (!mixed_cycle_fused<DIM>(h, R, k, st, c == 0, c == o.m_vcycles - 1)) {
       // float32 cycles on the correction equation: float64 residual before the
@@ -968,6 +1000,12 @@ void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bo
 }
 
 template <int DIM, int KIND>
+void correction_step(const fmg_hierarchy* h, Roles& R, int k, hipStream_t st, bool rhs_ready,
+                     bool defer_update, bool fold_next) {
+  correction_step_with<DIM, KIND>(h, R, k, st, rhs_ready, defer_update, fold_next, false);
+}
+
+template <int DIM, int KIND>
 void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
   const Plan& p = h->plan;
   const fmg_options& o = h->ro.o;
@@ -1022,7 +1060,22 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
     const LevelInfo& L = p.lev[k];
     const LevelInfo& C = p.lev[k - 1];
     const long long N = interior(L.g, DIM);
-    if (!folded && p.var)
+    // 3D float64 sweep-pair levels: the previous level's result is brought up
+    // to date here (u = Q w + alpha u~; P u equals the deferred form
+    // Q w + alpha P u~), the transition writes only b_k = M_k (g - f(P u)),
+    // and the first pre-smoothing pair forms x0 = P u itself
+    const bool fuse_tr = DIM == 3 && !folded && !p.var && o.precision == FMG_FP64 &&
+                         o.quadrature == FMG_QUAD_VERTEX && o.m_vcycles >= 1 && o.p_steps >= 1 && use_pair3(h, k);
+    if (fuse_tr) {
+      if constexpr (DIM == 3) {
+        if (pending_aug)
+          FMG_LAUNCH(h, st, KC_AUG_UPDATE, k - 1, interior(C.g, DIM), 16.0 * interior(C.g, DIM),
+                     k_aug_update<DIM><<<grid_of(C.g, DIM), kBlock, 0, st>>>(C.g, C.aug, h->ns(), R.x[k - 1]));
+        FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (2 * N + interior(C.g, DIM)),
+                   (launch_transition_rhs<DIM, KIND>(grid_of(L.g, DIM), st, transition_args(h, R, k, false),
+                                                     h->slot())));
+      }
+    } else if (!folded && p.var)
       FMG_LAUNCH(h, st, KC_TRANSITION, k, N, 8.0 * (3 * N + interior(C.g, DIM)),
                  (pending_aug ? launch_transition<DIM, KIND, true, true>(grid_of(L.g, DIM), st,
                                                                          transition_args(h, R, k, true), h->ns(),
@@ -1044,7 +1097,7 @@ void record_fmg(const fmg_hierarchy* h, Roles& R, bool finish, hipStream_t st) {
       // the last small-level augmented solve also performs a small next transition
       const bool fold = o.quadrature == FMG_QUAD_VERTEX && defer && k < p.nlev && N <= o.aug_small_nodes &&
                         interior(p.lev[k + 1].g, DIM) <= kFoldTransitionNodes;
-      correction_step<DIM, KIND>(h, R, k, st, l == 0, defer, fold);
+      correction_step_with<DIM, KIND>(h, R, k, st, l == 0, defer, fold, fuse_tr && l == 0);
       pending_aug = defer;
       folded = fold;
     }

@@ -1257,7 +1257,9 @@ struct TransitionArgs {
 // AUG: a.use_aug, as a template argument so that the node's code has no
 // branch and every load is issued before the first use.  CW: the weight c(x)
 // of f(x, u) = c(x) f(u) (slot->c, nullptr means c = 1), as for k_rhs.
-template <int DIM, int KIND, bool AUG, bool CW = false>
+// STORE_U = false: only b is written (the first sweep pair of the level forms
+// u_k^(0) itself).
+template <int DIM, int KIND, bool AUG, bool CW = false, bool STORE_U = true>
 __device__ __forceinline__ void transition_node(const TransitionArgs& a, const double* __restrict__ y,
                                                 const ProblemSlot* __restrict__ slot, int i, int j, int l) {
   const int si = i & 1, sj = j & 1, sl = DIM == 3 ? (l & 1) : 0;
@@ -1273,7 +1275,7 @@ __device__ __forceinline__ void transition_node(const TransitionArgs& a, const d
   double v = 0.5 * (v0 + v1);
   if constexpr (AUG) v = aug_apply<DIM>(t, v);
   const int q = gidx<DIM>(a.gf, i, j, l);
-  a.uf[q] = v;
+  if (STORE_U) a.uf[q] = v;
   if constexpr (CW) {
     const double* __restrict__ cw = slot->c;
     a.bf[q] = a.m * (gv - (cw ? cw[fi] : 1.0) * NL<KIND>::f(v, slot->param));
@@ -1288,6 +1290,15 @@ __global__ void __launch_bounds__(kBlock) k_transition(TransitionArgs a, const N
   int i, j, l;
   if (!node_of_thread<DIM>(a.gf, i, j, l)) return;
   transition_node<DIM, KIND, AUG, CW>(a, ns->y, slot, i, j, l);
+}
+
+// The transition's right-hand side b = M (g - f(P u_{k-1})) alone (3D float64
+// sweep-pair levels, where the first pre-smoothing pair starts from P u_{k-1}).
+template <int DIM, int KIND>
+__global__ void __launch_bounds__(kBlock) k_transition_rhs(TransitionArgs a, const ProblemSlot* __restrict__ slot) {
+  int i, j, l;
+  if (!node_of_thread<DIM>(a.gf, i, j, l)) return;
+  transition_node<DIM, KIND, false, false, false>(a, nullptr, slot, i, j, l);
 }
 
 // The same transition by the threads of one block (small fine levels, at the

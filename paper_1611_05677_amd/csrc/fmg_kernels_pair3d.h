@@ -29,6 +29,11 @@
 //     in-bounds) addresses; values outside the grid are masked to 0.
 // Arithmetic per node is the separate kernels' expression, in the same order:
 //   x' = x + wd (b - s (6 x - ((x_w + x_e) + (x_s + x_n) + (x_d + x_u)))).
+//
+// The first pre-smoothing of a level in the float64 FMG starts from the
+// natural inclusion x0 = P u_{k-1} of the previous level's result
+// (kP3ProlongFresh): x0 is formed from the coarse values as the planes
+// arrive, so the level transition only writes the right-hand side.
 #pragma once
 
 #include "fmg_device.h"
@@ -51,7 +56,8 @@ enum Pair3Mode {
   kP3Prolong = 2,    // x0 = x + P xc
   kP3Resid = 3,      // float32 cycle at the top level: r = (float)(b64 - A u64) is the right-hand side
                      // (stored to r32), x0 = 0
-  kP3ProlongAdd = 4  // float32 cycle at the top level: x0 = x + P xc, then u64 += (double) x2
+  kP3ProlongAdd = 4, // float32 cycle at the top level: x0 = x + P xc, then u64 += (double) x2
+  kP3ProlongFresh = 5  // x0 = P xc (x is not read): the level transition's start
 };
 
 // Launch geometry: strips of owned columns x row chunks x plane chunks; planes
@@ -97,7 +103,8 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(kP3Threads) k_sweep_pair3(Pair3Args A) {
   using TX = typename Pair3In<T, MODE>::type;
   constexpr int RW = kP3RowsPerWave;
-  constexpr bool PROLONG = MODE == kP3Prolong || MODE == kP3ProlongAdd;
+  constexpr bool FRESH = MODE == kP3ProlongFresh;
+  constexpr bool PROLONG = MODE == kP3Prolong || MODE == kP3ProlongAdd || FRESH;
   __shared__ TX lx[2][kP3Rows][64];   // x0 (or u) plane: the first stage's y-neighbours, by plane parity
   __shared__ T ls[2][kP3Rows][64];    // sweep-1 plane: sweep 2's y-neighbours
   const Grid g = A.g, cg = A.cg;
@@ -156,7 +163,7 @@ __global__ void __launch_bounds__(kP3Threads) k_sweep_pair3(Pair3Args A) {
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
       const size_t o = (size_t)z * g.pz + off[k];
-      if (MODE != kP3Zero) qx[d][k] = x[o];
+      if (MODE != kP3Zero && !FRESH) qx[d][k] = x[o];
       qb[d][k] = b[o];
       if (PROLONG) {   // integer arithmetic, not a select between c0 and c1
         const int odd = zl & 1;
@@ -202,7 +209,7 @@ __global__ void __launch_bounds__(kP3Threads) k_sweep_pair3(Pair3Args A) {
 #pragma unroll
       for (int k = 0; k < RW; ++k) {
         const bool ok = row_ok[k] && z_ok;
-        xn[k] = (MODE != kP3Zero && ok) ? qx[d][k] : TX(0);
+        xn[k] = (MODE != kP3Zero && !FRESH && ok) ? qx[d][k] : TX(0);
         bn[k] = ok ? qb[d][k] : TX(0);
         un[k] = (MODE == kP3ProlongAdd && ok) ? qu[d][k] : 0.0;
         if (PROLONG) {
@@ -213,7 +220,7 @@ __global__ void __launch_bounds__(kP3Threads) k_sweep_pair3(Pair3Args A) {
           if (ok && in_xy[k] && z_in) {
             T v = v0;
             if (cs[k] | (zl & 1)) v = T(0.5) * (v + v1);
-            xn[k] = xn[k] + v;
+            xn[k] = FRESH ? v : xn[k] + v;
           }
         }
       }

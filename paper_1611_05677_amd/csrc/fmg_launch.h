@@ -47,4 +47,8 @@ template <int DIM, int KIND, bool AUG, bool CW = false>
 void launch_transition(dim3 grid, hipStream_t st, TransitionArgs a, const NewtonState* ns,
                        const ProblemSlot* slot);
 
+// The transition's right-hand side alone (3D).
+template <int DIM, int KIND>
+void launch_transition_rhs(dim3 grid, hipStream_t st, TransitionArgs a, const ProblemSlot* slot);
+
 }  // namespace fmg

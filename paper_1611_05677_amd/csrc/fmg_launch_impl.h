@@ -67,11 +67,16 @@ void launch_transition(dim3 grid, hipStream_t st, TransitionArgs a, const Newton
                        const ProblemSlot* slot) {
   k_transition<DIM, KIND, AUG, CW><<<grid, kBlock, 0, st>>>(a, ns, slot);
 }
+template <int DIM, int KIND>
+void launch_transition_rhs(dim3 grid, hipStream_t st, TransitionArgs a, const ProblemSlot* slot) {
+  k_transition_rhs<DIM, KIND><<<grid, kBlock, 0, st>>>(a, slot);
+}
 
 }  // namespace fmg
 
 // Every launcher for dimension D and nonlinearity K (the 2D recorder never
-// launches the separate Newton finisher, so it is only instantiated in 3D).
+// launches the separate Newton finisher or the separate transition right-hand
+// side, so those are only instantiated in 3D, by FMG_INSTANTIATE_FINISH).
 #define FMG_INSTANTIATE_KIND(D, K)                                                                   \
   namespace fmg {                                                                                    \
   template void launch_rhs<D, K>(dim3, hipStream_t, Grid, const ProblemSlot*, int, int, const double*, \
@@ -111,6 +116,7 @@ void launch_transition(dim3 grid, hipStream_t st, TransitionArgs a, const Newton
   template void launch_newton_finish<D, K>(size_t, hipStream_t, Grid, AugShape, const double*,         \
                                            const ProblemSlot*, const double*, double, NewtonState*,   \
                                            fmg_report*, int, double);                                 \
+  template void launch_transition_rhs<D, K>(dim3, hipStream_t, TransitionArgs, const ProblemSlot*);   \
   }
 
 // The element-rule kernels for dimension D and nonlinearity K: right-hand
