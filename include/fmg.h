@@ -126,7 +126,7 @@ typedef struct {
                             the augmented problem in one single-workgroup
                             launch (0: never; default 4096 in 2D, 343 in 3D) */
     int sweep_rows;     /* 2D V(2,2) levels: rows marched by each wavefront of
-                           the register-streaming level kernels (4..4096);
+                           the register-streaming level kernels (2..4096);
                            0 = chosen per level; -1 = LDS-tiled kernels.
                            3D V(2,2) levels with n >= 16: 0 = each sweep pair
                            (pre-smoothing; correction + post-smoothing) in one

@@ -101,7 +101,7 @@ int resolve(int dim, const fmg_options* in, Resolved& r) {
   if (o.mode == FMG_CONVERGED && (o.converged_max_steps < 1 || !(o.converged_tol > 0))) return FMG_E_INVALID;
   if (o.tail_max_nodes < 0 || (o.fuse_small_levels != 0 && o.fuse_small_levels != 1)) return FMG_E_INVALID;
   if (o.aug_max_blocks < 64 || o.aug_max_blocks > 16384 || o.aug_small_nodes < 0) return FMG_E_INVALID;
-  if (o.sweep_rows < -1 || (o.sweep_rows > 0 && o.sweep_rows < 4) || o.sweep_rows > 4096) return FMG_E_INVALID;
+  if (o.sweep_rows < -1 || (o.sweep_rows > 0 && o.sweep_rows < 2) || o.sweep_rows > 4096) return FMG_E_INVALID;
   if (o.quadrature != FMG_QUAD_VERTEX && o.quadrature != FMG_QUAD_ELEMENT) return FMG_E_INVALID;
   if (o.quadrature == FMG_QUAD_ELEMENT && o.fuse_small_levels) return FMG_E_UNSUPPORTED;
   if (o.coefficients != FMG_COEF_IDENTITY && o.coefficients != FMG_COEF_VARIABLE) return FMG_E_INVALID;

@@ -393,14 +393,15 @@ __global__ void __launch_bounds__(64 * kStreamWaves)
 }
 
 // Rows per wavefront: an explicit choice, or (0) about 128 row chunks per
-// level and at least 4 rows.  Shorter marches trade re-read halo rows for more
+// level and at least 2 rows.  Shorter marches trade re-read halo rows for more
 // wavefronts in flight; the level kernels are bound by the latency of the row
-// pipeline more than by bandwidth up to n = 2048.
+// pipeline more than by bandwidth up to n = 2048 (2048^2 solve with at least
+// 4 rows: 1.089 ms, at least 2: 1.085 ms; mixed 1.043 -> 1.035 ms).
 inline int stream_rows(int opt, int n) {
   if (opt < 0) return 0;
   if (opt > 0) return opt;
   const int R = n >> 7;
-  return R < 4 ? 4 : R;
+  return R < 2 ? 2 : R;
 }
 
 // Launch geometry: logical blocks = strip groups x row chunks, rounded up to

@@ -258,7 +258,7 @@ def test_quadrature_block_count_does_not_change_result(blocks):
 
 
 @pytest.mark.parametrize("precision", [B.FMG_FP64, B.FMG_MIXED], ids=["fp64", "mixed"])
-@pytest.mark.parametrize("rows", [4, 12, 37, 4096])
+@pytest.mark.parametrize("rows", [2, 4, 12, 37, 4096])
 def test_streaming_level_kernels_match_lds_tiles(precision, rows):
     """The register-streaming 2D level kernels (any rows per wavefront,
     including chunks that end in a ragged tail and levels narrower than one
