@@ -60,10 +60,16 @@ enum Pair3Mode {
   kP3ProlongFresh = 5  // x0 = P xc (x is not read): the level transition's start
 };
 
-// Launch geometry: strips of owned columns x row chunks x plane chunks; planes
-// per chunk chosen for about `target` workgroups, within the bounds below.  Logical block order: strip
-// fastest, then row chunk, then plane chunk, so each XCD's contiguous range of
-// logical blocks holds tiles that share halo rows and columns.
+// Launch geometry: strips of owned columns x row chunks x plane chunks.  Two
+// workgroups are resident per CU (512 on the device), and a launch whose
+// workgroups overrun a whole number of such waves leaves CUs idle at its end,
+// so the plane chunks are as many as keep the workgroups within one wave on
+// levels with n <= 128 and within `target` (two waves) above (128^3: 495
+// workgroups instead of 528, pairs 19.7 -> 15.8 and 23.8 -> 19.6 us; 256^3:
+// 990 instead of 1100, 105 -> 101 and 121 -> 114 us; solve 2.461 -> 2.409 ms),
+// within the bounds below.  Logical block order: strip fastest, then row
+// chunk, then plane chunk, so each XCD's contiguous range of logical blocks
+// holds tiles that share halo rows and columns.
 struct Pair3Shape {
   int nsx, ncy, nzc, zc_planes;
 };
@@ -72,7 +78,7 @@ inline Pair3Shape pair3_shape(int n, int target = 1024) {
   Pair3Shape s;
   s.nsx = (n - 1 + kP3OwnX - 1) / kP3OwnX;
   s.ncy = (n - 1 + kP3OwnY - 1) / kP3OwnY;
-  int nzc = (target + s.nsx * s.ncy - 1) / (s.nsx * s.ncy);
+  int nzc = (n <= 128 ? 512 : target) / (s.nsx * s.ncy);
   // owned planes per chunk at least: 8 on large levels (a chunk loads four
   // halo planes); on small levels, whose launches are bound by the march's
   // chain of plane steps rather than by bytes, shorter chunks (n <= 32: 1,
