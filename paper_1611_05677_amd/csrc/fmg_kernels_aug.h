@@ -128,6 +128,75 @@ __device__ __forceinline__ long long fine_load_index(int nf1, int s, int i, int 
   return ((long long)l * s * nf1 + (long long)j * s) * nf1 + (long long)i * s;
 }
 
+// The values the setup pass needs at one fine node: u~ at the node (c) and at
+// its 2d axis neighbours (west, east, south, north, down, up), and the load g.
+struct StencilVals {
+  double c, w, e, s, n, d, u, g;
+};
+
+// (A u~) at the node from its stencil values: apply_A_at's expression, in the
+// same order.
+template <int DIM>
+__device__ __forceinline__ double apply_A_vals(const StencilVals& v, double scale) {
+  double s = (v.w + v.e) + (v.s + v.n);
+  if (DIM == 3) s += v.d + v.u;
+  return scale * (double(2 * DIM) * v.c - s);
+}
+
+// for_cell_nodes for the setup pass: the node's stencil values and its load
+// are loaded kSetupPrefetch visits ahead (from clamped, in-bounds addresses;
+// the values of the skipped Dirichlet nodes are never used), not at their
+// use, where each node waited for a round trip of its own.
+constexpr int kSetupPrefetch = 2;
+
+template <int DIM, typename Fn>
+__device__ __forceinline__ void for_cell_nodes_stencil(const Grid& g, const AugShape& s, int cx, int cy, int cz,
+                                                       int t0, int t1, int tid, int nthreads,
+                                                       const double* __restrict__ u,
+                                                       const double* __restrict__ gl, int nf1, int fs, Fn&& fn) {
+  const int r = 1 << s.log2r, mask = r - 1;
+  const double inv_r = 1.0 / r;
+  auto index_of = [&](int t, int& i, int& j, int& l) {
+    const int lx = t & mask, ly = (t >> s.log2r) & mask, lz = DIM == 3 ? t >> (2 * s.log2r) : 0;
+    i = cx * r + lx; j = cy * r + ly; l = cz * r + lz;
+    return gidx<DIM>(g, i, j, l);
+  };
+  auto load = [&](int t) {
+    int i, j, l;
+    const int c = index_of(t < t1 ? t : t1 - 1, i, j, l);
+    StencilVals v;
+    v.c = u[c];
+    v.w = u[max(c - 1, 0)];
+    v.e = u[c + 1];
+    v.s = u[max(c - g.px, 0)];
+    v.n = u[c + g.px];
+    v.d = DIM == 3 ? u[max(c - g.pz, 0)] : 0.0;
+    v.u = DIM == 3 ? u[c + g.pz] : 0.0;
+    v.g = gl[fine_load_index(nf1, fs, i, j, l)];
+    return v;
+  };
+  StencilVals q[kSetupPrefetch];
+#pragma unroll
+  for (int p = 0; p < kSetupPrefetch; ++p) q[p] = load(t0 + tid + p * nthreads);
+  for (int tb = t0 + tid; tb < t1; tb += kSetupPrefetch * nthreads) {
+#pragma unroll
+    for (int p = 0; p < kSetupPrefetch; ++p) {
+      const int t = tb + p * nthreads;
+      const StencilVals v = q[p];
+      q[p] = load(t + kSetupPrefetch * nthreads);
+      if (t < t1) {
+        int i, j, l;
+        const int c = index_of(t, i, j, l);
+        if (i != 0 && j != 0 && (DIM == 2 || l != 0)) {   // skip the Dirichlet nodes
+          const int lx = i - cx * r, ly = j - cy * r, lz = DIM == 3 ? l - cz * r : 0;
+          double tl[3] = {lx * inv_r, ly * inv_r, lz * inv_r};
+          fn(c, tl, i, j, l, v);
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Linearised right-hand side: b_j = m (g_j - f(u_j)) at level-k interior nodes.
 // ---------------------------------------------------------------------------
@@ -237,12 +306,12 @@ __device__ __forceinline__ void setup_quad_accumulate(const Grid& g, const AugSh
                                                       int nthreads, double* acc_s, double* acc_q) {
   int cx, cy, cz;
   cell_of<DIM>(cell, s.nH, cx, cy, cz);
-  for_cell_nodes<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, ut,
-                      [&](int c, const double* tl, int i, int j, int l, double u) {
+  for_cell_nodes_stencil<DIM>(g, s, cx, cy, cz, t0, t1, tid, nthreads, ut, gl, nf1, fs,
+                              [&](int, const double* tl, int, int, int, const StencilVals& v) {
     double phi[Acc<DIM>::NV];
     kuhn_phi<DIM>(tl, phi);
-    setup_node<DIM>(phi, u, apply_A_at<DIM>(ut, c, g, scale), gl[fine_load_index(nf1, fs, i, j, l)], acc_s);
-    quad_node<DIM, KIND>(phi, u, u, param, acc_q);
+    setup_node<DIM>(phi, v.c, apply_A_vals<DIM>(v, scale), v.g, acc_s);
+    quad_node<DIM, KIND>(phi, v.c, v.c, param, acc_q);
   });
 }
 
