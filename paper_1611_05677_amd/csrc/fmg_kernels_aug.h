@@ -972,6 +972,10 @@ __host__ __device__ constexpr int aug_threads() { return DIM == 2 ? kAugMaxThrea
 template <int DIM>
 __host__ __device__ constexpr int aug_wide_nodes_log() { return DIM == 2 ? 12 : 15; }
 
+// The 2D passes that also finish the Newton solve (FINISH) run 512 threads
+// over the node range of a 1024-thread block: with the completion code in the
+// same kernel, the 1024-thread bound (128 registers) spilled 116-300 bytes per
+// lane; at 512 none (2048^2 solve 1.083 -> 1.077 ms).
 // LDS doubles of k_newton_step / k_newton_finish for a block of `threads`.
 __host__ __device__ constexpr int newton_kernel_lds_doubles(int ncell, int NQ, int N1, int threads) {
   return ncell * NQ + newton_scratch_doubles(N1) + threads;
@@ -1001,7 +1005,7 @@ __device__ __forceinline__ void quad_cells_by_waves(const Grid& g, const AugShap
 // completion is left to k_newton_finish as well.
 // LDS: newton_kernel_lds_doubles(ncell, NQ, N1, blockDim).
 template <int DIM, int KIND, bool SETUP, bool FINISH, bool ELEM = false, bool VAR = false>
-__global__ void __launch_bounds__(ELEM || VAR ? kBlock : aug_threads<DIM>()) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
+__global__ void __launch_bounds__((ELEM || VAR ? kBlock : DIM == 2 && FINISH ? 512 : aug_threads<DIM>())) k_aug_pass(Grid g, AugShape s, const double* __restrict__ ut,
                                                      const ProblemSlot* __restrict__ slot, int nf1, int fs,
                                                      double scale, double m, const double* __restrict__ A1,
                                                      NewtonState* __restrict__ ns, fmg_report* __restrict__ rep,

@@ -37,6 +37,7 @@ void launch_aug_pass(int blocks, int threads, size_t lds, hipStream_t st, Grid g
                      const ProblemSlot* slot, int nf1, int fs, double scale, double m, const double* A1,
                      NewtonState* ns, fmg_report* rep, double* pq, double* ps, unsigned* tickets, int level,
                      int newton_max, double tol) {
+  if (DIM == 2 && FINISH && threads > 512) threads = 512;
   k_aug_pass<DIM, KIND, SETUP, FINISH, ELEM, VAR><<<blocks, threads, lds, st>>>(g, s, ut, slot, nf1, fs, scale, m, A1, ns,
                                                                            rep, pq, ps, tickets, level, newton_max,
                                                                            tol);
