@@ -976,6 +976,7 @@ __host__ __device__ constexpr int aug_wide_nodes_log() { return DIM == 2 ? 12 : 
 // over the node range of a 1024-thread block: with the completion code in the
 // same kernel, the 1024-thread bound (128 registers) spilled 116-300 bytes per
 // lane; at 512 none (2048^2 solve 1.083 -> 1.077 ms).
+
 // LDS doubles of k_newton_step / k_newton_finish for a block of `threads`.
 __host__ __device__ constexpr int newton_kernel_lds_doubles(int ncell, int NQ, int N1, int threads) {
   return ncell * NQ + newton_scratch_doubles(N1) + threads;
