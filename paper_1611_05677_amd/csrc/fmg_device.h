@@ -63,12 +63,17 @@ template <> struct NL<FMG_F_ABS_U_U> {
     double a = fabs(u); f = a * u; df = 2.0 * a; F = a * a * a * (1.0 / 3.0);
   }
 };
+// sign(u)|u|^q; the exponent q = 3/2 of the paper's Example 3 takes |u|^{1/2}
+// from sqrt (correctly rounded) instead of pow's logarithm and exponential.
 template <> struct NL<FMG_F_SIGNED_POW> {
-  __device__ static double f(double u, double q) { return copysign(pow(fabs(u), q), u); }
+  __device__ static double f(double u, double q) {
+    const double a = fabs(u);
+    return copysign(q == 1.5 ? a * sqrt(a) : pow(a, q), u);
+  }
   __device__ static void all(double u, double q, double& f, double& df, double& F) {
     double a = fabs(u);
-    double p = pow(a, q - 1.0);          // |u|^{q-1}
-    double aq = p * a;                   // |u|^q
+    double p = q == 1.5 ? sqrt(a) : pow(a, q - 1.0);   // |u|^{q-1}
+    double aq = p * a;                                  // |u|^q
     f = copysign(aq, u); df = q * p; F = aq * a / (q + 1.0);
   }
 };

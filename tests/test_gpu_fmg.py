@@ -74,6 +74,8 @@ PAPER_CASES = [
     W.fourier_problem("f_sin", 2, 4, 5, W.F_U_PLUS_SIN, [1, 3]),
     W.fourier_problem("f_abs", 2, 4, 5, W.F_ABS_U_U, [1, 4]),
     W.fourier_problem("f_pow", 2, 4, 4, W.F_SIGNED_POW, [1, 5], f_param=1.5),
+    # an exponent other than the 3/2 that takes its square-root path
+    W.fourier_problem("f_pow25", 2, 4, 4, W.F_SIGNED_POW, [1, 7], f_param=2.5),
     W.constant_load("f_exp", 2, 4, 4, 1.0, W.F_NEG_EXP),
     W.cube_u_plus_sin(1), W.cube_u_plus_sin(3),
     W.cube_example1(2), W.cube_example3(2), W.cube_example2(2),
